@@ -1,0 +1,192 @@
+/*
+ * rcpsp.h -- C ABI of the MI355X (gfx950) tabu-search library for the
+ * Resource Constrained Project Scheduling Problem, after Bukata, Sucha and
+ * Hanzalek, "Solving the RCPSP using the parallel Tabu Search designed for the
+ * CUDA platform" (JPDC 77, 2015).
+ *
+ * Conventions
+ *  - All integers are int32 unless stated; arrays are row-major.
+ *  - Host arrays passed to the library are copied; the caller keeps ownership.
+ *  - Outputs go to caller-allocated buffers.
+ *  - Every entry point returns an rcpsp_status; nothing throws across the ABI.
+ *    rcpsp_last_error() returns a thread-local message for the last failure.
+ *  - hip_stream is a hipStream_t (NULL = the null stream).  Entry points that
+ *    say "asynchronous" only enqueue work on it.
+ *  - Instances are immutable after creation and may be shared between threads;
+ *    a search or batch object must not be used by two threads at once.
+ */
+#ifndef RCPSP_H
+#define RCPSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RCPSP_OK = 0,
+    RCPSP_E_ARG = -1,        /* null pointer, size or parameter out of range */
+    RCPSP_E_CYCLE = -2,      /* the precedence graph is not acyclic (Section 2) */
+    RCPSP_E_REQUEST = -3,    /* r_ik < 0 or r_ik > R_k, or R_k < 0 (Section 2) */
+    RCPSP_E_DUMMY = -4,      /* d_0 or d_{N-1} != 0, dummy requests, an activity
+                                without predecessor lacks the arc 0->i, or one
+                                without successor lacks i->N-1 (Section 2) */
+    RCPSP_E_ORDER = -5,      /* not a precedence-feasible permutation with
+                                w_0 = 0 and w_{N-1} = N-1 (Sections 2, 4.2) */
+    RCPSP_E_BUFFER = -6,     /* caller buffer too small */
+    RCPSP_E_NOMEM = -7,      /* host or device allocation failed */
+    RCPSP_E_DEVICE = -8,     /* a HIP call failed */
+    RCPSP_E_TOO_LARGE = -9   /* beyond the kernels' limits (N, M, horizon, LDS) */
+} rcpsp_status;
+
+/* Resource evaluation algorithm used by the schedule decoder (Section 5). */
+typedef enum {
+    RCPSP_EVAL_AUTO = 0,      /* chosen per instance before the search (Section 5.4) */
+    RCPSP_EVAL_TIME = 1,      /* time-indexed: Algs. 5 and 6 */
+    RCPSP_EVAL_CAPACITY = 2   /* capacity-indexed: eq. 7 and Alg. 4 */
+} rcpsp_eval;
+
+typedef struct rcpsp_instance rcpsp_instance;
+
+/*
+ * Create a project instance (problem statement, Section 2).
+ *   n          N, number of activities including the dummies 0 and N-1 (3..2048)
+ *   m          M, number of renewable resources (1..16)
+ *   duration   [N]    d_i >= 0, d_0 = d_{N-1} = 0; sum d_i <= 32767
+ *   capacity   [M]    R_k >= 0 (<= 32767)
+ *   request    [N*M]  r_{i,k} at i*M+k, 0 <= r_ik <= R_k
+ *   succ_off   [N+1]  successor lists in CSR form (Table 1 "Successors")
+ *   succ       [succ_off[N]] successor ids
+ *   eval       decoder; AUTO resolves it from the instance attributes of
+ *              Table tab:attr (see rcpsp_instance_info) and may later be
+ *              replaced by rcpsp_autotune
+ *   out        receives the instance (library-owned; free with
+ *              rcpsp_destroy_instance)
+ * The instance is validated (errors above), derived data is computed on the
+ * host (predecessor lists, critical path, horizon) and a packed copy is
+ * uploaded to the current device.  Synchronous.
+ */
+rcpsp_status rcpsp_create_instance(int32_t n, int32_t m, const int32_t *duration,
+                                   const int32_t *capacity, const int32_t *request,
+                                   const int32_t *succ_off, const int32_t *succ,
+                                   rcpsp_eval eval, rcpsp_instance **out);
+
+typedef struct {
+    int32_t n, m, n_arcs;
+    int32_t horizon;          /* UB = sum of d_i (Section 5.2.1) */
+    int32_t critical_path;    /* longest 0 -> N-1 path, arc (i,j) weighted d_i (Section 2) */
+    int32_t eval;             /* resolved decoder: 1 time-indexed, 2 capacity-indexed */
+    int32_t min_capacity, max_capacity;
+    int32_t sum_capacity;     /* sum of R_k (capacity-indexed state size) */
+    int32_t field_bits;       /* 8 or 16: per-resource field width of the packed time-indexed profile */
+    int32_t avg_capacity_x1000, avg_duration_x1000, branch_factor_x1000; /* Table tab:attr */
+} rcpsp_info;
+
+rcpsp_status rcpsp_instance_info(const rcpsp_instance *inst, rcpsp_info *out);
+void rcpsp_destroy_instance(rcpsp_instance *inst);
+
+/* Evaluation of one neighbourhood (Sections 4.2-4.5, 5).
+ * Moves are swap(u,v) with 1 <= u < v <= N-2 and v-u <= swap_range, in the
+ * canonical order u ascending then v ascending; P is their number.
+ * A move is feasible under eqs. 5 and 6; every feasible move is decoded with
+ * the serial schedule generation scheme (Alg. 7) and the instance's decoder.
+ * A move is admissible if it is not tabu or its makespan is below
+ * `aspiration`; `best` is the lexicographically smallest (C_max, u, v) among
+ * admissible moves, or among all feasible moves if none is admissible.   */
+typedef struct {
+    int32_t u, v, makespan;   /* (0, 0, -1) when no move is feasible */
+    int32_t n_feasible;       /* number of feasible moves; RCPSP_E_ORDER (<0) if
+                                 the device variant was given an invalid order */
+} rcpsp_move;
+
+/* Host variant, synchronous on hip_stream.
+ *   order      [N] host, a precedence-feasible activity list
+ *   swap_range delta >= 1
+ *   tabu       NULL or [N*N] host bytes, tabu[u*N+v] != 0 marks swap(u,v) tabu
+ *   aspiration INT32_MAX for none
+ *   makespan   [cap] host: C_max per potential move, -1 if infeasible;
+ *              RCPSP_E_BUFFER if cap < P (P is still written to *n_potential)
+ *   n_potential receives P (may be NULL)
+ *   best       host, may be NULL                                            */
+rcpsp_status rcpsp_evaluate_neighbourhood(const rcpsp_instance *inst, const int32_t *order,
+                                          int32_t swap_range, const uint8_t *tabu,
+                                          int32_t aspiration, int32_t *makespan, int32_t cap,
+                                          int32_t *n_potential, rcpsp_move *best,
+                                          void *hip_stream);
+
+/* Device variant, asynchronous: order [N] int32, tabu [N*N] uint8 or NULL,
+ * makespan [P] int32 and best (one rcpsp_move) are device pointers.  The
+ * kernel checks the order itself; an invalid order writes
+ * best->n_feasible = RCPSP_E_ORDER and leaves makespan untouched.          */
+rcpsp_status rcpsp_evaluate_neighbourhood_device(const rcpsp_instance *inst, const int32_t *order,
+                                                 int32_t swap_range, const uint8_t *tabu,
+                                                 int32_t aspiration, int32_t *makespan,
+                                                 rcpsp_move *best, void *hip_stream);
+
+/* Number of potential swap moves P for (N, swap_range). */
+int32_t rcpsp_potential_moves(int32_t n, int32_t swap_range);
+
+/* Tabu search parameters (Sections 3, 4, 6; Table tab:params). */
+typedef struct {
+    int32_t swap_range;       /* delta (1..64) */
+    int32_t tabu_len;         /* |tabuList| (>= 1) */
+    int32_t iterations;       /* I_block: iterations per search (>= 0) */
+    int32_t searches;         /* B: number of concurrent searches (>= 1) */
+    int32_t elite;            /* |F|: working-set size; 0 = independent searches */
+    int32_t phi_max;          /* diversify when a record was read more than phi_max times */
+    int32_t phi_steps;        /* random feasible swaps per diversification */
+    int32_t threads;          /* threads per search: 0 = auto, else 64, 128, 256 */
+    int32_t profile_len;      /* time-indexed LDS profile slots per lane, 0 = auto */
+    int32_t record_trajectory;/* 1 = keep (u, v, C_after, C_best) per iteration on the device */
+    uint64_t seed;            /* seeds the initial orders and diversification */
+} rcpsp_search_params;
+
+/* Results; every pointer may be NULL (not copied).  Sizes in parentheses. */
+typedef struct {
+    int32_t *best_makespan;   /* [B] best makespan reached by each search */
+    int32_t *best_order;      /* [B*N] the corresponding activity lists */
+    int32_t *iterations_done; /* [B] */
+    int64_t *evaluations;     /* [B] decoded feasible candidates */
+    int32_t *trajectory;      /* [B*iterations*4] (u, v, C_after, C_best); -1 when not done */
+    int32_t *elite_makespan;  /* [elite] final working set */
+    int32_t *elite_order;     /* [elite*N] */
+    int32_t global_best;      /* out: minimum over searches and working set */
+    int64_t total_evaluations;/* out */
+    int32_t overflow_decodes; /* out: candidates that needed the long-profile path */
+} rcpsp_search_result;
+
+typedef struct rcpsp_search rcpsp_search;
+
+/* Build a search plan: device state, initial orders (Section 4.1) and, for a
+ * working set, the captured graph of iteration and exchange kernels.
+ * Synchronous. */
+rcpsp_status rcpsp_search_create(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                 void *hip_stream, rcpsp_search **out);
+/* Run the whole search from its initial state on the device (homogeneous
+ * model: no host traffic).  Asynchronous; may be called repeatedly and
+ * gives the same results each time. */
+rcpsp_status rcpsp_search_run(rcpsp_search *s, void *hip_stream);
+/* Wait for hip_stream and copy the results to the host buffers. */
+rcpsp_status rcpsp_search_results(rcpsp_search *s, rcpsp_search_result *res, void *hip_stream);
+void rcpsp_search_destroy(rcpsp_search *s);
+
+/* create + run + results + destroy. */
+rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                               rcpsp_search_result *res, void *hip_stream);
+
+/* Kernel names and per-launch statistics of the last run of a search plan:
+ * launches of the iteration kernel and the number of candidate decodes. */
+typedef struct {
+    int32_t threads, profile_len, lds_bytes, eval;
+    int32_t iteration_launches, round_launches;
+} rcpsp_search_config;
+rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out);
+
+const char *rcpsp_last_error(void);
+const char *rcpsp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RCPSP_H */

@@ -1,0 +1,780 @@
+// Host runtime behind include/rcpsp.h: instance validation and packing,
+// search plans (device state + captured HIP graph), result read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rcpsp.h"
+#include "rcpsp_internal.h"
+#include "rcpsp_launch.h"
+
+using namespace rcpsp;
+
+namespace {
+
+thread_local std::string g_err;
+
+rcpsp_status fail(rcpsp_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(e_ == hipErrorOutOfMemory ? RCPSP_E_NOMEM : RCPSP_E_DEVICE, "%s: %s (%s:%d)", #expr, \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                            \
+    } while (0)
+
+int potential_moves(int n, int delta) {
+    const int Lp = n - 2;
+    if (Lp < 2 || delta < 1) return 0;
+    const int dd = std::min(delta, Lp - 1);
+    return dd * Lp - dd * (dd + 1) / 2;
+}
+
+int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Blob {
+    std::vector<uint32_t> w;
+    int add16(const std::vector<int> &v) {
+        const int off = (int)w.size();
+        w.resize(w.size() + (v.size() + 1) / 2, 0u);
+        for (size_t i = 0; i < v.size(); ++i)
+            w[off + i / 2] |= (uint32_t)(v[i] & 0xffff) << (16 * (i & 1));
+        return off;
+    }
+    int add32(const std::vector<uint32_t> &v) {
+        const int off = (int)w.size();
+        w.insert(w.end(), v.begin(), v.end());
+        return off;
+    }
+};
+
+}  // namespace
+
+struct rcpsp_instance {
+    int n = 0, m = 0, n_arcs = 0, H = 0, cp = 0, eval = 0, dmax = 0;
+    std::vector<int> d, R, r, succ_off, succ, pred_off, pred;
+    InstDesc desc{};
+    uint32_t *d_blob = nullptr;
+    int device = 0;
+    rcpsp_info info{};
+};
+
+struct rcpsp_search {
+    const rcpsp_instance *inst = nullptr;
+    rcpsp_search_params p{};
+    int T = 64, L = 0, nw = 1, dec = 1, tcw = 1, P = 0;
+    Layout Ly{};
+    size_t lds = 0;
+    SearchArgs a{};
+    std::vector<void *> allocs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int iteration_launches = 0, round_launches = 0;
+};
+
+// ---------------------------------------------------------------------------
+// instances
+
+extern "C" const char *rcpsp_last_error(void) { return g_err.c_str(); }
+extern "C" const char *rcpsp_version(void) { return "rcpsp-mi355x 0.1 (gfx950)"; }
+extern "C" int32_t rcpsp_potential_moves(int32_t n, int32_t swap_range) { return potential_moves(n, swap_range); }
+
+static rcpsp_status validate_and_derive(rcpsp_instance *I, int32_t n, int32_t m, const int32_t *duration,
+                                        const int32_t *capacity, const int32_t *request,
+                                        const int32_t *succ_off, const int32_t *succ) {
+    if (!duration || !capacity || !request || !succ_off) return fail(RCPSP_E_ARG, "null input array");
+    if (n < 3) return fail(RCPSP_E_ARG, "N must be at least 3 (two dummies and one activity), got %d", n);
+    if (n > kMaxN) return fail(RCPSP_E_TOO_LARGE, "N=%d exceeds %d", n, kMaxN);
+    if (m < 1 || m > kMaxM) return fail(m < 1 ? RCPSP_E_ARG : RCPSP_E_TOO_LARGE, "M=%d outside 1..%d", m, kMaxM);
+    I->n = n;
+    I->m = m;
+    I->d.assign(duration, duration + n);
+    I->R.assign(capacity, capacity + m);
+    I->r.assign(request, request + (size_t)n * m);
+    long long H = 0;
+    for (int i = 0; i < n; ++i) {
+        if (I->d[i] < 0) return fail(RCPSP_E_ARG, "negative duration d_%d", i);
+        H += I->d[i];
+        I->dmax = std::max(I->dmax, I->d[i]);
+    }
+    if (I->d[0] != 0 || I->d[n - 1] != 0) return fail(RCPSP_E_DUMMY, "dummy activities must have zero duration");
+    if (H > kMaxHorizon) return fail(RCPSP_E_TOO_LARGE, "sum of durations %lld exceeds %d", H, kMaxHorizon);
+    I->H = (int)H;
+    for (int k = 0; k < m; ++k) {
+        if (I->R[k] < 0) return fail(RCPSP_E_REQUEST, "negative capacity R_%d", k);
+        if (I->R[k] > kMaxHorizon) return fail(RCPSP_E_TOO_LARGE, "capacity R_%d=%d too large", k, I->R[k]);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < m; ++k) {
+            const int rik = I->r[(size_t)i * m + k];
+            if (rik < 0 || rik > I->R[k]) return fail(RCPSP_E_REQUEST, "request r_%d,%d=%d outside 0..R_%d=%d", i, k, rik, k, I->R[k]);
+            if ((i == 0 || i == n - 1) && rik != 0) return fail(RCPSP_E_DUMMY, "dummy activity %d has a request", i);
+        }
+    if (succ_off[0] != 0) return fail(RCPSP_E_ARG, "succ_off[0] must be 0");
+    for (int i = 0; i < n; ++i)
+        if (succ_off[i + 1] < succ_off[i]) return fail(RCPSP_E_ARG, "succ_off not non-decreasing at %d", i);
+    const int E = succ_off[n];
+    if (E > 0 && !succ) return fail(RCPSP_E_ARG, "null successor array");
+    if (E > 65535) return fail(RCPSP_E_TOO_LARGE, "%d arcs exceed 65535", E);
+    I->n_arcs = E;
+    I->succ_off.assign(succ_off, succ_off + n + 1);
+    I->succ.assign(succ, succ + E);
+    std::vector<char> seen((size_t)n * n, 0);
+    std::vector<int> indeg(n, 0), outdeg(n, 0);
+    for (int i = 0; i < n; ++i) {
+        for (int e = succ_off[i]; e < succ_off[i + 1]; ++e) {
+            const int j = succ[e];
+            if (j < 0 || j >= n) return fail(RCPSP_E_ARG, "successor id %d of %d out of range", j, i);
+            if (j == i) return fail(RCPSP_E_CYCLE, "self loop on %d", i);
+            if (seen[(size_t)i * n + j]) return fail(RCPSP_E_ARG, "duplicate arc %d->%d", i, j);
+            seen[(size_t)i * n + j] = 1;
+            indeg[j]++;
+            outdeg[i]++;
+        }
+    }
+    if (indeg[0] != 0) return fail(RCPSP_E_DUMMY, "activity 0 must have no predecessor");
+    if (outdeg[n - 1] != 0) return fail(RCPSP_E_DUMMY, "activity N-1 must have no successor");
+    for (int i = 1; i < n; ++i)
+        if (indeg[i] == 0) return fail(RCPSP_E_DUMMY, "activity %d has no predecessor (arc 0->%d missing)", i, i);
+    for (int i = 0; i < n - 1; ++i)
+        if (outdeg[i] == 0) return fail(RCPSP_E_DUMMY, "activity %d has no successor (arc %d->N-1 missing)", i, i);
+    // topological order (Kahn) -> acyclicity, critical path, levels
+    std::vector<int> topo, deg = indeg;
+    topo.reserve(n);
+    for (int i = 0; i < n; ++i)
+        if (deg[i] == 0) topo.push_back(i);
+    for (size_t h = 0; h < topo.size(); ++h) {
+        const int i = topo[h];
+        for (int e = succ_off[i]; e < succ_off[i + 1]; ++e)
+            if (--deg[succ[e]] == 0) topo.push_back(succ[e]);
+    }
+    if ((int)topo.size() != n) return fail(RCPSP_E_CYCLE, "precedence graph has a cycle");
+    // predecessors, ascending id
+    I->pred_off.assign(n + 1, 0);
+    for (int j = 0; j < n; ++j) I->pred_off[j + 1] = I->pred_off[j] + indeg[j];
+    I->pred.assign(E, 0);
+    {
+        std::vector<int> fill(I->pred_off.begin(), I->pred_off.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int e = succ_off[i]; e < succ_off[i + 1]; ++e) I->pred[fill[succ[e]]++] = i;
+    }
+    // critical path: longest path with arc (i,j) weighted d_i (Section 2)
+    std::vector<int> est(n, 0), level(n, 0);
+    for (int i : topo)
+        for (int e = succ_off[i]; e < succ_off[i + 1]; ++e) {
+            const int j = succ[e];
+            est[j] = std::max(est[j], est[i] + I->d[i]);
+            level[j] = std::max(level[j], level[i] + 1);
+        }
+    I->cp = est[n - 1];
+    // pack
+    InstDesc &D = I->desc;
+    D = InstDesc{};
+    D.n = n;
+    D.m = m;
+    D.n_arcs = E;
+    D.horizon = I->H;
+    D.cp = I->cp;
+    int rmax_cap = 0, rq_max = 1, sum_r = 0, min_cap = INT_MAX;
+    for (int k = 0; k < m; ++k) {
+        rmax_cap = std::max(rmax_cap, I->R[k]);
+        min_cap = std::min(min_cap, I->R[k]);
+        D.R[k] = I->R[k];
+        D.cbase[k] = sum_r;
+        sum_r += I->R[k];
+    }
+    for (int v : I->r) rq_max = std::max(rq_max, v);
+    D.sum_r = sum_r;
+    D.copy_p = std::max(2, next_pow2(rq_max));
+    D.fbits = rmax_cap <= 127 ? 8 : 16;
+    const int fpw = 32 / D.fbits;
+    int nw = (m + fpw - 1) / fpw;
+    if (nw == 3) nw = 4;
+    D.nw = nw <= kMaxNW ? nw : 0;   // 0: time-indexed decoding unsupported
+    const int nwp = std::max(D.nw, 1);
+    for (int w = 0; w < nwp && D.nw; ++w) {
+        uint32_t g = 0, f = 0;
+        for (int fi = 0; fi < fpw; ++fi) {
+            const int sh = fi * D.fbits;
+            g |= 1u << (sh + D.fbits - 1);
+            const int k = w * fpw + fi;
+            if (k < m) f |= (uint32_t)I->R[k] << sh;
+        }
+        D.guard[w] = g;
+        D.full[w] = f;
+    }
+    Blob bl;
+    std::vector<int> v16;
+    v16.assign(I->d.begin(), I->d.end());
+    D.off_dur = bl.add16(v16);
+    v16.assign(I->pred_off.begin(), I->pred_off.end());
+    D.off_predoff = bl.add16(v16);
+    v16.assign(I->pred.begin(), I->pred.end());
+    if (v16.empty()) v16.push_back(0);
+    D.off_pred = bl.add16(v16);
+    v16.assign(I->succ_off.begin(), I->succ_off.end());
+    D.off_succoff = bl.add16(v16);
+    v16.assign(I->succ.begin(), I->succ.end());
+    if (v16.empty()) v16.push_back(0);
+    D.off_succ = bl.add16(v16);
+    {
+        std::vector<uint32_t> rq((size_t)n * nwp, 0u);
+        if (D.nw)
+            for (int i = 0; i < n; ++i)
+                for (int k = 0; k < m; ++k)
+                    rq[(size_t)i * nwp + k / fpw] |= (uint32_t)I->r[(size_t)i * m + k] << ((k % fpw) * D.fbits);
+        D.off_rq = bl.add32(rq);
+    }
+    v16.assign(I->r.begin(), I->r.end());
+    D.off_reqk = bl.add16(v16);
+    // level order (Section 4.1): levels ascending, ids ascending inside a level
+    int lmax = 0;
+    for (int i = 0; i < n; ++i) lmax = std::max(lmax, level[i]);
+    std::vector<int> base, lvl_off;
+    for (int l = 0; l <= lmax; ++l) {
+        lvl_off.push_back((int)base.size());
+        for (int i = 0; i < n; ++i)
+            if (level[i] == l) base.push_back(i);
+    }
+    lvl_off.push_back((int)base.size());
+    D.n_levels = lmax + 1;
+    D.off_base = bl.add16(base);
+    D.off_lvl = bl.add16(lvl_off);
+    {
+        // per resource: (R_k, first entry of c_k) as dword pairs
+        std::vector<uint32_t> res(2 * (size_t)m);
+        for (int k = 0; k < m; ++k) {
+            res[2 * k] = (uint32_t)I->R[k];
+            res[2 * k + 1] = (uint32_t)D.cbase[k];
+        }
+        D.off_res = bl.add32(res);
+    }
+    D.blob_dwords = (int)bl.w.size();
+    HIP_TRY(hipGetDevice(&I->device));
+    HIP_TRY(hipMalloc(&I->d_blob, bl.w.size() * sizeof(uint32_t)));
+    HIP_TRY(hipMemcpy(I->d_blob, bl.w.data(), bl.w.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    D.blob = I->d_blob;
+    // attributes (Table tab:attr)
+    rcpsp_info &f = I->info;
+    f.n = n;
+    f.m = m;
+    f.n_arcs = E;
+    f.horizon = I->H;
+    f.critical_path = I->cp;
+    f.min_capacity = min_cap;
+    f.max_capacity = rmax_cap;
+    f.sum_capacity = sum_r;
+    f.field_bits = D.fbits;
+    f.avg_capacity_x1000 = (int)(1000ll * sum_r / m);
+    f.avg_duration_x1000 = (int)(1000ll * I->H / n);
+    f.branch_factor_x1000 = (int)(1000ll * E / n);
+    return RCPSP_OK;
+}
+
+// Default decoder when none is requested: the capacity-indexed arrays cost
+// about R_k/2 loop steps per request, the time-indexed profile about one
+// packed slot per time unit (Section 5.4: capacity-indexed pays off for long
+// schedules with small capacities).
+static int auto_eval(const rcpsp_instance *I) {
+    if (I->desc.nw == 0) return kEvalCapacity;
+    long long ci = 0;
+    for (int i = 0; i < I->n; ++i)
+        for (int k = 0; k < I->m; ++k)
+            if (I->r[(size_t)i * I->m + k] > 0) ci += I->R[k] / 2 + 1;
+    const long long ti = (long long)I->desc.nw * I->H;
+    return ti <= ci ? kEvalTime : kEvalCapacity;
+}
+
+extern "C" rcpsp_status rcpsp_create_instance(int32_t n, int32_t m, const int32_t *duration,
+                                              const int32_t *capacity, const int32_t *request,
+                                              const int32_t *succ_off, const int32_t *succ, rcpsp_eval eval,
+                                              rcpsp_instance **out) {
+    if (!out) return fail(RCPSP_E_ARG, "null output pointer");
+    *out = nullptr;
+    if (eval < RCPSP_EVAL_AUTO || eval > RCPSP_EVAL_CAPACITY) return fail(RCPSP_E_ARG, "unknown decoder %d", (int)eval);
+    rcpsp_instance *I = new (std::nothrow) rcpsp_instance();
+    if (!I) return fail(RCPSP_E_NOMEM, "out of host memory");
+    rcpsp_status st = validate_and_derive(I, n, m, duration, capacity, request, succ_off, succ);
+    if (st != RCPSP_OK) {
+        if (I->d_blob) (void)hipFree(I->d_blob);
+        delete I;
+        return st;
+    }
+    if (eval == RCPSP_EVAL_TIME && I->desc.nw == 0) {
+        (void)hipFree(I->d_blob);
+        delete I;
+        return fail(RCPSP_E_TOO_LARGE, "time-indexed profile needs more than %d dwords per time unit", kMaxNW);
+    }
+    I->eval = eval == RCPSP_EVAL_AUTO ? auto_eval(I) : (int)eval;
+    I->info.eval = I->eval;
+    *out = I;
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_instance_info(const rcpsp_instance *inst, rcpsp_info *out) {
+    if (!inst || !out) return fail(RCPSP_E_ARG, "null pointer");
+    *out = inst->info;
+    return RCPSP_OK;
+}
+
+extern "C" void rcpsp_destroy_instance(rcpsp_instance *inst) {
+    if (!inst) return;
+    if (inst->d_blob) (void)hipFree(inst->d_blob);
+    delete inst;
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout
+
+static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, int L, int dec) {
+    Layout Ly{};
+    const int N2h = n2(D.n) / 2;
+    int o = 0;
+    Ly.blob = o; o += D.blob_dwords;
+    Ly.W = o; o += N2h;
+    Ly.Wimp = o; o += N2h;
+    Ly.pos = o; o += N2h;
+    Ly.fs = o; o += N2h;
+    Ly.lp = o; o += N2h;
+    Ly.cnt = o; o += T / 64 + 2;
+    Ly.tc = o; o += D.n * tcw;
+    Ly.ring = o; o += tl;
+    Ly.moves = o; o += std::max(pmax, 1);
+    o = (o + 1) & ~1;
+    Ly.red = o; o += 2 * (T / 64);
+    Ly.scal = o; o += 4;
+    o = (o + 3) & ~3;
+    Ly.region = o;
+    const int F0 = (D.n + 1) / 2;
+    if (dec == kEvalTime) Ly.per_lane = F0 + L * D.nw;
+    else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
+    o += T * Ly.per_lane;
+    Ly.long_len = dec == kEvalTime ? (T * Ly.per_lane - F0) / D.nw : 0;
+    Ly.total = o;
+    return Ly;
+}
+
+// Choose the per-lane time-indexed profile length: twice the critical path
+// plus two longest durations (makespans of the neighbourhood rarely exceed
+// it; longer schedules take the exact long-profile path), at least long
+// enough that the whole region holds one profile of the full horizon, and
+// within the LDS budget.
+static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw, int tl, int pmax, int L_req,
+                                int *L_out, Layout *Ly_out) {
+    const InstDesc &D = I->desc;
+    const int budget = kMaxLds - 1024;  // static shared variables
+    if (dec == kEvalCapacity) {
+        Layout Ly = make_layout(D, T, tcw, tl, pmax, 0, dec);
+        if ((size_t)Ly.total * 4 > (size_t)budget)
+            return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d)", Ly.total * 4, budget, T);
+        *L_out = 0;
+        *Ly_out = Ly;
+        return RCPSP_OK;
+    }
+    int L = L_req > 0 ? L_req : std::min(I->H, ((2 * I->cp + 2 * I->dmax + 15) / 16) * 16);
+    L = std::max(1, std::min(L, std::max(I->H, 1)));
+    for (;;) {
+        Layout Ly = make_layout(D, T, tcw, tl, pmax, L, dec);
+        if (Ly.long_len < I->H) {
+            ++L;
+            continue;
+        }
+        if ((size_t)Ly.total * 4 <= (size_t)budget) {
+            *L_out = L;
+            *Ly_out = Ly;
+            return RCPSP_OK;
+        }
+        if (L_req > 0 || L <= 16)
+            return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
+        L = std::max(16, L * 3 / 4);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// neighbourhood evaluation
+
+static rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, int32_t delta, const uint8_t *tabu,
+                                int32_t asp, int32_t *makespan, rcpsp_move *best, hipStream_t st) {
+    if (delta < 1 || delta > kMaxDelta) return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", delta, kMaxDelta);
+    const int P = potential_moves(I->n, delta);
+    int T = 256;
+    int L = 0;
+    Layout Ly;
+    rcpsp_status s = plan_layout(I, I->eval, T, 0, 0, P, 0, &L, &Ly);
+    while (s == RCPSP_E_TOO_LARGE && T > 64) {
+        T /= 2;
+        s = plan_layout(I, I->eval, T, 0, 0, P, 0, &L, &Ly);
+    }
+    if (s != RCPSP_OK) return s;
+    EvalArgs A{};
+    A.D = I->desc;
+    A.Ly = Ly;
+    A.delta = delta;
+    A.L = L;
+    A.aspiration = asp;
+    A.P = P;
+    A.order = order;
+    A.tabu = tabu;
+    A.makespan = makespan;
+    A.best = reinterpret_cast<int32_t *>(best);
+    HIP_TRY(launch_eval(A, T, I->desc.nw, I->eval, (size_t)Ly.total * 4, st));
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_evaluate_neighbourhood_device(const rcpsp_instance *inst, const int32_t *order,
+                                                            int32_t swap_range, const uint8_t *tabu,
+                                                            int32_t aspiration, int32_t *makespan, rcpsp_move *best,
+                                                            void *hip_stream) {
+    if (!inst || !order || !best) return fail(RCPSP_E_ARG, "null pointer");
+    return eval_device(inst, order, swap_range, tabu, aspiration, makespan, best, (hipStream_t)hip_stream);
+}
+
+static bool feasible_order(const rcpsp_instance *I, const int32_t *order) {
+    const int n = I->n;
+    if (order[0] != 0 || order[n - 1] != n - 1) return false;
+    std::vector<int> pos(n, -1);
+    for (int p = 0; p < n; ++p) {
+        if (order[p] < 0 || order[p] >= n || pos[order[p]] >= 0) return false;
+        pos[order[p]] = p;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int e = I->succ_off[i]; e < I->succ_off[i + 1]; ++e)
+            if (pos[i] >= pos[I->succ[e]]) return false;
+    return true;
+}
+
+extern "C" rcpsp_status rcpsp_evaluate_neighbourhood(const rcpsp_instance *inst, const int32_t *order,
+                                                     int32_t swap_range, const uint8_t *tabu, int32_t aspiration,
+                                                     int32_t *makespan, int32_t cap, int32_t *n_potential,
+                                                     rcpsp_move *best, void *hip_stream) {
+    if (!inst || !order) return fail(RCPSP_E_ARG, "null pointer");
+    if (swap_range < 1 || swap_range > kMaxDelta)
+        return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", swap_range, kMaxDelta);
+    const int P = potential_moves(inst->n, swap_range);
+    if (n_potential) *n_potential = P;
+    if (makespan && cap < P) return fail(RCPSP_E_BUFFER, "makespan buffer holds %d entries, %d needed", cap, P);
+    if (!feasible_order(inst, order)) return fail(RCPSP_E_ORDER, "order is not a precedence-feasible permutation");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int n = inst->n;
+    int32_t *d_order = nullptr, *d_mk = nullptr;
+    rcpsp_move *d_best = nullptr;
+    uint8_t *d_tabu = nullptr;
+    rcpsp_status rs = RCPSP_OK;
+    auto cleanup = [&]() {
+        if (d_order) (void)hipFree(d_order);
+        if (d_mk) (void)hipFree(d_mk);
+        if (d_best) (void)hipFree(d_best);
+        if (d_tabu) (void)hipFree(d_tabu);
+    };
+    do {
+        hipError_t e;
+        if ((e = hipMalloc(&d_order, sizeof(int32_t) * n)) != hipSuccess) break;
+        if ((e = hipMalloc(&d_mk, sizeof(int32_t) * std::max(P, 1))) != hipSuccess) break;
+        if ((e = hipMalloc(&d_best, sizeof(rcpsp_move))) != hipSuccess) break;
+        if (tabu && (e = hipMalloc(&d_tabu, (size_t)n * n)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(d_order, order, sizeof(int32_t) * n, hipMemcpyHostToDevice, st)) != hipSuccess) break;
+        if (tabu && (e = hipMemcpyAsync(d_tabu, tabu, (size_t)n * n, hipMemcpyHostToDevice, st)) != hipSuccess) break;
+        rs = eval_device(inst, d_order, swap_range, d_tabu, aspiration, d_mk, d_best, st);
+        if (rs != RCPSP_OK) {
+            cleanup();
+            return rs;
+        }
+        rcpsp_move hb{};
+        if ((e = hipMemcpyAsync(&hb, d_best, sizeof(rcpsp_move), hipMemcpyDeviceToHost, st)) != hipSuccess) break;
+        if (makespan && (e = hipMemcpyAsync(makespan, d_mk, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st)) != hipSuccess)
+            break;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
+        if (best) *best = hb;
+        cleanup();
+        return RCPSP_OK;
+    } while (0);
+    hipError_t e = hipGetLastError();
+    cleanup();
+    return fail(RCPSP_E_DEVICE, "device error in neighbourhood evaluation: %s", hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// search plans
+
+// eq. 8 decay table: E[0] = 2^24, E[j] = floor(E[j-1] K / 2^32) with
+// K = round(2^32 exp(-1/256)), until it reaches 0.
+static std::vector<uint32_t> decay_table() {
+    const uint64_t K = 4278222805ull;
+    std::vector<uint32_t> t;
+    uint64_t e = 1ull << 24;
+    while (e > 0) {
+        t.push_back((uint32_t)e);
+        e = (e * K) >> 32;
+    }
+    return t;
+}
+
+template <typename P>
+static hipError_t dalloc(rcpsp_search *s, P **ptr, size_t bytes) {
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, std::max<size_t>(bytes, 4));
+    if (e == hipSuccess) {
+        s->allocs.push_back(v);
+        *ptr = static_cast<P *>(v);
+    }
+    return e;
+}
+
+extern "C" void rcpsp_search_destroy(rcpsp_search *s) {
+    if (!s) return;
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (void *v : s->allocs) (void)hipFree(v);
+    delete s;
+}
+
+static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
+    const rcpsp_instance *I = s->inst;
+    const rcpsp_search_params &p = s->p;
+    const int N = I->n, N2 = n2(N), B = p.searches, NF = p.elite;
+    s->dec = I->eval;
+    s->nw = I->desc.nw;
+    s->tcw = (p.swap_range + 31) / 32;
+    s->P = potential_moves(N, p.swap_range);
+    int T = p.threads;
+    if (T == 0) T = B >= 256 ? 64 : (B >= 64 ? 128 : 256);
+    if (T != 64 && T != 128 && T != 256) return fail(RCPSP_E_ARG, "threads must be 0, 64, 128 or 256");
+    rcpsp_status st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, &s->L, &s->Ly);
+    while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
+        T /= 2;
+        st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, &s->L, &s->Ly);
+    }
+    if (st != RCPSP_OK) return st;
+    s->T = T;
+    s->lds = (size_t)s->Ly.total * 4;
+    if (NF > 0 && round_lds_bytes(B, NF) > (size_t)kMaxLds)
+        return fail(RCPSP_E_TOO_LARGE, "%d searches with a working set exceed the exchange kernel's LDS", B);
+
+    SearchArgs &a = s->a;
+    a = SearchArgs{};
+    a.D = I->desc;
+    a.Ly = s->Ly;
+    a.delta = p.swap_range;
+    a.tl = p.tabu_len;
+    a.iters = p.iterations;
+    a.B = B;
+    a.NF = NF;
+    a.phi_max = p.phi_max;
+    a.phi_steps = p.phi_steps;
+    a.tcw = s->tcw;
+    a.L = s->L;
+    a.record = p.record_trajectory ? 1 : 0;
+    a.seed = p.seed;
+    const int tcn = N * s->tcw;
+    HIP_TRY(dalloc(s, &a.sc, sizeof(SearchScalars) * B));
+    HIP_TRY(dalloc(s, &a.Wcur, sizeof(uint16_t) * (size_t)B * N2));
+    HIP_TRY(dalloc(s, &a.Wimp, sizeof(uint16_t) * (size_t)B * N2));
+    HIP_TRY(dalloc(s, &a.Wbest, sizeof(uint16_t) * (size_t)B * N2));
+    HIP_TRY(dalloc(s, &a.ring, sizeof(uint32_t) * (size_t)B * p.tabu_len));
+    HIP_TRY(dalloc(s, &a.tc, sizeof(uint32_t) * (size_t)B * tcn));
+    if (NF > 0) {
+        HIP_TRY(dalloc(s, &a.Xw, sizeof(uint16_t) * 2 * (size_t)B * N2));
+        HIP_TRY(dalloc(s, &a.Xring, sizeof(uint32_t) * 2 * (size_t)B * p.tabu_len));
+        HIP_TRY(dalloc(s, &a.Xtc, sizeof(uint32_t) * 2 * (size_t)B * tcn));
+        HIP_TRY(dalloc(s, &a.Xwidx, sizeof(int) * 2 * (size_t)B));
+        HIP_TRY(dalloc(s, &a.Fw, sizeof(uint16_t) * 2 * (size_t)NF * N2));
+        HIP_TRY(dalloc(s, &a.Fring, sizeof(uint32_t) * 2 * (size_t)NF * p.tabu_len));
+        HIP_TRY(dalloc(s, &a.Ftc, sizeof(uint32_t) * 2 * (size_t)NF * tcn));
+        HIP_TRY(dalloc(s, &a.Fwidx, sizeof(int) * 2 * (size_t)NF));
+        HIP_TRY(dalloc(s, &a.Fmeta, sizeof(SlotMeta) * NF));
+    }
+    HIP_TRY(dalloc(s, &a.g, sizeof(Global)));
+    if (a.record) HIP_TRY(dalloc(s, &a.traj, sizeof(int) * 4 * (size_t)B * std::max(p.iterations, 1)));
+    {
+        std::vector<uint32_t> E = decay_table();
+        uint32_t *dE = nullptr;
+        HIP_TRY(dalloc(s, &dE, sizeof(uint32_t) * E.size()));
+        HIP_TRY(hipMemcpy(dE, E.data(), sizeof(uint32_t) * E.size(), hipMemcpyHostToDevice));
+        a.decay = dE;
+        a.decay_len = (int)E.size();
+    }
+    HIP_TRY(hipMemset(a.g, 0, sizeof(Global)));
+    if (NF > 0) {
+        // export and record buffers are always written before they are read;
+        // clear them once so that no uninitialised memory is ever copied
+        HIP_TRY(hipMemset(a.Xwidx, 0, sizeof(int) * 2 * (size_t)B));
+        HIP_TRY(hipMemset(a.Fwidx, 0, sizeof(int) * 2 * (size_t)NF));
+    }
+
+    HIP_TRY(prepare_search(T, s->nw, s->dec, s->lds, B, NF));
+    // capture the whole run as one graph
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    auto end_capture = [&](hipError_t err) -> rcpsp_status {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        return fail(RCPSP_E_DEVICE, "graph capture failed: %s", hipGetErrorString(err));
+    };
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return fail(RCPSP_E_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    s->iteration_launches = 0;
+    s->round_launches = 0;
+    if ((e = launch_reset(a, cs)) != hipSuccess) return end_capture(e);
+    if (NF > 0) {
+        if ((e = launch_decode_records(a, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
+        if ((e = launch_round(a, 0, 1, cs)) != hipSuccess) return end_capture(e);
+        s->round_launches++;
+        for (int it = 0; it < p.iterations; ++it) {
+            SearchArgs ai = a;
+            ai.it0 = it;
+            ai.n_it = 1;
+            if ((e = launch_search(ai, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
+            s->iteration_launches++;
+            if (it < p.iterations - 1) {
+                if ((e = launch_round(ai, it & 1, 0, cs)) != hipSuccess) return end_capture(e);
+                s->round_launches++;
+            }
+        }
+        if (p.iterations == 0) {
+            SearchArgs ai = a;
+            ai.it0 = 0;
+            ai.n_it = 0;
+            if ((e = launch_search(ai, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
+            s->iteration_launches++;
+        }
+    } else {
+        SearchArgs ai = a;
+        ai.it0 = 0;
+        ai.n_it = p.iterations;
+        if ((e = launch_search(ai, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
+        s->iteration_launches++;
+    }
+    e = hipStreamEndCapture(cs, &s->graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(RCPSP_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    HIP_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+    (void)user_stream;
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_search_create(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                            void *hip_stream, rcpsp_search **out) {
+    if (!inst || !params || !out) return fail(RCPSP_E_ARG, "null pointer");
+    *out = nullptr;
+    const rcpsp_search_params &p = *params;
+    if (p.swap_range < 1 || p.swap_range > kMaxDelta)
+        return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", p.swap_range, kMaxDelta);
+    if (p.tabu_len < 1) return fail(RCPSP_E_ARG, "tabu_len must be >= 1");
+    if (p.iterations < 0) return fail(RCPSP_E_ARG, "iterations must be >= 0");
+    if (p.searches < 1) return fail(RCPSP_E_ARG, "searches must be >= 1");
+    if (p.elite < 0) return fail(RCPSP_E_ARG, "elite must be >= 0");
+    if (p.phi_max < 0 || p.phi_steps < 0) return fail(RCPSP_E_ARG, "phi_max and phi_steps must be >= 0");
+    if ((long long)p.searches * std::max(p.iterations, 1) * 4 > (1ll << 40))
+        return fail(RCPSP_E_TOO_LARGE, "trajectory too large");
+    rcpsp_search *s = new (std::nothrow) rcpsp_search();
+    if (!s) return fail(RCPSP_E_NOMEM, "out of host memory");
+    s->inst = inst;
+    s->p = p;
+    rcpsp_status st = build_plan(s, (hipStream_t)hip_stream);
+    if (st != RCPSP_OK) {
+        rcpsp_search_destroy(s);
+        return st;
+    }
+    *out = s;
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_search_run(rcpsp_search *s, void *hip_stream) {
+    if (!s) return fail(RCPSP_E_ARG, "null search");
+    HIP_TRY(hipGraphLaunch(s->exec, (hipStream_t)hip_stream));
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out) {
+    if (!s || !out) return fail(RCPSP_E_ARG, "null pointer");
+    out->threads = s->T;
+    out->profile_len = s->L;
+    out->lds_bytes = (int)s->lds;
+    out->eval = s->dec;
+    out->iteration_launches = s->iteration_launches;
+    out->round_launches = s->round_launches;
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_search_results(rcpsp_search *s, rcpsp_search_result *res, void *hip_stream) {
+    if (!s || !res) return fail(RCPSP_E_ARG, "null pointer");
+    const SearchArgs &a = s->a;
+    const int N = s->inst->n, N2 = n2(N), B = a.B, NF = a.NF;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    std::vector<SearchScalars> sc(B);
+    HIP_TRY(hipMemcpy(sc.data(), a.sc, sizeof(SearchScalars) * B, hipMemcpyDeviceToHost));
+    int gbest = INT_MAX;
+    long long tot = 0, ovf = 0;
+    for (int b = 0; b < B; ++b) {
+        gbest = std::min(gbest, sc[b].C_best);
+        tot += sc[b].evals;
+        ovf += sc[b].overflow;
+        if (res->best_makespan) res->best_makespan[b] = sc[b].C_best;
+        if (res->iterations_done) res->iterations_done[b] = sc[b].it_done;
+        if (res->evaluations) res->evaluations[b] = sc[b].evals;
+    }
+    if (res->best_order) {
+        std::vector<uint16_t> w((size_t)B * N2);
+        HIP_TRY(hipMemcpy(w.data(), a.Wbest, sizeof(uint16_t) * w.size(), hipMemcpyDeviceToHost));
+        for (int b = 0; b < B; ++b)
+            for (int i = 0; i < N; ++i) res->best_order[(size_t)b * N + i] = w[(size_t)b * N2 + i];
+    }
+    if (res->trajectory) {
+        if (!a.record) return fail(RCPSP_E_ARG, "trajectory requested but the plan does not record it");
+        HIP_TRY(hipMemcpy(res->trajectory, a.traj, sizeof(int) * 4 * (size_t)B * a.iters, hipMemcpyDeviceToHost));
+    }
+    if (NF > 0) {
+        std::vector<SlotMeta> meta(NF);
+        HIP_TRY(hipMemcpy(meta.data(), a.Fmeta, sizeof(SlotMeta) * NF, hipMemcpyDeviceToHost));
+        std::vector<uint16_t> fw(2 * (size_t)NF * N2);
+        if (res->elite_order)
+            HIP_TRY(hipMemcpy(fw.data(), a.Fw, sizeof(uint16_t) * fw.size(), hipMemcpyDeviceToHost));
+        for (int k = 0; k < NF; ++k) {
+            gbest = std::min(gbest, meta[k].C);
+            if (res->elite_makespan) res->elite_makespan[k] = meta[k].C;
+            if (res->elite_order)
+                for (int i = 0; i < N; ++i)
+                    res->elite_order[(size_t)k * N + i] = fw[((size_t)meta[k].buf * NF + k) * N2 + i];
+        }
+    }
+    res->global_best = gbest;
+    res->total_evaluations = tot;
+    res->overflow_decodes = (int32_t)std::min<long long>(ovf, INT_MAX);
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                          rcpsp_search_result *res, void *hip_stream) {
+    rcpsp_search *s = nullptr;
+    rcpsp_status st = rcpsp_search_create(inst, params, hip_stream, &s);
+    if (st != RCPSP_OK) return st;
+    st = rcpsp_search_run(s, hip_stream);
+    if (st == RCPSP_OK) st = rcpsp_search_results(s, res, hip_stream);
+    rcpsp_search_destroy(s);
+    return st;
+}

@@ -1,0 +1,100 @@
+// Library-internal definitions shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcpsp {
+
+constexpr int kMaxM = 16;        // resources
+constexpr int kMaxN = 2048;      // activities incl. dummies (positions fit in 16 bits)
+constexpr int kMaxNW = 4;        // dwords per packed time slot of the time-indexed profile
+constexpr int kMaxDelta = 64;    // swap range
+constexpr int kMaxHorizon = 32767;  // times are stored in 16 bits
+constexpr int kMaxLds = 160 * 1024; // LDS per workgroup on gfx950
+
+constexpr int kEvalTime = 1;
+constexpr int kEvalCapacity = 2;
+
+// Packed instance, passed by value to every kernel.  The arrays live in one
+// device blob (dword sections) that kernels copy into LDS.
+struct InstDesc {
+    int n, m, n_arcs, horizon, cp;
+    int nw;          // dwords per time slot (time-indexed profile)
+    int fbits;       // 8 or 16 bits per resource field
+    int sum_r;       // sum of R_k: capacity-indexed state size (16-bit entries)
+    int copy_p;      // capacity-indexed copy ring length (power of two >= max request)
+    int n_levels;
+    uint32_t guard[kMaxNW];  // top bit of every field
+    uint32_t full[kMaxNW];   // R_k of every field
+    int R[kMaxM];
+    int cbase[kMaxM];        // first entry of c_k in the capacity-indexed state
+    // blob sections (dword offsets)
+    int off_dur, off_predoff, off_pred, off_succoff, off_succ, off_rq, off_reqk, off_base, off_lvl, off_res;
+    int blob_dwords;
+    const uint32_t *blob;
+};
+
+// Dword offsets of the workgroup's LDS areas.
+struct Layout {
+    int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, red, scal, region;
+    int per_lane;    // dwords of private decode state per lane
+    int long_len;    // time slots available to the single-lane long-profile decode
+    int total;       // dwords
+};
+
+// Per-search scalar state in device memory.
+struct SearchScalars {
+    int C_cur, C_best, C_imp, C_read;
+    int it_done, it_read, I_assigned, slot;
+    int fired, stopped, widx, flags;
+    int src_kind, src_idx, src_buf, src_C;
+    unsigned long long rng_ctr;
+    long long evals;
+    long long overflow;
+    long long pad;
+};
+
+enum : int {
+    kFlagInitDecode = 1,   // decode the initial order at the first launch
+    kFlagReadPending = 2,  // take the record chosen by the last exchange round
+    kFlagDiversify = 4     // and diversify it
+};
+enum : int { kSrcRecord = 0, kSrcExport = 1 };
+
+struct SlotMeta {
+    int C, IC, reads, buf;
+};
+
+struct Global {
+    int Cstar;
+    int gstop;
+    int pad[2];
+};
+
+constexpr uint64_t kStreamInit = 0ull;
+constexpr uint64_t kStreamDiversify = 1ull << 32;
+
+// Search plan arguments for the kernels.
+struct SearchArgs {
+    InstDesc D;
+    Layout Ly;
+    int delta, tl, iters, B, NF, phi_max, phi_steps, tcw, L, record;
+    int it0, n_it;
+    int decay_len;
+    unsigned long long seed;
+    SearchScalars *sc;
+    uint16_t *Wcur, *Wimp, *Wbest;       // [B][N2] (N2 = N rounded up to even)
+    uint32_t *ring;                      // [B][tl]
+    uint32_t *tc;                        // [B][N*tcw]
+    uint16_t *Xw; uint32_t *Xring; uint32_t *Xtc; int *Xwidx;   // exports [2][B]
+    uint16_t *Fw; uint32_t *Fring; uint32_t *Ftc; int *Fwidx;   // working set [2][NF]
+    SlotMeta *Fmeta;                     // [NF]
+    Global *g;
+    int *traj;                           // [B][iters][4]
+    const uint32_t *decay;               // eq. 8 table
+};
+
+__host__ __device__ inline int n2(int n) { return (n + 1) & ~1; }
+
+}  // namespace rcpsp

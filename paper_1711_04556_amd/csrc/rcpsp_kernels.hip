@@ -1,0 +1,961 @@
+// HIP kernels for gfx950: swap-neighbourhood evaluation with the serial
+// schedule generation scheme, and the tabu search built on it.
+//
+// Design (one workgroup per search, wave64):
+//  - the instance (durations, packed requests, precedence lists) is staged
+//    from one device blob into LDS once per launch;
+//  - feasible moves are found in O(1) each: with a feasible order, eq. 5
+//    holds for swap(u,v) iff v is before the first successor of w_u, and
+//    eq. 6 iff u is after the last predecessor of w_v (Section 4.3-4.4);
+//  - every lane decodes one candidate order with Alg. 7.  Its private state
+//    (finish times, resource profile or capacity arrays) sits in LDS with a
+//    lane-interleaved layout (dword i of lane l at i*T+l), so lanes never
+//    conflict on a bank;
+//  - the time-indexed profile packs all resources of one time unit into one
+//    or more dwords (8- or 16-bit fields with a guard bit), so the capacity
+//    test of Alg. 5 for all resources is one subtract and mask, and Alg. 6 is
+//    one subtract;
+//  - the best admissible move is a 64-bit key (non-admissible, C_max, u, v)
+//    reduced with cross-lane shuffles inside a wave and LDS across waves.
+#include <hip/hip_runtime.h>
+
+#include "rcpsp_internal.h"
+#include "rcpsp_launch.h"
+
+namespace rcpsp {
+
+// ---------------------------------------------------------------------------
+// LDS views
+
+struct Sh {
+    const uint16_t *dur, *predoff, *pred, *succoff, *succ, *reqk, *base, *lvl;
+    const uint32_t *rq, *res;
+    uint16_t *W, *Wimp, *pos, *fs, *lp;
+    int *cnt;
+    uint32_t *tc, *ring, *moves;
+    unsigned long long *red;
+    int *scal;
+    uint32_t *region;
+};
+
+__device__ inline Sh make_sh(uint32_t *lds, const InstDesc &D, const Layout &Ly) {
+    Sh s;
+    uint32_t *b = lds + Ly.blob;
+    s.dur = reinterpret_cast<const uint16_t *>(b + D.off_dur);
+    s.predoff = reinterpret_cast<const uint16_t *>(b + D.off_predoff);
+    s.pred = reinterpret_cast<const uint16_t *>(b + D.off_pred);
+    s.succoff = reinterpret_cast<const uint16_t *>(b + D.off_succoff);
+    s.succ = reinterpret_cast<const uint16_t *>(b + D.off_succ);
+    s.reqk = reinterpret_cast<const uint16_t *>(b + D.off_reqk);
+    s.base = reinterpret_cast<const uint16_t *>(b + D.off_base);
+    s.lvl = reinterpret_cast<const uint16_t *>(b + D.off_lvl);
+    s.rq = b + D.off_rq;
+    s.res = b + D.off_res;
+    s.W = reinterpret_cast<uint16_t *>(lds + Ly.W);
+    s.Wimp = reinterpret_cast<uint16_t *>(lds + Ly.Wimp);
+    s.pos = reinterpret_cast<uint16_t *>(lds + Ly.pos);
+    s.fs = reinterpret_cast<uint16_t *>(lds + Ly.fs);
+    s.lp = reinterpret_cast<uint16_t *>(lds + Ly.lp);
+    s.cnt = reinterpret_cast<int *>(lds + Ly.cnt);
+    s.tc = lds + Ly.tc;
+    s.ring = lds + Ly.ring;
+    s.moves = lds + Ly.moves;
+    s.red = reinterpret_cast<unsigned long long *>(lds + Ly.red);
+    s.scal = reinterpret_cast<int *>(lds + Ly.scal);
+    s.region = lds + Ly.region;
+    return s;
+}
+
+template <int T>
+__device__ inline void stage_blob(uint32_t *lds, const InstDesc &D, const Layout &Ly) {
+    for (int i = threadIdx.x; i < D.blob_dwords; i += T) lds[Ly.blob + i] = D.blob[i];
+}
+
+// Lane-private storage: dword i at base[i*STRIDE]; 16-bit element e in dword e>>1.
+template <int STRIDE>
+struct LaneMem {
+    uint32_t *base;
+    __device__ inline uint32_t ld(int i) const { return base[i * STRIDE]; }
+    __device__ inline void st(int i, uint32_t v) const { base[i * STRIDE] = v; }
+    __device__ inline int ld16(int e) const {
+        return reinterpret_cast<const uint16_t *>(base + (e >> 1) * STRIDE)[e & 1];
+    }
+    __device__ inline void st16(int e, int v) const {
+        reinterpret_cast<uint16_t *>(base + (e >> 1) * STRIDE)[e & 1] = (uint16_t)v;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Random numbers: counter-based SplitMix64 (Steele, Lea & Flood 2014).
+
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint32_t rng_below(uint64_t seed, uint64_t stream, uint64_t i, uint32_t n) {
+    const uint64_t G = 0x9E3779B97F4A7C15ull;
+    uint64_t key = mix64(seed + (stream + 1) * G);
+    uint64_t x = mix64(key + (i + 1) * G);
+    return (uint32_t)(((x >> 32) * (uint64_t)n) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup primitives
+
+template <int T>
+__device__ inline int block_excl_scan(int x, int *total, int *sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) sh[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < T / 64; ++i) {
+            int t = sh[i];
+            sh[i] = acc;
+            acc += t;
+        }
+        sh[T / 64] = acc;
+    }
+    __syncthreads();
+    int r = incl - x + sh[w];
+    *total = sh[T / 64];
+    __syncthreads();
+    return r;
+}
+
+template <int T>
+__device__ inline unsigned long long block_min_u64(unsigned long long x, unsigned long long *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < T / 64; ++i) x = red[i] < x ? red[i] : x;
+        red[0] = x;
+    }
+    __syncthreads();
+    x = red[0];
+    __syncthreads();
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Neighbourhood (Sections 4.2-4.4)
+
+// Position of the first successor / last predecessor of each w_p, then the
+// feasible swaps in canonical order (u ascending, v ascending).  Returns the
+// number of feasible moves (uniform across the workgroup).
+template <int T>
+__device__ int build_moves(const Sh &S, const InstDesc &D, int delta) {
+    const int N = D.n, tid = threadIdx.x;
+    for (int p = tid; p < N; p += T) S.pos[S.W[p]] = (uint16_t)p;
+    __syncthreads();
+    for (int p = tid; p < N; p += T) {
+        const int a = S.W[p];
+        int fsv = N, lpv = 0;  // lp stored +1; 0 = no predecessor
+        for (int e = S.succoff[a]; e < S.succoff[a + 1]; ++e) fsv = min(fsv, (int)S.pos[S.succ[e]]);
+        for (int e = S.predoff[a]; e < S.predoff[a + 1]; ++e) lpv = max(lpv, (int)S.pos[S.pred[e]] + 1);
+        S.fs[p] = (uint16_t)fsv;
+        S.lp[p] = (uint16_t)lpv;
+    }
+    __syncthreads();
+    const int nu = N - 2;
+    const int ch = (nu + T - 1) / T;
+    const int u0 = 1 + tid * ch, u1 = min(u0 + ch, N - 1);
+    int c = 0;
+    for (int u = u0; u < u1; ++u) {
+        const int vmax = min(min(u + delta, N - 2), (int)S.fs[u] - 1);
+        for (int v = u + 1; v <= vmax; ++v) c += (S.lp[v] <= u);
+    }
+    int total;
+    int off = block_excl_scan<T>(c, &total, S.cnt);
+    for (int u = u0; u < u1; ++u) {
+        const int vmax = min(min(u + delta, N - 2), (int)S.fs[u] - 1);
+        for (int v = u + 1; v <= vmax; ++v)
+            if (S.lp[v] <= u) S.moves[off++] = (uint32_t)u | ((uint32_t)v << 16);
+    }
+    __syncthreads();
+    return total;
+}
+
+// Canonical index of swap(u,v) among all potential moves.
+__device__ inline int canon_index(int N, int delta, int u, int v) {
+    const int Lp = N - 2;
+    const int dd = min(delta, Lp - 1);
+    int cum;
+    if (u - 1 <= Lp - dd) {
+        cum = (u - 1) * dd;
+    } else {
+        cum = (Lp - dd) * dd + ((dd - 1) * dd) / 2 - ((Lp - u) * (Lp - u + 1)) / 2;
+    }
+    return cum + (v - u - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Schedule decoders (Section 5).  The candidate order is W with positions u
+// and v exchanged (u = v = 0 decodes W itself).  Finish times s_a + d_a are
+// kept per activity; C_max is the finish time of the end dummy N-1.
+
+// Time-indexed: Alg. 5 scans for the first d consecutive time units at or
+// after es_prec with enough capacity on every resource; Alg. 6 subtracts the
+// requests over [s, s+d).  Only the first L time units are held; a lane whose
+// schedule would pass L reports overflow and is decoded again with a longer
+// profile.  Time units at or beyond `front` have never been written and hold
+// the full capacity implicitly.
+template <int NW, int STRIDE>
+__device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, int L, int u, int v,
+                         bool &ovf) {
+    LaneMem<STRIDE> M{lane_base};
+    const int N = D.n;
+    const int F0 = (N + 1) >> 1;
+    uint32_t G[NW], FULL[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        G[w] = D.guard[w];
+        FULL[w] = D.full[w];
+    }
+    const int wu = S.W[u], wv = S.W[v];
+    int front = 0;
+    for (int p = 0; p < N; ++p) {
+        int a = S.W[p];
+        a = (p == u) ? wv : a;
+        a = (p == v) ? wu : a;
+        int es = 0;
+        const int e1 = S.predoff[a + 1];
+        for (int e = S.predoff[a]; e < e1; ++e) es = max(es, M.ld16(S.pred[e]));
+        const int d = S.dur[a];
+        uint32_t rq[NW];
+        uint32_t any = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            rq[w] = S.rq[a * NW + w];
+            any |= rq[w];
+        }
+        int s = es;
+        if (any != 0 && d > 0) {
+            int t = es, run = 0;
+            while (run < d) {
+                if (t >= L) {
+                    ovf = true;
+                    return -1;
+                }
+                bool ok = true;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    uint32_t A = (t < front) ? M.ld(F0 + t * NW + w) : FULL[w];
+                    ok = ok && ((((A | G[w]) - rq[w]) & G[w]) == G[w]);
+                }
+                run = ok ? run + 1 : 0;
+                ++t;
+            }
+            s = t - d;
+            for (int x = front; x < s; ++x) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) M.st(F0 + x * NW + w, FULL[w]);
+            }
+            for (int x = s; x < s + d; ++x) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    uint32_t A = (x < front) ? M.ld(F0 + x * NW + w) : FULL[w];
+                    M.st(F0 + x * NW + w, A - rq[w]);
+                }
+            }
+            front = max(front, s + d);
+        }
+        M.st16(a, s + d);
+    }
+    return M.ld16(N - 1);
+}
+
+// Capacity-indexed: eq. 7 gives the resource earliest start, Alg. 4 updates
+// each c_k.  c_k holds R_k 16-bit times; Alg. 4's auxiliary copy array is
+// only read r_ik entries behind its write position, so a ring of copy_p
+// (a power of two >= every request) entries replaces it.
+template <int STRIDE>
+__device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, int u, int v) {
+    LaneMem<STRIDE> M{lane_base};
+    const int N = D.n, Mr = D.m;
+    const int F0 = (N + 1) >> 1;
+    const int Cd = (D.sum_r + 1) >> 1;
+    const int ce0 = 2 * F0;               // first c_k entry (16-bit element index)
+    const int pe0 = 2 * (F0 + Cd);        // first copy ring entry
+    const int pmask = D.copy_p - 1;
+    for (int i = 0; i < Cd; ++i) M.st(F0 + i, 0u);
+    const int wu = S.W[u], wv = S.W[v];
+    for (int p = 0; p < N; ++p) {
+        int a = S.W[p];
+        a = (p == u) ? wv : a;
+        a = (p == v) ? wu : a;
+        int es = 0;
+        const int e1 = S.predoff[a + 1];
+        for (int e = S.predoff[a]; e < e1; ++e) es = max(es, M.ld16(S.pred[e]));
+        const int d = S.dur[a];
+        int esr = 0;
+        for (int k = 0; k < Mr; ++k) {
+            const int r = S.reqk[a * Mr + k];
+            if (r > 0) esr = max(esr, M.ld16(ce0 + (int)S.res[2 * k + 1] + (int)S.res[2 * k] - r));
+        }
+        const int s = max(es, esr);
+        if (d > 0) {
+            for (int k = 0; k < Mr; ++k) {
+                const int r = S.reqk[a * Mr + k];
+                if (r == 0) continue;
+                const int cb = ce0 + (int)S.res[2 * k + 1], Rk = (int)S.res[2 * k];
+                int effort = r * d, ri = 0, ci = 0, newTime = s + d;
+                while (effort > 0 && ri < Rk) {
+                    const int cv = M.ld16(cb + ri);
+                    if (cv < newTime) {
+                        if (ci >= r) newTime = M.ld16(pe0 + ((ci - r) & pmask));
+                        const int td = newTime - max(cv, s);
+                        if (effort - td > 0) {
+                            effort -= td;
+                            M.st16(pe0 + (ci & pmask), cv);
+                            ++ci;
+                            M.st16(cb + ri, newTime);
+                        } else {
+                            M.st16(cb + ri, max(cv, s) + effort);
+                            effort = 0;
+                        }
+                    }
+                    ++ri;
+                }
+            }
+        }
+        M.st16(a, s + d);
+    }
+    return M.ld16(N - 1);
+}
+
+// One thread decodes W (no swap) using the whole decode region as its
+// private storage (stride 1): the time-indexed profile then spans long_len
+// >= horizon time units.
+template <int NW, int DEC>
+__device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int u, int v) {
+    if (DEC == kEvalTime) {
+        bool ovf = false;
+        return decode_ti<NW, 1>(S, D, S.region, Ly.long_len, u, v, ovf);
+    }
+    return decode_ci<1>(S, D, S.region, u, v);
+}
+
+// Key of a decoded move: non-admissible moves sort after admissible ones,
+// then (C_max, u, v) lexicographically.
+__device__ inline unsigned long long move_key(int c, int u, int v, bool tabu, int asp) {
+    const bool adm = !tabu || c < asp;
+    return ((unsigned long long)(adm ? 0u : 1u) << 63) | ((unsigned long long)(uint32_t)c << 32) |
+           ((unsigned long long)(uint32_t)u << 16) | (unsigned long long)(uint32_t)v;
+}
+
+__device__ inline bool tc_get(const uint32_t *tc, int tcw, int u, int v) {
+    const int o = v - u - 1;
+    return (tc[u * tcw + (o >> 5)] >> (o & 31)) & 1u;
+}
+
+struct TabuSrc {
+    const uint32_t *tc;     // LDS tabu cache bits or null
+    const uint8_t *bytes;   // global N*N bytes or null
+    int tcw, n;
+    __device__ inline bool get(int u, int v) const {
+        if (tc) return tc_get(tc, tcw, u, v);
+        if (bytes) return bytes[u * n + v] != 0;
+        return false;
+    }
+};
+
+// Decode every feasible move; return the workgroup's minimum key.
+// out_mk (global, canonical index) receives every makespan when non-null.
+template <int NW, int T, int DEC>
+__device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
+                                             int L, int delta, TabuSrc tabu, int asp, int *out_mk,
+                                             long long *ovf_total) {
+    const int tid = threadIdx.x;
+    unsigned long long best = ~0ull;
+    int *ovf_n = S.scal;
+    if (tid == 0) *ovf_n = 0;
+    __syncthreads();
+    uint32_t *lane_base = S.region + tid;
+    for (int j0 = 0; j0 < nfeas; j0 += T) {
+        const int j = j0 + tid;
+        if (j < nfeas) {
+            const uint32_t mv = S.moves[j];
+            const int u = mv & 0xffff, v = mv >> 16;
+            bool ovf = false;
+            int c;
+            if (DEC == kEvalTime) c = decode_ti<NW, T>(S, D, lane_base, L, u, v, ovf);
+            else c = decode_ci<T>(S, D, lane_base, u, v);
+            if (ovf) {
+                S.moves[j] = mv | 0x80000000u;
+                atomicAdd(ovf_n, 1);
+            } else {
+                const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
+                best = k < best ? k : best;
+                if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+            }
+        }
+    }
+    __syncthreads();
+    if (DEC == kEvalTime) {
+        const int novf = *ovf_n;
+        if (novf > 0) {
+            if (tid == 0) {
+                for (int j = 0; j < nfeas; ++j) {
+                    const uint32_t mv = S.moves[j];
+                    if (mv & 0x80000000u) {
+                        const int u = mv & 0xffff, v = (mv >> 16) & 0x7fff;
+                        const int c = decode_long<NW, DEC>(S, D, Ly, u, v);
+                        const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
+                        best = k < best ? k : best;
+                        if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+                        S.moves[j] = mv & 0x7fffffffu;
+                    }
+                }
+                if (ovf_total) *ovf_total += novf;
+            }
+            __syncthreads();
+        }
+    }
+    return block_min_u64<T>(best, S.red);
+}
+
+// ---------------------------------------------------------------------------
+// rcpsp_evaluate_neighbourhood
+
+template <int NW, int T, int DEC>
+__global__ __launch_bounds__(T) void k_eval(EvalArgs A) {
+    extern __shared__ uint32_t lds[];
+    const InstDesc &D = A.D;
+    const Layout &Ly = A.Ly;
+    Sh S = make_sh(lds, D, Ly);
+    const int N = D.n, tid = threadIdx.x;
+    stage_blob<T>(lds, D, Ly);
+    __shared__ int err;
+    if (tid == 0) err = 0;
+    for (int p = tid; p < N; p += T) S.fs[p] = 0;
+    __syncthreads();
+    // the order must be a permutation with w_0 = 0, w_{N-1} = N-1 ...
+    for (int p = tid; p < N; p += T) {
+        const int a = A.order[p];
+        if (a < 0 || a >= N) err = 1;
+        else S.W[p] = (uint16_t)a;
+    }
+    __syncthreads();
+    if (!err) {
+        // every id seen exactly once: 16-bit counters, two per dword
+        for (int p = tid; p < N; p += T) {
+            const int a = S.W[p];
+            const unsigned int prev =
+                atomicAdd(reinterpret_cast<unsigned int *>(S.fs + (a & ~1)), (a & 1) ? 0x10000u : 1u);
+            if (((prev >> ((a & 1) * 16)) & 0xffffu) != 0u) err = 1;
+        }
+        if (tid == 0 && (S.W[0] != 0 || S.W[N - 1] != N - 1)) err = 1;
+    }
+    __syncthreads();
+    // ... and respect every precedence arc
+    if (!err) {
+        for (int p = tid; p < N; p += T) S.pos[S.W[p]] = (uint16_t)p;
+        __syncthreads();
+        for (int i = tid; i < N; i += T)
+            for (int e = S.succoff[i]; e < S.succoff[i + 1]; ++e)
+                if (S.pos[i] >= S.pos[S.succ[e]]) err = 1;
+    }
+    __syncthreads();
+    if (err) {
+        if (tid == 0) A.best[3] = -5;  // RCPSP_E_ORDER
+        return;
+    }
+    const int nf = build_moves<T>(S, D, A.delta);
+    if (A.makespan) {
+        for (int i = tid; i < A.P; i += T) A.makespan[i] = -1;
+    }
+    __syncthreads();
+    TabuSrc tb{nullptr, A.tabu, 0, N};
+    const unsigned long long k =
+        evaluate_moves<NW, T, DEC>(S, D, Ly, nf, A.L, A.delta, tb, A.aspiration, A.makespan, nullptr);
+    if (tid == 0) {
+        if (nf == 0) {
+            A.best[0] = 0; A.best[1] = 0; A.best[2] = -1; A.best[3] = 0;
+        } else {
+            A.best[0] = (int)((k >> 16) & 0xffff);
+            A.best[1] = (int)(k & 0xffff);
+            A.best[2] = (int)((k >> 32) & 0x7fffffff);
+            A.best[3] = nf;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tabu search
+
+// Reset a search plan to its initial state.  Block i: search i (if i < B)
+// and working-set record i (if i < NF).  Initial orders (Section 4.1): the
+// level order (levels ascending, ids ascending) with every level shuffled by
+// Fisher-Yates on the stream (seed, i).
+__global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
+    __shared__ uint16_t w[kMaxN];
+    const InstDesc &D = A.D;
+    const int i = blockIdx.x, tid = threadIdx.x, N = D.n, N2 = n2(N);
+    const uint16_t *base = reinterpret_cast<const uint16_t *>(D.blob + D.off_base);
+    const uint16_t *lvl = reinterpret_cast<const uint16_t *>(D.blob + D.off_lvl);
+    const bool has_search = i < A.B, has_rec = i < A.NF;
+    for (int p = tid; p < N; p += 64) w[p] = base[p];
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t ctr = 0;
+        for (int l = 0; l < D.n_levels; ++l) {
+            const int b0 = lvl[l], len = lvl[l + 1] - lvl[l];
+            for (int j = len - 1; j >= 1; --j) {
+                const int r = (int)rng_below(A.seed, kStreamInit + (uint64_t)i, ctr++, (uint32_t)(j + 1));
+                const uint16_t t = w[b0 + j];
+                w[b0 + j] = w[b0 + r];
+                w[b0 + r] = t;
+            }
+        }
+    }
+    __syncthreads();
+    const int tcn = N * A.tcw;
+    if (has_search) {
+        if (A.NF == 0)
+            for (int p = tid; p < N2; p += 64) A.Wcur[(size_t)i * N2 + p] = p < N ? w[p] : 0;
+        for (int x = tid; x < A.tl; x += 64) A.ring[(size_t)i * A.tl + x] = 0;
+        for (int x = tid; x < tcn; x += 64) A.tc[(size_t)i * tcn + x] = 0;
+        if (A.record && A.traj) {
+            const size_t n4 = (size_t)A.iters * 4;
+            for (size_t x = tid; x < n4; x += 64) A.traj[(size_t)i * n4 + x] = -1;
+        }
+        if (tid == 0) {
+            SearchScalars s = {};
+            s.C_cur = 0x7fffffff; s.C_best = 0x7fffffff; s.C_imp = 0x7fffffff; s.C_read = 0x7fffffff;
+            s.flags = A.NF == 0 ? kFlagInitDecode : 0;
+            A.sc[i] = s;
+        }
+    }
+    if (has_rec) {
+        for (int p = tid; p < N2; p += 64) A.Fw[(size_t)i * N2 + p] = p < N ? w[p] : 0;
+        for (int x = tid; x < A.tl; x += 64) A.Fring[(size_t)i * A.tl + x] = 0;
+        for (int x = tid; x < tcn; x += 64) A.Ftc[(size_t)i * tcn + x] = 0;
+        if (tid == 0) {
+            A.Fwidx[i] = 0;
+            A.Fmeta[i].IC = 0; A.Fmeta[i].reads = 0; A.Fmeta[i].buf = 0; A.Fmeta[i].C = 0x7fffffff;
+        }
+    }
+    if (i == 0 && tid == 0) {
+        A.g->Cstar = 0x7fffffff;
+        A.g->gstop = 0;
+    }
+}
+
+// Makespan of every initial working-set record (buffer 0).
+template <int NW, int T, int DEC>
+__global__ __launch_bounds__(T) void k_decode_records(SearchArgs A) {
+    extern __shared__ uint32_t lds[];
+    const InstDesc &D = A.D;
+    Sh S = make_sh(lds, D, A.Ly);
+    const int k = blockIdx.x, N2 = n2(D.n);
+    stage_blob<T>(lds, D, A.Ly);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(A.Fw + (size_t)k * N2);
+    for (int i = threadIdx.x; i < N2 / 2; i += T) reinterpret_cast<uint32_t *>(S.W)[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) A.Fmeta[k].C = decode_long<NW, DEC>(S, D, A.Ly, 0, 0);
+}
+
+template <int T>
+__device__ inline void copy_dw(uint32_t *dst, const uint32_t *src, int n) {
+    for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
+}
+
+// One workgroup per search; iterations [it0, it0 + n_it).
+template <int NW, int T, int DEC>
+__global__ __launch_bounds__(T) void k_search(SearchArgs A) {
+    extern __shared__ uint32_t lds[];
+    __shared__ SearchScalars sc;
+    __shared__ int dirty_best, dirty_imp;
+    const InstDesc &D = A.D;
+    const Layout &Ly = A.Ly;
+    Sh S = make_sh(lds, D, Ly);
+    const int b = blockIdx.x, tid = threadIdx.x, N = D.n, N2 = n2(N);
+    const int tcn = N * A.tcw;
+    const bool coop = A.NF > 0;
+    if (tid == 0) {
+        sc = A.sc[b];
+        dirty_best = 0;
+        dirty_imp = 0;
+    }
+    stage_blob<T>(lds, D, Ly);
+    __syncthreads();
+    // control flow below depends on the flags as loaded; thread 0 rewrites
+    // sc.flags later, so every thread takes its copy before that can happen.
+    // After a global stop (the working set reached the critical path) a
+    // read chosen by the last round is still completed, then nothing runs.
+    const int flags0 = sc.flags;
+    const bool gstop = A.g->gstop != 0;
+    if (sc.stopped || (gstop && !(flags0 & (kFlagReadPending | kFlagInitDecode)))) return;
+    const int it_end = gstop ? A.it0 : A.it0 + A.n_it;
+    __syncthreads();
+    uint32_t *Wd = reinterpret_cast<uint32_t *>(S.W);
+    if (flags0 & kFlagReadPending) {
+        const uint32_t *sw, *sr, *st;
+        int swidx;
+        if (sc.src_kind == kSrcRecord) {
+            const size_t r = (size_t)sc.src_buf * A.NF + sc.src_idx;
+            sw = reinterpret_cast<const uint32_t *>(A.Fw + r * N2);
+            sr = A.Fring + r * A.tl;
+            st = A.Ftc + r * tcn;
+            swidx = A.Fwidx[r];
+        } else {
+            const size_t r = (size_t)sc.src_buf * A.B + sc.src_idx;
+            sw = reinterpret_cast<const uint32_t *>(A.Xw + r * N2);
+            sr = A.Xring + r * A.tl;
+            st = A.Xtc + r * tcn;
+            swidx = A.Xwidx[r];
+        }
+        copy_dw<T>(Wd, sw, N2 / 2);
+        copy_dw<T>(S.ring, sr, A.tl);
+        copy_dw<T>(S.tc, st, tcn);
+        __syncthreads();
+        if (tid == 0) {
+            sc.widx = swidx;
+            sc.C_cur = sc.src_C;
+        }
+        if (flags0 & kFlagDiversify) {
+            // Section 6.1: phi_steps random feasible swaps, tabu list untouched
+            for (int step = 0; step < A.phi_steps; ++step) {
+                const int nf = build_moves<T>(S, D, A.delta);
+                if (nf == 0) break;
+                if (tid == 0) {
+                    const int j = (int)rng_below(A.seed, kStreamDiversify + (uint64_t)b, sc.rng_ctr++, (uint32_t)nf);
+                    const uint32_t mv = S.moves[j];
+                    const int u = mv & 0xffff, v = mv >> 16;
+                    const uint16_t t = S.W[u];
+                    S.W[u] = S.W[v];
+                    S.W[v] = t;
+                }
+                __syncthreads();
+            }
+            if (tid == 0) sc.C_cur = decode_long<NW, DEC>(S, D, Ly, 0, 0);
+        }
+        __syncthreads();
+        copy_dw<T>(reinterpret_cast<uint32_t *>(S.Wimp), Wd, N2 / 2);
+        if (tid == 0) {
+            sc.C_imp = sc.C_cur;
+            if (sc.C_cur < sc.C_best) {
+                sc.C_best = sc.C_cur;
+                dirty_best = 1;
+            }
+            sc.flags &= ~(kFlagReadPending | kFlagDiversify);
+        }
+        __syncthreads();
+    } else {
+        copy_dw<T>(Wd, reinterpret_cast<const uint32_t *>(A.Wcur + (size_t)b * N2), N2 / 2);
+        copy_dw<T>(S.ring, A.ring + (size_t)b * A.tl, A.tl);
+        copy_dw<T>(S.tc, A.tc + (size_t)b * tcn, tcn);
+        if (coop) copy_dw<T>(reinterpret_cast<uint32_t *>(S.Wimp),
+                             reinterpret_cast<const uint32_t *>(A.Wimp + (size_t)b * N2), N2 / 2);
+        __syncthreads();
+        if (flags0 & kFlagInitDecode) {
+            if (tid == 0) {
+                sc.C_cur = decode_long<NW, DEC>(S, D, Ly, 0, 0);
+                sc.C_best = sc.C_cur;
+                dirty_best = 1;
+                sc.flags &= ~kFlagInitDecode;
+            }
+            __syncthreads();
+        }
+    }
+    const int dirty0 = dirty_best;
+    __syncthreads();
+    if (dirty0) copy_dw<T>(reinterpret_cast<uint32_t *>(A.Wbest + (size_t)b * N2), Wd, N2 / 2);
+    if (tid == 0) dirty_best = 0;
+    __syncthreads();
+
+    TabuSrc tb{S.tc, nullptr, A.tcw, N};
+    for (int it = A.it0; it < it_end; ++it) {
+        bool stop = sc.it_done >= A.iters || (!coop && sc.C_best == D.cp);
+        const int asp = coop ? min(sc.C_best, A.g->Cstar) : sc.C_best;
+        __syncthreads();
+        if (stop) {
+            if (tid == 0 && sc.it_done < A.iters) sc.stopped = 1;
+            break;
+        }
+        const int nf = build_moves<T>(S, D, A.delta);
+        if (nf == 0) {
+            if (tid == 0) sc.stopped = 1;
+            break;
+        }
+        const unsigned long long key =
+            evaluate_moves<NW, T, DEC>(S, D, Ly, nf, A.L, A.delta, tb, asp, nullptr, &sc.overflow);
+        if (tid == 0) {
+            const int u = (int)((key >> 16) & 0xffff), v = (int)(key & 0xffff);
+            const int c = (int)((key >> 32) & 0x7fffffff);
+            const uint16_t t = S.W[u];
+            S.W[u] = S.W[v];
+            S.W[v] = t;
+            // Alg. 3: evict the oldest entry, insert (u,v), advance the write index
+            const uint32_t old = S.ring[sc.widx];
+            if (old != 0u) {
+                const int uo = old & 0xffff, vo = old >> 16, o = vo - uo - 1;
+                S.tc[uo * A.tcw + (o >> 5)] &= ~(1u << (o & 31));
+            }
+            S.ring[sc.widx] = (uint32_t)u | ((uint32_t)v << 16);
+            {
+                const int o = v - u - 1;
+                S.tc[u * A.tcw + (o >> 5)] |= 1u << (o & 31);
+            }
+            sc.widx = (sc.widx + 1) % A.tl;
+            sc.C_cur = c;
+            sc.evals += nf;
+            if (c < sc.C_best) {
+                sc.C_best = c;
+                dirty_best = 1;
+            }
+            if (A.record) {
+                int *rec = A.traj + ((size_t)b * A.iters + it) * 4;
+                rec[0] = u; rec[1] = v; rec[2] = c; rec[3] = sc.C_best;
+            }
+            sc.it_done++;
+            if (coop) {
+                sc.it_read++;
+                if (c < sc.C_imp) {
+                    sc.C_imp = c;
+                    dirty_imp = 1;
+                }
+                sc.fired = (sc.C_imp < sc.C_read) || (sc.it_read > sc.I_assigned);
+            }
+        }
+        __syncthreads();
+        const int db = dirty_best, di = dirty_imp;
+        if (db) copy_dw<T>(reinterpret_cast<uint32_t *>(A.Wbest + (size_t)b * N2), Wd, N2 / 2);
+        if (di) copy_dw<T>(reinterpret_cast<uint32_t *>(S.Wimp), Wd, N2 / 2);
+        __syncthreads();
+        if (tid == 0) {
+            dirty_best = 0;
+            dirty_imp = 0;
+        }
+        __syncthreads();
+    }
+    // export for the exchange round
+    if (coop && sc.fired && sc.C_imp < sc.C_read) {
+        const int par = A.it0 & 1;
+        const size_t r = (size_t)par * A.B + b;
+        copy_dw<T>(reinterpret_cast<uint32_t *>(A.Xw + r * N2), reinterpret_cast<uint32_t *>(S.Wimp), N2 / 2);
+        copy_dw<T>(A.Xring + r * A.tl, S.ring, A.tl);
+        copy_dw<T>(A.Xtc + r * tcn, S.tc, tcn);
+        if (tid == 0) A.Xwidx[r] = sc.widx;
+    }
+    copy_dw<T>(reinterpret_cast<uint32_t *>(A.Wcur + (size_t)b * N2), Wd, N2 / 2);
+    copy_dw<T>(A.ring + (size_t)b * A.tl, S.ring, A.tl);
+    copy_dw<T>(A.tc + (size_t)b * tcn, S.tc, tcn);
+    if (coop)
+        copy_dw<T>(reinterpret_cast<uint32_t *>(A.Wimp + (size_t)b * N2), reinterpret_cast<uint32_t *>(S.Wimp),
+                   N2 / 2);
+    __syncthreads();
+    if (tid == 0) A.sc[b] = sc;
+}
+
+// eq. 8, read as floor(I_block (4 E[a] + E[b]) / (25 * 2^24)) >= 1 with the
+// decay table E[j] ~ 2^24 exp(-j/256).
+__device__ inline int iterations_assigned(int iblock, int ck, int cstar, int ic, const uint32_t *E, int elen) {
+    const long long a = cstar > 0 ? (25600ll * (ck - cstar)) / cstar : 0;
+    const long long bq = iblock > 0 ? (1024ll * ic) / iblock : 0;
+    const long long ea = (a >= 0 && a < elen) ? E[a] : 0;
+    const long long eb = (bq >= 0 && bq < elen) ? E[bq] : 0;
+    const long long ia = ((long long)iblock * (4 * ea + eb)) / (25ll << 24);
+    return ia < 1 ? 1 : (int)ia;
+}
+
+// Working-set exchange round (Section 6.1), one workgroup.  Searches whose
+// exchange condition fired are taken in ascending id: each writes its best
+// solution since its last read to the record it read (if it improved that
+// solution and beats the record's current content) and reads the next
+// record.  The bookkeeping is sequential; the data moves are done by the
+// readers themselves in the next iteration launch, from the record buffer or
+// from the writer's export buffer they were pointed at.
+__global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int init) {
+    extern __shared__ int rs[];
+    const int B = A.B, NF = A.NF, tid = threadIdx.x, N2 = n2(A.D.n), tcn = A.D.n * A.tcw;
+    int *fired = rs, *slot = rs + B, *itr = rs + 2 * B, *cimp = rs + 3 * B, *cread = rs + 4 * B;
+    int *newr = rs + 5 * B;
+    int *fC = rs + 6 * B, *fIC = fC + NF, *fR = fIC + NF, *fB = fR + NF, *content = fB + NF;
+    __shared__ int cstar_s;
+    for (int b = tid; b < B; b += 256) {
+        const SearchScalars &s = A.sc[b];
+        if (init) {
+            fired[b] = 1;
+            slot[b] = (b + NF - 1) % NF;
+            itr[b] = 0;
+            cimp[b] = 0x7fffffff;
+            cread[b] = 0x7fffffff;
+        } else {
+            fired[b] = s.fired && !s.stopped;
+            slot[b] = s.slot;
+            itr[b] = s.it_read;
+            cimp[b] = s.C_imp;
+            cread[b] = s.C_read;
+        }
+        newr[b] = 0;
+    }
+    for (int k = tid; k < NF; k += 256) {
+        fC[k] = A.Fmeta[k].C;
+        fIC[k] = A.Fmeta[k].IC;
+        fR[k] = A.Fmeta[k].reads;
+        fB[k] = A.Fmeta[k].buf;
+        content[k] = -1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int cstar = 0x7fffffff;
+        for (int k = 0; k < NF; ++k) cstar = min(cstar, fC[k]);
+        for (int b = 0; b < B; ++b) {
+            if (!fired[b]) continue;
+            const int k = slot[b];
+            fIC[k] += itr[b];
+            if (cimp[b] < cread[b] && cimp[b] < fC[k]) {
+                fC[k] = cimp[b];
+                fIC[k] = 0;
+                fR[k] = 0;
+                content[k] = b;
+                cstar = min(cstar, fC[k]);
+            }
+            const int k2 = (k + 1) % NF;
+            fR[k2] += 1;
+            SearchScalars &s = A.sc[b];
+            if (content[k2] < 0) {
+                s.src_kind = kSrcRecord;
+                s.src_idx = k2;
+                s.src_buf = fB[k2];
+            } else {
+                s.src_kind = kSrcExport;
+                s.src_idx = content[k2];
+                s.src_buf = parity;
+            }
+            s.src_C = fC[k2];
+            s.C_read = fC[k2];
+            s.I_assigned = iterations_assigned(A.iters, fC[k2], cstar, fIC[k2], A.decay, A.decay_len);
+            s.flags |= kFlagReadPending | (fR[k2] > A.phi_max ? kFlagDiversify : 0);
+            s.slot = k2;
+            s.it_read = 0;
+            s.fired = 0;
+            newr[b] = 1;
+        }
+        cstar_s = cstar;
+    }
+    __syncthreads();
+    // final content of each written record -> its other buffer
+    for (int k = 0; k < NF; ++k) {
+        const int w = content[k];
+        if (w < 0) continue;
+        const size_t src = (size_t)parity * B + w;
+        const size_t dst = (size_t)(fB[k] ^ 1) * NF + k;
+        for (int i = tid; i < N2 / 2; i += 256)
+            reinterpret_cast<uint32_t *>(A.Fw + dst * N2)[i] = reinterpret_cast<const uint32_t *>(A.Xw + src * N2)[i];
+        for (int i = tid; i < A.tl; i += 256) A.Fring[dst * A.tl + i] = A.Xring[src * A.tl + i];
+        for (int i = tid; i < tcn; i += 256) A.Ftc[dst * tcn + i] = A.Xtc[src * tcn + i];
+        if (tid == 0) A.Fwidx[dst] = A.Xwidx[src];
+    }
+    __syncthreads();
+    for (int k = tid; k < NF; k += 256) {
+        A.Fmeta[k].C = fC[k];
+        A.Fmeta[k].IC = fIC[k];
+        A.Fmeta[k].reads = fR[k];
+        A.Fmeta[k].buf = content[k] >= 0 ? (fB[k] ^ 1) : fB[k];
+    }
+    if (tid == 0) {
+        A.g->Cstar = cstar_s;
+        A.g->gstop = cstar_s == A.D.cp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+#define RCPSP_DISPATCH(NWV, TV, DECV, CALL)                                                 \
+    switch (DECV) {                                                                         \
+    case kEvalCapacity:                                                                     \
+        switch (TV) {                                                                       \
+        case 64: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity; CALL; } break;     \
+        case 128: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity; CALL; } break;   \
+        case 256: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity; CALL; } break;   \
+        default: return hipErrorInvalidValue;                                               \
+        }                                                                                   \
+        break;                                                                              \
+    default:                                                                                \
+        switch ((TV) * 16 + (NWV)) {                                                        \
+        case 64 * 16 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime; CALL; } break;    \
+        case 64 * 16 + 2: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime; CALL; } break;    \
+        case 64 * 16 + 4: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime; CALL; } break;    \
+        case 128 * 16 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime; CALL; } break;  \
+        case 128 * 16 + 2: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime; CALL; } break;  \
+        case 128 * 16 + 4: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime; CALL; } break;  \
+        case 256 * 16 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime; CALL; } break;  \
+        case 256 * 16 + 2: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime; CALL; } break;  \
+        case 256 * 16 + 4: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime; CALL; } break;  \
+        default: return hipErrorInvalidValue;                                               \
+        }                                                                                   \
+    }
+
+template <typename K>
+static hipError_t set_lds(K kernel, size_t lds) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+hipError_t launch_eval(const EvalArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipError_t e = set_lds(k_eval<NW_, T_, DEC_>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_eval<NW_, T_, DEC_>), dim3(1), dim3(T_), lds, st, A);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(const SearchArgs &A, hipStream_t st) {
+    const int g = A.B > A.NF ? A.B : A.NF;
+    hipLaunchKernelGGL(k_reset, dim3(g), dim3(64), 0, st, A);
+    return hipGetLastError();
+}
+
+size_t round_lds_bytes(int B, int NF) { return sizeof(int) * (6 * (size_t)B + 5 * (size_t)NF); }
+
+// Raise the dynamic LDS limit of the search kernels (outside graph capture).
+hipError_t prepare_search(int T, int nw, int dec, size_t lds, int B, int NF) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipError_t e = set_lds(k_decode_records<NW_, T_, DEC_>, lds);
+        if (e != hipSuccess) return e;
+        e = set_lds(k_search<NW_, T_, DEC_>, lds);
+        if (e != hipSuccess) return e;
+    });
+    if (NF > 0) return set_lds(k_round, round_lds_bytes(B, NF));
+    return hipSuccess;
+}
+
+hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipLaunchKernelGGL((k_decode_records<NW_, T_, DEC_>), dim3(A.NF), dim3(T_), lds, st, A);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipLaunchKernelGGL((k_search<NW_, T_, DEC_>), dim3(A.B), dim3(T_), lds, st, A);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t st) {
+    const size_t lds = round_lds_bytes(A.B, A.NF);
+    hipLaunchKernelGGL(k_round, dim3(1), dim3(256), lds, st, A, parity, init);
+    return hipGetLastError();
+}
+
+}  // namespace rcpsp

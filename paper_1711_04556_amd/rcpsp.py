@@ -1,0 +1,252 @@
+"""Python binding of librcpsp (include/rcpsp.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+and torch tensors to pointers and status codes to exceptions.  It raises if
+the library has not been built or cannot be loaded (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from .build import LIB
+
+INT32_MAX = 2 ** 31 - 1
+
+EVAL_AUTO, EVAL_TIME, EVAL_CAPACITY = 0, 1, 2
+
+STATUS = {
+    0: "RCPSP_OK", -1: "RCPSP_E_ARG", -2: "RCPSP_E_CYCLE", -3: "RCPSP_E_REQUEST", -4: "RCPSP_E_DUMMY",
+    -5: "RCPSP_E_ORDER", -6: "RCPSP_E_BUFFER", -7: "RCPSP_E_NOMEM", -8: "RCPSP_E_DEVICE", -9: "RCPSP_E_TOO_LARGE",
+}
+
+
+class RcpspError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rcpsp_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "n", "m", "n_arcs", "horizon", "critical_path", "eval", "min_capacity", "max_capacity", "sum_capacity",
+        "field_bits", "avg_capacity_x1000", "avg_duration_x1000", "branch_factor_x1000")]
+
+
+class rcpsp_move(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_int32), ("v", ctypes.c_int32), ("makespan", ctypes.c_int32),
+                ("n_feasible", ctypes.c_int32)]
+
+
+class rcpsp_search_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
+        "profile_len", "record_trajectory")] + [("seed", ctypes.c_uint64)]
+
+
+class rcpsp_search_result(ctypes.Structure):
+    _fields_ = [("best_makespan", ctypes.c_void_p), ("best_order", ctypes.c_void_p),
+                ("iterations_done", ctypes.c_void_p), ("evaluations", ctypes.c_void_p),
+                ("trajectory", ctypes.c_void_p), ("elite_makespan", ctypes.c_void_p),
+                ("elite_order", ctypes.c_void_p), ("global_best", ctypes.c_int32),
+                ("total_evaluations", ctypes.c_int64), ("overflow_decodes", ctypes.c_int32)]
+
+
+class rcpsp_search_config(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches")]
+
+
+_lib = None
+
+
+def lib():
+    """Load librcpsp.so; raise if it is missing (build it with
+    paper_1711_04556_amd.build.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        raise RuntimeError(f"{LIB} is not built; run paper_1711_04556_amd.build.build() first")
+    L = ctypes.CDLL(LIB)
+    vp, i32, i32p, u8p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p
+    L.rcpsp_create_instance.argtypes = [i32, i32, i32p, i32p, i32p, i32p, i32p, ctypes.c_int, ctypes.POINTER(vp)]
+    L.rcpsp_create_instance.restype = ctypes.c_int
+    L.rcpsp_instance_info.argtypes = [vp, ctypes.POINTER(rcpsp_info)]
+    L.rcpsp_instance_info.restype = ctypes.c_int
+    L.rcpsp_destroy_instance.argtypes = [vp]
+    L.rcpsp_destroy_instance.restype = None
+    L.rcpsp_evaluate_neighbourhood.argtypes = [vp, i32p, i32, u8p, i32, i32p, i32, i32p,
+                                               ctypes.POINTER(rcpsp_move), vp]
+    L.rcpsp_evaluate_neighbourhood.restype = ctypes.c_int
+    L.rcpsp_evaluate_neighbourhood_device.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
+    L.rcpsp_evaluate_neighbourhood_device.restype = ctypes.c_int
+    L.rcpsp_potential_moves.argtypes = [i32, i32]
+    L.rcpsp_potential_moves.restype = i32
+    L.rcpsp_search_create.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), vp, ctypes.POINTER(vp)]
+    L.rcpsp_search_create.restype = ctypes.c_int
+    L.rcpsp_search_run.argtypes = [vp, vp]
+    L.rcpsp_search_run.restype = ctypes.c_int
+    L.rcpsp_search_results.argtypes = [vp, ctypes.POINTER(rcpsp_search_result), vp]
+    L.rcpsp_search_results.restype = ctypes.c_int
+    L.rcpsp_search_destroy.argtypes = [vp]
+    L.rcpsp_search_destroy.restype = None
+    L.rcpsp_search_get_config.argtypes = [vp, ctypes.POINTER(rcpsp_search_config)]
+    L.rcpsp_search_get_config.restype = ctypes.c_int
+    L.rcpsp_tabu_search.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), ctypes.POINTER(rcpsp_search_result), vp]
+    L.rcpsp_tabu_search.restype = ctypes.c_int
+    L.rcpsp_last_error.argtypes = []
+    L.rcpsp_last_error.restype = ctypes.c_char_p
+    L.rcpsp_version.argtypes = []
+    L.rcpsp_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise RcpspError(status, lib().rcpsp_last_error().decode())
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a: Optional[np.ndarray], ct=ctypes.c_int32):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream)) or None
+
+
+def potential_moves(n: int, swap_range: int) -> int:
+    return lib().rcpsp_potential_moves(n, swap_range)
+
+
+class Instance:
+    """A project instance on the current device (rcpsp_create_instance)."""
+
+    def __init__(self, inst, eval: int = EVAL_AUTO):
+        L = lib()
+        self.n, self.m = inst.n, inst.m
+        d, R, r = _i32(inst.duration), _i32(inst.capacity), _i32(inst.request)
+        so = _i32(inst.succ_off)
+        s = _i32(inst.succ_flat if inst.n_arcs else [0])
+        h = ctypes.c_void_p()
+        _check(L.rcpsp_create_instance(inst.n, inst.m, _ptr(d), _ptr(R), _ptr(r), _ptr(so), _ptr(s), eval,
+                                       ctypes.byref(h)))
+        self.h = h
+
+    def close(self) -> None:
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.rcpsp_destroy_instance(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def info(self) -> dict:
+        out = rcpsp_info()
+        _check(lib().rcpsp_instance_info(self.h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in rcpsp_info._fields_}
+
+    def evaluate_neighbourhood(self, order: Sequence[int], swap_range: int, tabu: Optional[np.ndarray] = None,
+                               aspiration: int = INT32_MAX, stream=None):
+        """Host arrays in and out: returns (makespan[P] with -1 for infeasible
+        moves, dict(u, v, makespan, n_feasible))."""
+        P = potential_moves(self.n, swap_range)
+        mk = np.zeros(max(P, 1), dtype=np.int32)
+        best = rcpsp_move()
+        npot = ctypes.c_int32()
+        tb = None
+        if tabu is not None:
+            tb = np.ascontiguousarray(np.asarray(tabu, dtype=np.uint8).reshape(self.n * self.n))
+        _check(lib().rcpsp_evaluate_neighbourhood(self.h, _ptr(_i32(order)), swap_range,
+                                                  tb.ctypes.data if tb is not None else None, aspiration,
+                                                  _ptr(mk), mk.size, ctypes.byref(npot), ctypes.byref(best),
+                                                  _stream_ptr(stream)))
+        return mk[:P], dict(u=best.u, v=best.v, makespan=best.makespan, n_feasible=best.n_feasible)
+
+    def evaluate_neighbourhood_device(self, order, swap_range: int, makespan, best, tabu=None,
+                                      aspiration: int = INT32_MAX, stream=None) -> None:
+        """Device tensors (torch, int32 / uint8): order[N], makespan[P],
+        best[4] = (u, v, C_max, n_feasible); asynchronous on `stream`."""
+        _check(lib().rcpsp_evaluate_neighbourhood_device(
+            self.h, order.data_ptr(), swap_range, tabu.data_ptr() if tabu is not None else None, aspiration,
+            makespan.data_ptr() if makespan is not None else None, best.data_ptr(), _stream_ptr(stream)))
+
+
+def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
+                  phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
+                  record_trajectory: bool = True, seed: int = 1) -> rcpsp_search_params:
+    return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
+                               profile_len, int(record_trajectory), seed)
+
+
+class SearchPlan:
+    """rcpsp_search_create / _run / _results / _destroy."""
+
+    def __init__(self, instance: Instance, params: rcpsp_search_params, stream=None):
+        self.instance = instance
+        self.params = params
+        h = ctypes.c_void_p()
+        _check(lib().rcpsp_search_create(instance.h, ctypes.byref(params), _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self) -> None:
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.rcpsp_search_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def config(self) -> dict:
+        out = rcpsp_search_config()
+        _check(lib().rcpsp_search_get_config(self.h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in rcpsp_search_config._fields_}
+
+    def run(self, stream=None) -> None:
+        _check(lib().rcpsp_search_run(self.h, _stream_ptr(stream)))
+
+    def results(self, stream=None, orders: bool = True, trajectory: bool = True) -> dict:
+        p = self.params
+        B, N, F = p.searches, self.instance.n, p.elite
+        out = dict(best_makespan=np.zeros(B, np.int32), iterations_done=np.zeros(B, np.int32),
+                   evaluations=np.zeros(B, np.int64),
+                   best_order=np.zeros((B, N), np.int32) if orders else None,
+                   trajectory=np.zeros((B, p.iterations, 4), np.int32) if (trajectory and p.record_trajectory) else None,
+                   elite_makespan=np.zeros(max(F, 1), np.int32),
+                   elite_order=np.zeros((max(F, 1), N), np.int32) if orders else None)
+        res = rcpsp_search_result(*[out[k].ctypes.data if out[k] is not None else None for k in
+                                    ("best_makespan", "best_order", "iterations_done", "evaluations", "trajectory",
+                                     "elite_makespan", "elite_order")])
+        _check(lib().rcpsp_search_results(self.h, ctypes.byref(res), _stream_ptr(stream)))
+        out["elite_makespan"] = out["elite_makespan"][:F]
+        if out["elite_order"] is not None:
+            out["elite_order"] = out["elite_order"][:F]
+        out["global_best"] = res.global_best
+        out["total_evaluations"] = res.total_evaluations
+        out["overflow_decodes"] = res.overflow_decodes
+        return out
+
+
+def tabu_search(instance: Instance, stream=None, **kw) -> dict:
+    plan = SearchPlan(instance, search_params(**kw), stream)
+    try:
+        plan.run(stream)
+        return plan.results(stream)
+    finally:
+        plan.close()
+
+
+def version() -> str:
+    return lib().rcpsp_version().decode()

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.  All results are integers and must match exactly."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_04556_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TIME, CAP = 1, 2
+
+
+@pytest.fixture(scope="module")
+def rc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_04556_amd import rcpsp
+    rcpsp.lib()
+    return rcpsp
+
+
+def _serial_instance():
+    """One resource, every activity needs all of it: C_max = sum of durations,
+    far beyond the default profile length (exercises the long-profile path)."""
+    base = synth.generate(14, 1, 6, 1.0, rs=0.5, seed=77)
+    req = [0] + [4] * (base.n - 2) + [0]
+    return synth.Instance(n=base.n, m=1, duration=base.duration, capacity=[4], request=req, succ=base.succ,
+                          name="serial14")
+
+
+def _wide_instance():
+    """Capacities above 127 force 16-bit profile fields (two dwords for M=4)."""
+    return synth.generate(40, 4, 10, 0.75, rs=0.7, seed=3003, name="wide40")
+
+
+EVAL_CASES = [
+    ("table1", synth.table1_instance, 10),
+    ("g30", lambda: synth.single_instance_30(1), 8),
+    ("tiny", lambda: synth.random_tiny(5, n_real=5), 3),
+    ("g60", lambda: synth.generate(60, 4, 10, 0.5, rs=0.4, seed=61), 14),
+    ("wide40", _wide_instance, 12),
+    ("m8", lambda: synth.generate(50, 8, 20, 0.5, rs=None, cap_range=(10, 60), seed=4001), 20),
+    ("serial14", _serial_instance, 5),
+    ("g120", synth.instance_120_rs30, 20),
+]
+
+
+@pytest.mark.parametrize("name,make,delta", EVAL_CASES, ids=[c[0] for c in EVAL_CASES])
+@pytest.mark.parametrize("dec", [TIME, CAP])
+def test_neighbourhood_parity(rc, name, make, delta, dec):
+    inst = make()
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=dec)
+    assert gi.info["eval"] == dec
+    rng = synth.Stream(17, 3)
+    for t in range(3):
+        W = synth.random_feasible_order(inst, 100 + t) if t else orc.initial_order(5, 0)
+        tabu = None
+        asp = 2 ** 31 - 1
+        if t == 2:
+            tabu = np.zeros((inst.n, inst.n), np.uint8)
+            for _ in range(3 * inst.n):
+                u = 1 + rng.below(max(inst.n - 3, 1))
+                v = min(u + 1 + rng.below(delta), inst.n - 2)
+                if v > u:
+                    tabu[u, v] = 1
+            asp = orc.decode(W, dec)
+        mk_g, best_g = gi.evaluate_neighbourhood(W, delta, tabu=tabu, aspiration=asp)
+        mk_o, best_o = orc.evaluate_neighbourhood(W, delta, dec, tabu=tabu, aspiration=asp)
+        assert np.array_equal(mk_g, mk_o), (name, t, np.nonzero(mk_g != mk_o)[0][:10])
+        assert [best_g["u"], best_g["v"], best_g["makespan"], best_g["n_feasible"]] == best_o
+
+
+def test_neighbourhood_edge_cases(rc):
+    # one real activity: no potential move at all
+    one = synth.Instance(n=3, m=1, duration=[0, 3, 0], capacity=[2], request=[0, 1, 0], succ=[[1], [2], []])
+    gi = rc.Instance(one, eval=TIME)
+    mk, best = gi.evaluate_neighbourhood([0, 1, 2], 4)
+    assert mk.size == 0 and best == dict(u=0, v=0, makespan=-1, n_feasible=0)
+    # a chain: every swap breaks a precedence arc
+    chain = synth.Instance(n=6, m=1, duration=[0, 1, 2, 3, 4, 0], capacity=[1], request=[0, 1, 1, 1, 1, 0],
+                           succ=[[1], [2], [3], [4], [5], []])
+    gi = rc.Instance(chain, eval=CAP)
+    mk, best = gi.evaluate_neighbourhood([0, 1, 2, 3, 4, 5], 3)
+    assert (mk == -1).all() and best["n_feasible"] == 0
+    # swap range beyond N
+    inst = synth.single_instance_30(1)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    W = orc.initial_order(1, 3)
+    mk_g, b_g = gi.evaluate_neighbourhood(W, 64)
+    mk_o, b_o = orc.evaluate_neighbourhood(W, 64, TIME)
+    assert np.array_equal(mk_g, mk_o)
+    # an infeasible order is rejected
+    bad = list(W)
+    i = bad.index(inst.succ[0][0])
+    bad[i], bad[-2] = bad[-2], bad[i]
+    if not orc.is_feasible_order(bad):
+        with pytest.raises(rc.RcpspError) as e:
+            gi.evaluate_neighbourhood(bad, 8)
+        assert e.value.status == -5
+
+
+def test_neighbourhood_device_variant(rc):
+    import torch
+    inst = synth.generate(60, 4, 10, 0.5, rs=0.4, seed=62)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    W = orc.initial_order(2, 1)
+    P = rc.potential_moves(inst.n, 14)
+    order = torch.tensor(W, dtype=torch.int32, device="cuda")
+    mk = torch.empty(P, dtype=torch.int32, device="cuda")
+    best = torch.empty(4, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+    gi.evaluate_neighbourhood_device(order, 14, mk, best, stream=s)
+    torch.cuda.synchronize()
+    mk_o, best_o = orc.evaluate_neighbourhood(W, 14, TIME)
+    assert np.array_equal(mk.cpu().numpy(), mk_o)
+    assert best.cpu().tolist() == best_o
+    # invalid order: duplicate id -> n_feasible = RCPSP_E_ORDER, makespans untouched
+    bad = list(W)
+    bad[5] = bad[6]
+    mk.fill_(7)
+    gi.evaluate_neighbourhood_device(torch.tensor(bad, dtype=torch.int32, device="cuda"), 14, mk, best, stream=s)
+    torch.cuda.synchronize()
+    assert best.cpu().tolist()[3] == -5
+    assert (mk.cpu().numpy() == 7).all()
+
+
+def _compare_search(g, o, elite=0):
+    assert np.array_equal(g["trajectory"], o["trajectory"]), np.argwhere(g["trajectory"] != o["trajectory"])[:5]
+    assert np.array_equal(g["best_makespan"], o["best_makespan"])
+    assert np.array_equal(g["iterations_done"], o["iterations_done"])
+    assert np.array_equal(g["evaluations"], o["evaluations"])
+    assert np.array_equal(g["best_order"], o["best_order"])
+    if elite:
+        assert np.array_equal(g["elite_makespan"], o["elite_makespan"])
+        assert np.array_equal(g["elite_order"], o["elite_order"])
+
+
+@pytest.mark.parametrize("dec", [TIME, CAP])
+def test_single_search_trajectory_30(rc, dec):
+    """30 activities, 4 resources, one search, swap range 8, tabu list 60, 200 iterations, seed 1."""
+    inst = synth.single_instance_30(1)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=dec)
+    kw = dict(swap_range=8, tabu_len=60, iterations=200, searches=1, elite=0, seed=1)
+    g = rc.tabu_search(gi, **kw)
+    o = orc.tabu_search(8, 60, 200, searches=1, elite=0, decoder=dec, seed=1)
+    _compare_search(g, o)
+
+
+@pytest.mark.parametrize("threads", [64, 128, 256])
+def test_independent_searches_any_launch_shape(rc, threads):
+    inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=63)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    g = rc.tabu_search(gi, swap_range=14, tabu_len=110, iterations=40, searches=5, threads=threads, seed=4)
+    o = orc.tabu_search(14, 110, 40, searches=5, decoder=TIME, seed=4)
+    _compare_search(g, o)
+
+
+def test_short_profile_overflow_path(rc):
+    """A 16-slot lane profile forces most candidates through the long-profile
+    decode; results must not change."""
+    inst = synth.single_instance_30(1)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    g = rc.tabu_search(gi, swap_range=8, tabu_len=60, iterations=30, searches=2, profile_len=16, seed=2)
+    o = orc.tabu_search(8, 60, 30, searches=2, decoder=TIME, seed=2)
+    _compare_search(g, o)
+    assert g["overflow_decodes"] > 0
+
+
+@pytest.mark.parametrize("dec", [TIME, CAP])
+def test_cooperative_search_small(rc, dec):
+    inst = synth.generate(30, 4, 10, 0.5, rs=0.3, seed=21)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=dec)
+    kw = dict(swap_range=8, tabu_len=40, iterations=40, searches=12, elite=4, phi_max=3, phi_steps=5, seed=9)
+    g = rc.tabu_search(gi, **kw)
+    o = orc.tabu_search(8, 40, 40, searches=12, elite=4, phi_max=3, phi_steps=5, decoder=dec, seed=9)
+    _compare_search(g, o, elite=4)
+
+
+def test_cooperative_search_many_exchanges(rc):
+    """Short stints (I_block small) make searches exchange almost every
+    iteration, including several writers and readers of one record per round."""
+    inst = synth.generate(20, 3, 8, 0.6, rs=0.25, seed=22)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=6, tabu_len=12, iterations=25, searches=20, elite=3, phi_max=1, phi_steps=3, seed=5)
+    g = rc.tabu_search(gi, **kw)
+    o = orc.tabu_search(6, 12, 25, searches=20, elite=3, phi_max=1, phi_steps=3, decoder=TIME, seed=5)
+    _compare_search(g, o, elite=3)
+
+
+def test_plan_rerun_is_identical(rc):
+    inst = synth.generate(30, 4, 10, 0.5, rs=0.3, seed=23)
+    gi = rc.Instance(inst, eval=CAP)
+    plan = rc.SearchPlan(gi, rc.search_params(8, 40, 30, searches=8, elite=4, phi_steps=5, seed=3))
+    plan.run()
+    a = plan.results()
+    plan.run()
+    b = plan.results()
+    for k in ("trajectory", "best_makespan", "evaluations", "elite_order", "best_order"):
+        assert np.array_equal(a[k], b[k]), k
+    plan.close()
+
+
+def test_plain_480_searches_full_size_short_run(rc):
+    """The 120-activity workload (480 searches, working set 16, swap range 20,
+    tabu list 329) in the launch configuration the benchmark times, for 3
+    iterations: every trajectory record, best and working set match."""
+    inst = synth.instance_120_rs30()
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=20, tabu_len=329, iterations=3, searches=480, elite=16, phi_max=3, phi_steps=20, seed=2)
+    g = rc.tabu_search(gi, **kw)
+    o = orc.tabu_search(20, 329, 3, searches=480, elite=16, phi_max=3, phi_steps=20, decoder=TIME, seed=2)
+    _compare_search(g, o, elite=16)
+
+
+def test_plain_480_searches_full_run_properties(rc):
+    """Full 1000-iteration run: properties that hold at any size, checked with
+    the oracle's decoder on the returned orders."""
+    inst = synth.instance_120_rs30()
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst)
+    dec = gi.info["eval"]
+    g = rc.tabu_search(gi, swap_range=20, tabu_len=329, iterations=1000, searches=480, elite=16, phi_max=3,
+                       phi_steps=20, seed=2)
+    cp = orc.critical_path
+    assert g["global_best"] >= cp
+    assert g["global_best"] == min(g["best_makespan"].min(), g["elite_makespan"].min())
+    for b in range(0, 480, 37):
+        assert orc.is_feasible_order(g["best_order"][b])
+        assert orc.decode(g["best_order"][b], dec) == g["best_makespan"][b]
+        tr = g["trajectory"][b]
+        done = g["iterations_done"][b]
+        assert (tr[done:] == -1).all()
+        assert (np.diff(tr[:done, 3]) <= 0).all()
+    for k in range(16):
+        assert orc.is_feasible_order(g["elite_order"][k])
+        assert orc.decode(g["elite_order"][k], dec) == g["elite_makespan"][k]
+    assert g["total_evaluations"] == g["evaluations"].sum() > 0
