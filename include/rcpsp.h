@@ -139,6 +139,8 @@ typedef struct {
     int32_t threads;          /* threads per search: 0 = auto, else 64, 128, 256 */
     int32_t profile_len;      /* time-indexed LDS profile slots per lane, 0 = auto */
     int32_t record_trajectory;/* 1 = keep (u, v, C_after, C_best) per iteration on the device */
+    int32_t count_work;       /* 1 = also count the decodes' algorithmic operations
+                                 (instrumented kernels; for measurement runs) */
     uint64_t seed;            /* seeds the initial orders and diversification */
 } rcpsp_search_params;
 
@@ -154,6 +156,11 @@ typedef struct {
     int32_t global_best;      /* out: minimum over searches and working set */
     int64_t total_evaluations;/* out */
     int32_t overflow_decodes; /* out: candidates that needed the long-profile path */
+    int64_t total_work;       /* out: algorithmic operations (count_work plans only):
+                                 time-indexed: activities + predecessor reads + time
+                                 units examined by Alg. 5 + time units updated by
+                                 Alg. 6; capacity-indexed: activities + predecessor
+                                 reads + eq. 7 lookups + Alg. 4 loop steps */
 } rcpsp_search_result;
 
 typedef struct rcpsp_search rcpsp_search;
@@ -167,6 +174,12 @@ rcpsp_status rcpsp_search_create(const rcpsp_instance *inst, const rcpsp_search_
  * model: no host traffic).  Asynchronous; may be called repeatedly and
  * gives the same results each time. */
 rcpsp_status rcpsp_search_run(rcpsp_search *s, void *hip_stream);
+/* Same launches as rcpsp_search_run, issued one by one on hip_stream with
+ * HIP events around each iteration-kernel and exchange-round launch; waits
+ * for completion and reports the summed device milliseconds of each kind and
+ * of the whole run (any pointer may be NULL).  Synchronous. */
+rcpsp_status rcpsp_search_run_timed(rcpsp_search *s, void *hip_stream, double *iteration_ms,
+                                    double *round_ms, double *total_ms);
 /* Wait for hip_stream and copy the results to the host buffers. */
 rcpsp_status rcpsp_search_results(rcpsp_search *s, rcpsp_search_result *res, void *hip_stream);
 void rcpsp_search_destroy(rcpsp_search *s);

@@ -548,6 +548,78 @@ extern "C" void rcpsp_search_destroy(rcpsp_search *s) {
     delete s;
 }
 
+// Timing of one eager run: HIP events recorded on the launch stream around
+// every iteration-kernel and exchange-round launch.
+struct RunTimer {
+    std::vector<hipEvent_t> it_ev, rd_ev;
+    size_t it_n = 0, rd_n = 0;
+    hipError_t mark(std::vector<hipEvent_t> &v, size_t &n, hipStream_t st) {
+        if (n == v.size()) {
+            hipEvent_t ev;
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return e;
+            v.push_back(ev);
+        }
+        return hipEventRecord(v[n++], st);
+    }
+    ~RunTimer() {
+        for (hipEvent_t e : it_ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : rd_ev) (void)hipEventDestroy(e);
+    }
+};
+
+// The launch sequence of one run: reset, then for a working set the record
+// decodes, the initial exchange round and iteration/round pairs; without a
+// working set one launch runs every iteration.
+static hipError_t enqueue_run(rcpsp_search *s, hipStream_t st, RunTimer *tm) {
+    const rcpsp_search_params &p = s->p;
+    const SearchArgs &a = s->a;
+    const int T = s->T, NF = p.elite;
+    hipError_t e;
+    auto search = [&](int it0, int n_it) -> hipError_t {
+        SearchArgs ai = a;
+        ai.it0 = it0;
+        ai.n_it = n_it;
+        hipError_t r;
+        if (tm && (r = tm->mark(tm->it_ev, tm->it_n, st)) != hipSuccess) return r;
+        if ((r = launch_search(ai, T, s->nw, s->dec, s->lds, st)) != hipSuccess) return r;
+        if (tm && (r = tm->mark(tm->it_ev, tm->it_n, st)) != hipSuccess) return r;
+        return hipSuccess;
+    };
+    auto round = [&](int parity, int init) -> hipError_t {
+        hipError_t r;
+        if (tm && (r = tm->mark(tm->rd_ev, tm->rd_n, st)) != hipSuccess) return r;
+        if ((r = launch_round(a, parity, init, st)) != hipSuccess) return r;
+        if (tm && (r = tm->mark(tm->rd_ev, tm->rd_n, st)) != hipSuccess) return r;
+        return hipSuccess;
+    };
+    int nit = 0, nrd = 0;
+    if ((e = launch_reset(a, st)) != hipSuccess) return e;
+    if (NF > 0) {
+        if ((e = launch_decode_records(a, T, s->nw, s->dec, s->lds, st)) != hipSuccess) return e;
+        if ((e = round(0, 1)) != hipSuccess) return e;
+        ++nrd;
+        for (int it = 0; it < p.iterations; ++it) {
+            if ((e = search(it, 1)) != hipSuccess) return e;
+            ++nit;
+            if (it < p.iterations - 1) {
+                if ((e = round(it & 1, 0)) != hipSuccess) return e;
+                ++nrd;
+            }
+        }
+        if (p.iterations == 0) {
+            if ((e = search(0, 0)) != hipSuccess) return e;
+            ++nit;
+        }
+    } else {
+        if ((e = search(0, p.iterations)) != hipSuccess) return e;
+        ++nit;
+    }
+    s->iteration_launches = nit;
+    s->round_launches = nrd;
+    return hipSuccess;
+}
+
 static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     const rcpsp_instance *I = s->inst;
     const rcpsp_search_params &p = s->p;
@@ -584,6 +656,7 @@ static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     a.tcw = s->tcw;
     a.L = s->L;
     a.record = p.record_trajectory ? 1 : 0;
+    a.count_work = p.count_work ? 1 : 0;
     a.seed = p.seed;
     const int tcn = N * s->tcw;
     HIP_TRY(dalloc(s, &a.sc, sizeof(SearchScalars) * B));
@@ -626,48 +699,17 @@ static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    auto end_capture = [&](hipError_t err) -> rcpsp_status {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(cs, &g);
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipStreamDestroy(cs);
-        return fail(RCPSP_E_DEVICE, "graph capture failed: %s", hipGetErrorString(err));
-    };
     if (e != hipSuccess) {
         (void)hipStreamDestroy(cs);
         return fail(RCPSP_E_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     }
-    s->iteration_launches = 0;
-    s->round_launches = 0;
-    if ((e = launch_reset(a, cs)) != hipSuccess) return end_capture(e);
-    if (NF > 0) {
-        if ((e = launch_decode_records(a, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
-        if ((e = launch_round(a, 0, 1, cs)) != hipSuccess) return end_capture(e);
-        s->round_launches++;
-        for (int it = 0; it < p.iterations; ++it) {
-            SearchArgs ai = a;
-            ai.it0 = it;
-            ai.n_it = 1;
-            if ((e = launch_search(ai, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
-            s->iteration_launches++;
-            if (it < p.iterations - 1) {
-                if ((e = launch_round(ai, it & 1, 0, cs)) != hipSuccess) return end_capture(e);
-                s->round_launches++;
-            }
-        }
-        if (p.iterations == 0) {
-            SearchArgs ai = a;
-            ai.it0 = 0;
-            ai.n_it = 0;
-            if ((e = launch_search(ai, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
-            s->iteration_launches++;
-        }
-    } else {
-        SearchArgs ai = a;
-        ai.it0 = 0;
-        ai.n_it = p.iterations;
-        if ((e = launch_search(ai, T, s->nw, s->dec, s->lds, cs)) != hipSuccess) return end_capture(e);
-        s->iteration_launches++;
+    e = enqueue_run(s, cs, nullptr);
+    if (e != hipSuccess) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        return fail(RCPSP_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
     }
     e = hipStreamEndCapture(cs, &s->graph);
     (void)hipStreamDestroy(cs);
@@ -710,6 +752,33 @@ extern "C" rcpsp_status rcpsp_search_run(rcpsp_search *s, void *hip_stream) {
     return RCPSP_OK;
 }
 
+extern "C" rcpsp_status rcpsp_search_run_timed(rcpsp_search *s, void *hip_stream, double *iteration_ms,
+                                               double *round_ms, double *total_ms) {
+    if (!s) return fail(RCPSP_E_ARG, "null search");
+    hipStream_t st = (hipStream_t)hip_stream;
+    RunTimer tm;
+    hipEvent_t t0, t1;
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, st));
+    hipError_t e = enqueue_run(s, st, &tm);
+    if (e == hipSuccess) e = hipEventRecord(t1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    double it = 0.0, rd = 0.0;
+    float ms = 0.f;
+    for (size_t i = 0; e == hipSuccess && i + 1 < tm.it_n; i += 2)
+        if ((e = hipEventElapsedTime(&ms, tm.it_ev[i], tm.it_ev[i + 1])) == hipSuccess) it += ms;
+    for (size_t i = 0; e == hipSuccess && i + 1 < tm.rd_n; i += 2)
+        if ((e = hipEventElapsedTime(&ms, tm.rd_ev[i], tm.rd_ev[i + 1])) == hipSuccess) rd += ms;
+    if (e == hipSuccess && (e = hipEventElapsedTime(&ms, t0, t1)) == hipSuccess && total_ms) *total_ms = ms;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return fail(RCPSP_E_DEVICE, "timed run: %s", hipGetErrorString(e));
+    if (iteration_ms) *iteration_ms = it;
+    if (round_ms) *round_ms = rd;
+    return RCPSP_OK;
+}
+
 extern "C" rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out) {
     if (!s || !out) return fail(RCPSP_E_ARG, "null pointer");
     out->threads = s->T;
@@ -729,11 +798,12 @@ extern "C" rcpsp_status rcpsp_search_results(rcpsp_search *s, rcpsp_search_resul
     std::vector<SearchScalars> sc(B);
     HIP_TRY(hipMemcpy(sc.data(), a.sc, sizeof(SearchScalars) * B, hipMemcpyDeviceToHost));
     int gbest = INT_MAX;
-    long long tot = 0, ovf = 0;
+    long long tot = 0, ovf = 0, work = 0;
     for (int b = 0; b < B; ++b) {
         gbest = std::min(gbest, sc[b].C_best);
         tot += sc[b].evals;
         ovf += sc[b].overflow;
+        work += sc[b].work;
         if (res->best_makespan) res->best_makespan[b] = sc[b].C_best;
         if (res->iterations_done) res->iterations_done[b] = sc[b].it_done;
         if (res->evaluations) res->evaluations[b] = sc[b].evals;
@@ -765,6 +835,7 @@ extern "C" rcpsp_status rcpsp_search_results(rcpsp_search *s, rcpsp_search_resul
     res->global_best = gbest;
     res->total_evaluations = tot;
     res->overflow_decodes = (int32_t)std::min<long long>(ovf, INT_MAX);
+    res->total_work = work;
     return RCPSP_OK;
 }
 

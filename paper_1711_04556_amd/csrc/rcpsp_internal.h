@@ -52,7 +52,7 @@ struct SearchScalars {
     unsigned long long rng_ctr;
     long long evals;
     long long overflow;
-    long long pad;
+    long long work;      // algorithmic operations of all decodes (counting runs only)
 };
 
 enum : int {
@@ -79,7 +79,7 @@ constexpr uint64_t kStreamDiversify = 1ull << 32;
 struct SearchArgs {
     InstDesc D;
     Layout Ly;
-    int delta, tl, iters, B, NF, phi_max, phi_steps, tcw, L, record;
+    int delta, tl, iters, B, NF, phi_max, phi_steps, tcw, L, record, count_work;
     int it0, n_it;
     int decay_len;
     unsigned long long seed;

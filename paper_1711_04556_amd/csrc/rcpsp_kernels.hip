@@ -213,9 +213,14 @@ __device__ inline int canon_index(int N, int delta, int u, int v) {
 // schedule would pass L reports overflow and is decoded again with a longer
 // profile.  Time units at or beyond `front` have never been written and hold
 // the full capacity implicitly.
-template <int NW, int STRIDE>
+// With COUNT, *wk receives the decode's algorithmic operations: one per
+// activity, one per predecessor read, one per time unit examined by Alg. 5
+// and one per time unit updated by Alg. 6 (d of each for an activity that
+// requests nothing).
+template <int NW, int STRIDE, bool COUNT = false>
 __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, int L, int u, int v,
-                         bool &ovf) {
+                         bool &ovf, long long *wk = nullptr) {
+    long long w_ops = 0;
     LaneMem<STRIDE> M{lane_base};
     const int N = D.n;
     const int F0 = (N + 1) >> 1;
@@ -235,6 +240,7 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         const int e1 = S.predoff[a + 1];
         for (int e = S.predoff[a]; e < e1; ++e) es = max(es, M.ld16(S.pred[e]));
         const int d = S.dur[a];
+        if (COUNT) w_ops += 1 + (e1 - S.predoff[a]);
         uint32_t rq[NW];
         uint32_t any = 0;
 #pragma unroll
@@ -260,6 +266,7 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 ++t;
             }
             s = t - d;
+            if (COUNT) w_ops += (t - es) + d;
             for (int x = front; x < s; ++x) {
 #pragma unroll
                 for (int w = 0; w < NW; ++w) M.st(F0 + x * NW + w, FULL[w]);
@@ -272,9 +279,12 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 }
             }
             front = max(front, s + d);
+        } else if (COUNT) {
+            w_ops += 2 * d;
         }
         M.st16(a, s + d);
     }
+    if (COUNT) *wk += w_ops;
     return M.ld16(N - 1);
 }
 
@@ -282,8 +292,12 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
 // each c_k.  c_k holds R_k 16-bit times; Alg. 4's auxiliary copy array is
 // only read r_ik entries behind its write position, so a ring of copy_p
 // (a power of two >= every request) entries replaces it.
-template <int STRIDE>
-__device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, int u, int v) {
+// With COUNT, *wk receives one operation per activity, per predecessor read,
+// per eq. 7 lookup and per Alg. 4 loop step.
+template <int STRIDE, bool COUNT = false>
+__device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, int u, int v,
+                         long long *wk = nullptr) {
+    long long w_ops = 0;
     LaneMem<STRIDE> M{lane_base};
     const int N = D.n, Mr = D.m;
     const int F0 = (N + 1) >> 1;
@@ -301,10 +315,14 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         const int e1 = S.predoff[a + 1];
         for (int e = S.predoff[a]; e < e1; ++e) es = max(es, M.ld16(S.pred[e]));
         const int d = S.dur[a];
+        if (COUNT) w_ops += 1 + (e1 - S.predoff[a]);
         int esr = 0;
         for (int k = 0; k < Mr; ++k) {
             const int r = S.reqk[a * Mr + k];
-            if (r > 0) esr = max(esr, M.ld16(ce0 + (int)S.res[2 * k + 1] + (int)S.res[2 * k] - r));
+            if (r > 0) {
+                esr = max(esr, M.ld16(ce0 + (int)S.res[2 * k + 1] + (int)S.res[2 * k] - r));
+                if (COUNT) ++w_ops;
+            }
         }
         const int s = max(es, esr);
         if (d > 0) {
@@ -314,6 +332,7 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 const int cb = ce0 + (int)S.res[2 * k + 1], Rk = (int)S.res[2 * k];
                 int effort = r * d, ri = 0, ci = 0, newTime = s + d;
                 while (effort > 0 && ri < Rk) {
+                    if (COUNT) ++w_ops;
                     const int cv = M.ld16(cb + ri);
                     if (cv < newTime) {
                         if (ci >= r) newTime = M.ld16(pe0 + ((ci - r) & pmask));
@@ -334,19 +353,21 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         }
         M.st16(a, s + d);
     }
+    if (COUNT) *wk += w_ops;
     return M.ld16(N - 1);
 }
 
 // One thread decodes W (no swap) using the whole decode region as its
 // private storage (stride 1): the time-indexed profile then spans long_len
 // >= horizon time units.
-template <int NW, int DEC>
-__device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int u, int v) {
+template <int NW, int DEC, bool COUNT = false>
+__device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int u, int v,
+                           long long *wk = nullptr) {
     if (DEC == kEvalTime) {
         bool ovf = false;
-        return decode_ti<NW, 1>(S, D, S.region, Ly.long_len, u, v, ovf);
+        return decode_ti<NW, 1, COUNT>(S, D, S.region, Ly.long_len, u, v, ovf, wk);
     }
-    return decode_ci<1>(S, D, S.region, u, v);
+    return decode_ci<1, COUNT>(S, D, S.region, u, v, wk);
 }
 
 // Key of a decoded move: non-admissible moves sort after admissible ones,
@@ -373,14 +394,33 @@ struct TabuSrc {
     }
 };
 
+template <int T>
+__device__ inline long long block_sum_i64(long long x, unsigned long long *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (unsigned long long)x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < T / 64; ++i) x += (long long)red[i];
+        red[0] = (unsigned long long)x;
+    }
+    __syncthreads();
+    x = (long long)red[0];
+    __syncthreads();
+    return x;
+}
+
 // Decode every feasible move; return the workgroup's minimum key.
 // out_mk (global, canonical index) receives every makespan when non-null.
-template <int NW, int T, int DEC>
+// With COUNT, thread 0 adds the algorithmic operations of all decodes to
+// *work_total (a lane's aborted short-profile decode is not counted).
+template <int NW, int T, int DEC, bool COUNT = false>
 __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
                                              int L, int delta, TabuSrc tabu, int asp, int *out_mk,
-                                             long long *ovf_total) {
+                                             long long *ovf_total, long long *work_total = nullptr) {
     const int tid = threadIdx.x;
     unsigned long long best = ~0ull;
+    long long lw = 0;
     int *ovf_n = S.scal;
     if (tid == 0) *ovf_n = 0;
     __syncthreads();
@@ -392,8 +432,10 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
             const int u = mv & 0xffff, v = mv >> 16;
             bool ovf = false;
             int c;
-            if (DEC == kEvalTime) c = decode_ti<NW, T>(S, D, lane_base, L, u, v, ovf);
-            else c = decode_ci<T>(S, D, lane_base, u, v);
+            long long cw = 0;
+            if (DEC == kEvalTime) c = decode_ti<NW, T, COUNT>(S, D, lane_base, L, u, v, ovf, &cw);
+            else c = decode_ci<T, COUNT>(S, D, lane_base, u, v, &cw);
+            if (COUNT && !ovf) lw += cw;
             if (ovf) {
                 S.moves[j] = mv | 0x80000000u;
                 atomicAdd(ovf_n, 1);
@@ -413,7 +455,7 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
                     const uint32_t mv = S.moves[j];
                     if (mv & 0x80000000u) {
                         const int u = mv & 0xffff, v = (mv >> 16) & 0x7fff;
-                        const int c = decode_long<NW, DEC>(S, D, Ly, u, v);
+                        const int c = decode_long<NW, DEC, COUNT>(S, D, Ly, u, v, &lw);
                         const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
                         best = k < best ? k : best;
                         if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
@@ -424,6 +466,10 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
             }
             __syncthreads();
         }
+    }
+    if (COUNT) {
+        const long long tot = block_sum_i64<T>(lw, S.red);
+        if (tid == 0) *work_total += tot;
     }
     return block_min_u64<T>(best, S.red);
 }
@@ -574,8 +620,9 @@ __device__ inline void copy_dw(uint32_t *dst, const uint32_t *src, int n) {
     for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
 }
 
-// One workgroup per search; iterations [it0, it0 + n_it).
-template <int NW, int T, int DEC>
+// One workgroup per search; iterations [it0, it0 + n_it).  COUNT adds the
+// algorithmic operations of every decode to the search's work counter.
+template <int NW, int T, int DEC, bool COUNT>
 __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ SearchScalars sc;
@@ -693,7 +740,7 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
             break;
         }
         const unsigned long long key =
-            evaluate_moves<NW, T, DEC>(S, D, Ly, nf, A.L, A.delta, tb, asp, nullptr, &sc.overflow);
+            evaluate_moves<NW, T, DEC, COUNT>(S, D, Ly, nf, A.L, A.delta, tb, asp, nullptr, &sc.overflow, &sc.work);
         if (tid == 0) {
             const int u = (int)((key >> 16) & 0xffff), v = (int)(key & 0xffff);
             const int c = (int)((key >> 32) & 0x7fffffff);
@@ -931,7 +978,9 @@ hipError_t prepare_search(int T, int nw, int dec, size_t lds, int B, int NF) {
     RCPSP_DISPATCH(nw, T, dec, {
         hipError_t e = set_lds(k_decode_records<NW_, T_, DEC_>, lds);
         if (e != hipSuccess) return e;
-        e = set_lds(k_search<NW_, T_, DEC_>, lds);
+        e = set_lds(k_search<NW_, T_, DEC_, false>, lds);
+        if (e != hipSuccess) return e;
+        e = set_lds(k_search<NW_, T_, DEC_, true>, lds);
         if (e != hipSuccess) return e;
     });
     if (NF > 0) return set_lds(k_round, round_lds_bytes(B, NF));
@@ -947,7 +996,10 @@ hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, si
 
 hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
     RCPSP_DISPATCH(nw, T, dec, {
-        hipLaunchKernelGGL((k_search<NW_, T_, DEC_>), dim3(A.B), dim3(T_), lds, st, A);
+        if (A.count_work)
+            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, true>), dim3(A.B), dim3(T_), lds, st, A);
+        else
+            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, false>), dim3(A.B), dim3(T_), lds, st, A);
     });
     return hipGetLastError();
 }

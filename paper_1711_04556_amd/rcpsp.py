@@ -44,7 +44,7 @@ class rcpsp_move(ctypes.Structure):
 class rcpsp_search_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
-        "profile_len", "record_trajectory")] + [("seed", ctypes.c_uint64)]
+        "profile_len", "record_trajectory", "count_work")] + [("seed", ctypes.c_uint64)]
 
 
 class rcpsp_search_result(ctypes.Structure):
@@ -52,7 +52,8 @@ class rcpsp_search_result(ctypes.Structure):
                 ("iterations_done", ctypes.c_void_p), ("evaluations", ctypes.c_void_p),
                 ("trajectory", ctypes.c_void_p), ("elite_makespan", ctypes.c_void_p),
                 ("elite_order", ctypes.c_void_p), ("global_best", ctypes.c_int32),
-                ("total_evaluations", ctypes.c_int64), ("overflow_decodes", ctypes.c_int32)]
+                ("total_evaluations", ctypes.c_int64), ("overflow_decodes", ctypes.c_int32),
+                ("total_work", ctypes.c_int64)]
 
 
 class rcpsp_search_config(ctypes.Structure):
@@ -90,6 +91,9 @@ def lib():
     L.rcpsp_search_create.restype = ctypes.c_int
     L.rcpsp_search_run.argtypes = [vp, vp]
     L.rcpsp_search_run.restype = ctypes.c_int
+    L.rcpsp_search_run_timed.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+    L.rcpsp_search_run_timed.restype = ctypes.c_int
     L.rcpsp_search_results.argtypes = [vp, ctypes.POINTER(rcpsp_search_result), vp]
     L.rcpsp_search_results.restype = ctypes.c_int
     L.rcpsp_search_destroy.argtypes = [vp]
@@ -185,9 +189,9 @@ class Instance:
 
 def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                   phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
-                  record_trajectory: bool = True, seed: int = 1) -> rcpsp_search_params:
+                  record_trajectory: bool = True, count_work: bool = False, seed: int = 1) -> rcpsp_search_params:
     return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
-                               profile_len, int(record_trajectory), seed)
+                               profile_len, int(record_trajectory), int(count_work), seed)
 
 
 class SearchPlan:
@@ -217,6 +221,14 @@ class SearchPlan:
     def run(self, stream=None) -> None:
         _check(lib().rcpsp_search_run(self.h, _stream_ptr(stream)))
 
+    def run_timed(self, stream=None) -> dict:
+        """Eager run with HIP events around every launch: device milliseconds
+        of the iteration kernels, the exchange rounds and the whole run."""
+        it, rd, tot = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().rcpsp_search_run_timed(self.h, _stream_ptr(stream), ctypes.byref(it), ctypes.byref(rd),
+                                            ctypes.byref(tot)))
+        return dict(iteration_ms=it.value, round_ms=rd.value, total_ms=tot.value)
+
     def results(self, stream=None, orders: bool = True, trajectory: bool = True) -> dict:
         p = self.params
         B, N, F = p.searches, self.instance.n, p.elite
@@ -236,6 +248,7 @@ class SearchPlan:
         out["global_best"] = res.global_best
         out["total_evaluations"] = res.total_evaluations
         out["overflow_decodes"] = res.overflow_decodes
+        out["total_work"] = res.total_work
         return out
 
 

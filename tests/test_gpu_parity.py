@@ -246,3 +246,27 @@ def test_plain_480_searches_full_run_properties(rc):
         assert orc.is_feasible_order(g["elite_order"][k])
         assert orc.decode(g["elite_order"][k], dec) == g["elite_makespan"][k]
     assert g["total_evaluations"] == g["evaluations"].sum() > 0
+
+
+@pytest.mark.parametrize("dec", [TIME, CAP])
+def test_counting_and_timed_runs_match_graph_run(rc, dec):
+    """The instrumented (work-counting) kernels and the event-timed eager run
+    give the same search as the graph replay."""
+    inst = synth.generate(40, 4, 10, 0.5, rs=0.3, seed=24)
+    gi = rc.Instance(inst, eval=dec)
+    kw = dict(swap_range=10, tabu_len=60, iterations=20, searches=10, elite=4, phi_steps=4, seed=6)
+    plan = rc.SearchPlan(gi, rc.search_params(**kw))
+    plan.run()
+    a = plan.results()
+    t = plan.run_timed()
+    b = plan.results()
+    assert t["iteration_ms"] > 0 and t["total_ms"] >= t["iteration_ms"]
+    cplan = rc.SearchPlan(gi, rc.search_params(count_work=True, **kw))
+    cplan.run()
+    c = cplan.results()
+    for k in ("trajectory", "best_makespan", "evaluations", "elite_order", "best_order"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+    assert a["total_work"] == 0 and c["total_work"] > c["total_evaluations"] * inst.n
+    plan.close()
+    cplan.close()
