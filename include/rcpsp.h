@@ -141,6 +141,9 @@ typedef struct {
     int32_t record_trajectory;/* 1 = keep (u, v, C_after, C_best) per iteration on the device */
     int32_t count_work;       /* 1 = also count the decodes' algorithmic operations
                                  (instrumented kernels; for measurement runs) */
+    int32_t full_decode;      /* 1 = decode every candidate from its first position
+                                 instead of continuing from the schedule prefix it
+                                 shares with the current order (same results) */
     uint64_t seed;            /* seeds the initial orders and diversification */
 } rcpsp_search_params;
 

@@ -349,6 +349,7 @@ extern "C" void rcpsp_destroy_instance(rcpsp_instance *inst) {
 static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, int L, int dec) {
     Layout Ly{};
     const int N2h = n2(D.n) / 2;
+    const int F0 = (D.n + 1) / 2;
     int o = 0;
     Ly.blob = o; o += D.blob_dwords;
     Ly.W = o; o += N2h;
@@ -361,15 +362,22 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     Ly.ring = o; o += tl;
     Ly.moves = o; o += std::max(pmax, 1);
     o = (o + 1) & ~1;
+    Ly.prec = o; o += 2 * D.n;
+    Ly.prq = o; o += D.n * std::max(D.nw, 1);
+    o = (o + 1) & ~1;
     Ly.red = o; o += 2 * (T / 64);
     Ly.scal = o; o += 4;
+    // per candidate: finish times, then the time-indexed profile (L units
+    // plus 4 of slack for the 4-wide scan) or the capacity arrays and the
+    // copy ring
+    if (dec == kEvalTime) Ly.per_lane = F0 + (L + 4) * D.nw;
+    else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
+    o = (o + 3) & ~3;
+    Ly.bst = o; o += Ly.per_lane;
     o = (o + 3) & ~3;
     Ly.region = o;
-    const int F0 = (D.n + 1) / 2;
-    if (dec == kEvalTime) Ly.per_lane = F0 + L * D.nw;
-    else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
     o += T * Ly.per_lane;
-    Ly.long_len = dec == kEvalTime ? (T * Ly.per_lane - F0) / D.nw : 0;
+    Ly.long_len = dec == kEvalTime ? (T * Ly.per_lane - F0) / D.nw - 4 : 0;
     Ly.total = o;
     return Ly;
 }
@@ -657,6 +665,7 @@ static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     a.L = s->L;
     a.record = p.record_trajectory ? 1 : 0;
     a.count_work = p.count_work ? 1 : 0;
+    a.full_decode = p.full_decode ? 1 : 0;
     a.seed = p.seed;
     const int tcn = N * s->tcw;
     HIP_TRY(dalloc(s, &a.sc, sizeof(SearchScalars) * B));

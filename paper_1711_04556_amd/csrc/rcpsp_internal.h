@@ -37,9 +37,9 @@ struct InstDesc {
 
 // Dword offsets of the workgroup's LDS areas.
 struct Layout {
-    int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, red, scal, region;
+    int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, prec, prq, bst, red, scal, region;
     int per_lane;    // dwords of private decode state per lane
-    int long_len;    // time slots available to the single-lane long-profile decode
+    int long_len;    // time slots available to the single-thread long-profile decode
     int total;       // dwords
 };
 
@@ -79,7 +79,7 @@ constexpr uint64_t kStreamDiversify = 1ull << 32;
 struct SearchArgs {
     InstDesc D;
     Layout Ly;
-    int delta, tl, iters, B, NF, phi_max, phi_steps, tcw, L, record, count_work;
+    int delta, tl, iters, B, NF, phi_max, phi_steps, tcw, L, record, count_work, full_decode;
     int it0, n_it;
     int decay_len;
     unsigned long long seed;

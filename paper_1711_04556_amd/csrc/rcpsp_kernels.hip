@@ -32,7 +32,7 @@ struct Sh {
     const uint32_t *rq, *res;
     uint16_t *W, *Wimp, *pos, *fs, *lp;
     int *cnt;
-    uint32_t *tc, *ring, *moves;
+    uint32_t *tc, *ring, *moves, *prec, *prq, *bst;
     unsigned long long *red;
     int *scal;
     uint32_t *region;
@@ -60,6 +60,9 @@ __device__ inline Sh make_sh(uint32_t *lds, const InstDesc &D, const Layout &Ly)
     s.tc = lds + Ly.tc;
     s.ring = lds + Ly.ring;
     s.moves = lds + Ly.moves;
+    s.prec = lds + Ly.prec;
+    s.prq = lds + Ly.prq;
+    s.bst = lds + Ly.bst;
     s.red = reinterpret_cast<unsigned long long *>(lds + Ly.red);
     s.scal = reinterpret_cast<int *>(lds + Ly.scal);
     s.region = lds + Ly.region;
@@ -153,12 +156,28 @@ __device__ inline unsigned long long block_min_u64(unsigned long long x, unsigne
 // ---------------------------------------------------------------------------
 // Neighbourhood (Sections 4.2-4.4)
 
+// Per-position records of the current order W:
+//   prec[2p] = w_p | d << 16, prec[2p+1] = first predecessor index | count << 16,
+//   prq[p*NW + w] = packed requests of w_p (time-indexed profile words).
+template <int T>
+__device__ inline void build_records(const Sh &S, const InstDesc &D) {
+    const int N = D.n, NW = D.nw;
+    for (int p = threadIdx.x; p < N; p += T) {
+        const int a = S.W[p];
+        const int po = S.predoff[a];
+        S.prec[2 * p] = (uint32_t)a | ((uint32_t)S.dur[a] << 16);
+        S.prec[2 * p + 1] = (uint32_t)po | ((uint32_t)(S.predoff[a + 1] - po) << 16);
+        for (int w = 0; w < NW; ++w) S.prq[p * NW + w] = S.rq[a * NW + w];
+    }
+}
+
 // Position of the first successor / last predecessor of each w_p, then the
 // feasible swaps in canonical order (u ascending, v ascending).  Returns the
 // number of feasible moves (uniform across the workgroup).
 template <int T>
 __device__ int build_moves(const Sh &S, const InstDesc &D, int delta) {
     const int N = D.n, tid = threadIdx.x;
+    build_records<T>(S, D);
     for (int p = tid; p < N; p += T) S.pos[S.W[p]] = (uint16_t)p;
     __syncthreads();
     for (int p = tid; p < N; p += T) {
@@ -202,174 +221,6 @@ __device__ inline int canon_index(int N, int delta, int u, int v) {
     return cum + (v - u - 1);
 }
 
-// ---------------------------------------------------------------------------
-// Schedule decoders (Section 5).  The candidate order is W with positions u
-// and v exchanged (u = v = 0 decodes W itself).  Finish times s_a + d_a are
-// kept per activity; C_max is the finish time of the end dummy N-1.
-
-// Time-indexed: Alg. 5 scans for the first d consecutive time units at or
-// after es_prec with enough capacity on every resource; Alg. 6 subtracts the
-// requests over [s, s+d).  Only the first L time units are held; a lane whose
-// schedule would pass L reports overflow and is decoded again with a longer
-// profile.  Time units at or beyond `front` have never been written and hold
-// the full capacity implicitly.
-// With COUNT, *wk receives the decode's algorithmic operations: one per
-// activity, one per predecessor read, one per time unit examined by Alg. 5
-// and one per time unit updated by Alg. 6 (d of each for an activity that
-// requests nothing).
-template <int NW, int STRIDE, bool COUNT = false>
-__device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, int L, int u, int v,
-                         bool &ovf, long long *wk = nullptr) {
-    long long w_ops = 0;
-    LaneMem<STRIDE> M{lane_base};
-    const int N = D.n;
-    const int F0 = (N + 1) >> 1;
-    uint32_t G[NW], FULL[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        G[w] = D.guard[w];
-        FULL[w] = D.full[w];
-    }
-    const int wu = S.W[u], wv = S.W[v];
-    int front = 0;
-    for (int p = 0; p < N; ++p) {
-        int a = S.W[p];
-        a = (p == u) ? wv : a;
-        a = (p == v) ? wu : a;
-        int es = 0;
-        const int e1 = S.predoff[a + 1];
-        for (int e = S.predoff[a]; e < e1; ++e) es = max(es, M.ld16(S.pred[e]));
-        const int d = S.dur[a];
-        if (COUNT) w_ops += 1 + (e1 - S.predoff[a]);
-        uint32_t rq[NW];
-        uint32_t any = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            rq[w] = S.rq[a * NW + w];
-            any |= rq[w];
-        }
-        int s = es;
-        if (any != 0 && d > 0) {
-            int t = es, run = 0;
-            while (run < d) {
-                if (t >= L) {
-                    ovf = true;
-                    return -1;
-                }
-                bool ok = true;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    uint32_t A = (t < front) ? M.ld(F0 + t * NW + w) : FULL[w];
-                    ok = ok && ((((A | G[w]) - rq[w]) & G[w]) == G[w]);
-                }
-                run = ok ? run + 1 : 0;
-                ++t;
-            }
-            s = t - d;
-            if (COUNT) w_ops += (t - es) + d;
-            for (int x = front; x < s; ++x) {
-#pragma unroll
-                for (int w = 0; w < NW; ++w) M.st(F0 + x * NW + w, FULL[w]);
-            }
-            for (int x = s; x < s + d; ++x) {
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    uint32_t A = (x < front) ? M.ld(F0 + x * NW + w) : FULL[w];
-                    M.st(F0 + x * NW + w, A - rq[w]);
-                }
-            }
-            front = max(front, s + d);
-        } else if (COUNT) {
-            w_ops += 2 * d;
-        }
-        M.st16(a, s + d);
-    }
-    if (COUNT) *wk += w_ops;
-    return M.ld16(N - 1);
-}
-
-// Capacity-indexed: eq. 7 gives the resource earliest start, Alg. 4 updates
-// each c_k.  c_k holds R_k 16-bit times; Alg. 4's auxiliary copy array is
-// only read r_ik entries behind its write position, so a ring of copy_p
-// (a power of two >= every request) entries replaces it.
-// With COUNT, *wk receives one operation per activity, per predecessor read,
-// per eq. 7 lookup and per Alg. 4 loop step.
-template <int STRIDE, bool COUNT = false>
-__device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, int u, int v,
-                         long long *wk = nullptr) {
-    long long w_ops = 0;
-    LaneMem<STRIDE> M{lane_base};
-    const int N = D.n, Mr = D.m;
-    const int F0 = (N + 1) >> 1;
-    const int Cd = (D.sum_r + 1) >> 1;
-    const int ce0 = 2 * F0;               // first c_k entry (16-bit element index)
-    const int pe0 = 2 * (F0 + Cd);        // first copy ring entry
-    const int pmask = D.copy_p - 1;
-    for (int i = 0; i < Cd; ++i) M.st(F0 + i, 0u);
-    const int wu = S.W[u], wv = S.W[v];
-    for (int p = 0; p < N; ++p) {
-        int a = S.W[p];
-        a = (p == u) ? wv : a;
-        a = (p == v) ? wu : a;
-        int es = 0;
-        const int e1 = S.predoff[a + 1];
-        for (int e = S.predoff[a]; e < e1; ++e) es = max(es, M.ld16(S.pred[e]));
-        const int d = S.dur[a];
-        if (COUNT) w_ops += 1 + (e1 - S.predoff[a]);
-        int esr = 0;
-        for (int k = 0; k < Mr; ++k) {
-            const int r = S.reqk[a * Mr + k];
-            if (r > 0) {
-                esr = max(esr, M.ld16(ce0 + (int)S.res[2 * k + 1] + (int)S.res[2 * k] - r));
-                if (COUNT) ++w_ops;
-            }
-        }
-        const int s = max(es, esr);
-        if (d > 0) {
-            for (int k = 0; k < Mr; ++k) {
-                const int r = S.reqk[a * Mr + k];
-                if (r == 0) continue;
-                const int cb = ce0 + (int)S.res[2 * k + 1], Rk = (int)S.res[2 * k];
-                int effort = r * d, ri = 0, ci = 0, newTime = s + d;
-                while (effort > 0 && ri < Rk) {
-                    if (COUNT) ++w_ops;
-                    const int cv = M.ld16(cb + ri);
-                    if (cv < newTime) {
-                        if (ci >= r) newTime = M.ld16(pe0 + ((ci - r) & pmask));
-                        const int td = newTime - max(cv, s);
-                        if (effort - td > 0) {
-                            effort -= td;
-                            M.st16(pe0 + (ci & pmask), cv);
-                            ++ci;
-                            M.st16(cb + ri, newTime);
-                        } else {
-                            M.st16(cb + ri, max(cv, s) + effort);
-                            effort = 0;
-                        }
-                    }
-                    ++ri;
-                }
-            }
-        }
-        M.st16(a, s + d);
-    }
-    if (COUNT) *wk += w_ops;
-    return M.ld16(N - 1);
-}
-
-// One thread decodes W (no swap) using the whole decode region as its
-// private storage (stride 1): the time-indexed profile then spans long_len
-// >= horizon time units.
-template <int NW, int DEC, bool COUNT = false>
-__device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int u, int v,
-                           long long *wk = nullptr) {
-    if (DEC == kEvalTime) {
-        bool ovf = false;
-        return decode_ti<NW, 1, COUNT>(S, D, S.region, Ly.long_len, u, v, ovf, wk);
-    }
-    return decode_ci<1, COUNT>(S, D, S.region, u, v, wk);
-}
-
 // Key of a decoded move: non-admissible moves sort after admissible ones,
 // then (C_max, u, v) lexicographically.
 __device__ inline unsigned long long move_key(int c, int u, int v, bool tabu, int asp) {
@@ -394,6 +245,7 @@ struct TabuSrc {
     }
 };
 
+
 template <int T>
 __device__ inline long long block_sum_i64(long long x, unsigned long long *red) {
 #pragma unroll
@@ -410,31 +262,312 @@ __device__ inline long long block_sum_i64(long long x, unsigned long long *red) 
     return x;
 }
 
+
+// ---------------------------------------------------------------------------
+// Schedule decoders (Section 5).  The candidate order is W with positions u
+// and v exchanged (u = v = 0 decodes W itself).  Finish times s_a + d_a are
+// kept per activity; C_max is the finish time of the end dummy N-1.
+//
+// A decode covers positions [p0, p1) and continues from the state the caller
+// holds for positions [0, p0) (finish times, resource state, `front`).  All
+// candidates of one round share the prefix of W before their smallest u, so
+// that prefix is decoded once (Alg. 7 places activities in list order, and
+// the state after a list prefix depends on that prefix only).
+
+// es_prec: the latest finish time among the predecessors (two reads in flight).
+template <int STRIDE>
+__device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int po, int np) {
+    int es = 0;
+    for (int e = 0; e < np; e += 2) {
+        const int j0 = S.pred[po + e];
+        const int j1 = (e + 1 < np) ? S.pred[po + e + 1] : j0;
+        es = max(es, max(M.ld16(j0), M.ld16(j1)));
+    }
+    return es;
+}
+
+// Time-indexed: Alg. 5 scans for the first d consecutive time units at or
+// after es_prec with enough capacity on every resource; Alg. 6 subtracts the
+// requests over [s, s+d).  Only the first L time units are held (the lane's
+// storage has L+4 so the scan may read four units at a time); a candidate
+// whose schedule would pass L reports overflow and is decoded again with a
+// longer profile.  Time units at or beyond `front` have never been written and
+// hold the full capacity, so a scan that reaches `front` ends there.
+// With COUNT, *wk receives the decode's algorithmic operations: one per
+// activity, one per predecessor read, one per time unit examined by Alg. 5
+// and one per time unit updated by Alg. 6 (d of each for an activity that
+// requests nothing).
+template <int NW, int STRIDE, bool COUNT = false>
+__device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, int L, int u, int v, int p0, int p1,
+                         int &front, bool &ovf, long long *wk = nullptr) {
+    LaneMem<STRIDE> M{lane_base};
+    const int F0 = (D.n + 1) >> 1;
+    uint32_t G[NW], FULL[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        G[w] = D.guard[w];
+        FULL[w] = D.full[w];
+    }
+    const uint2 *rec = reinterpret_cast<const uint2 *>(S.prec);
+    long long w_ops = 0;
+    int fr = front;
+    for (int p = p0; p < p1; ++p) {
+        const int q = (p == u) ? v : ((p == v) ? u : p);
+        const uint2 r = rec[q];
+        uint32_t rq[NW];
+        uint32_t any = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            rq[w] = S.prq[q * NW + w];
+            any |= rq[w];
+        }
+        const int a = r.x & 0xffff, d = r.x >> 16, po = r.y & 0xffff, np = r.y >> 16;
+        const int es = prec_earliest<STRIDE>(S, M, po, np);
+        if (COUNT) w_ops += 1 + np;
+        int s = es;
+        if (any != 0 && d > 0) {
+            int t = es, run = 0;
+            s = -1;
+            while (t < fr) {
+                uint32_t A[4][NW];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) A[k][w] = M.ld(F0 + (t + k) * NW + w);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    bool ok = true;
+                    if (t + k < fr) {
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) ok = ok && ((((A[k][w] | G[w]) - rq[w]) & G[w]) == G[w]);
+                    }
+                    run = ok ? run + 1 : 0;
+                    if (run == d) {
+                        s = t + k + 1 - d;
+                        break;
+                    }
+                }
+                if (s >= 0) break;
+                t += 4;
+            }
+            if (s < 0) s = t - run;  // reached the frontier: all later units are free
+            if (s + d > L) {
+                ovf = true;
+                return -1;
+            }
+            if (COUNT) w_ops += (s + d - es) + d;
+            for (int x = fr; x < s; ++x) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) M.st(F0 + x * NW + w, FULL[w]);
+            }
+            for (int x = s; x < s + d; x += 2) {
+                uint32_t A0[NW], A1[NW];
+                const bool two = x + 1 < s + d;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    A0[w] = (x < fr) ? M.ld(F0 + x * NW + w) : FULL[w];
+                    A1[w] = (x + 1 < fr) ? M.ld(F0 + (x + 1) * NW + w) : FULL[w];
+                }
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    M.st(F0 + x * NW + w, A0[w] - rq[w]);
+                    if (two) M.st(F0 + (x + 1) * NW + w, A1[w] - rq[w]);
+                }
+            }
+            fr = max(fr, s + d);
+        } else if (COUNT) {
+            w_ops += 2 * d;
+        }
+        M.st16(a, s + d);
+    }
+    front = fr;
+    if (COUNT) *wk += w_ops;
+    return p1 == D.n ? M.ld16(D.n - 1) : 0;
+}
+
+// Capacity-indexed: eq. 7 gives the resource earliest start, Alg. 4 updates
+// each c_k.  c_k holds R_k 16-bit times; Alg. 4's auxiliary copy array is
+// only read r_ik entries behind its write position, so a ring of copy_p
+// (a power of two >= every request) entries replaces it.  Alg. 4 does
+// nothing but advance its index while c_k[i] >= s + d; because c_k stays
+// non-increasing (s is never below the eq. 7 start), those leading steps are
+// skipped by a binary search for the first entry below s + d.
+// With COUNT, *wk receives one operation per activity, per predecessor read,
+// per eq. 7 lookup and per Alg. 4 loop step (skipped steps included).
+template <int STRIDE, bool COUNT = false>
+__device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, int u, int v, int p0, int p1,
+                         long long *wk = nullptr) {
+    LaneMem<STRIDE> M{lane_base};
+    const int Mr = D.m;
+    const int F0 = (D.n + 1) >> 1;
+    const int Cd = (D.sum_r + 1) >> 1;
+    const int ce0 = 2 * F0;               // first c_k entry (16-bit element index)
+    const int pe0 = 2 * (F0 + Cd);        // first copy ring entry
+    const int pmask = D.copy_p - 1;
+    const uint2 *rec = reinterpret_cast<const uint2 *>(S.prec);
+    long long w_ops = 0;
+    for (int p = p0; p < p1; ++p) {
+        const int q = (p == u) ? v : ((p == v) ? u : p);
+        const uint2 r = rec[q];
+        const int a = r.x & 0xffff, d = r.x >> 16, po = r.y & 0xffff, np = r.y >> 16;
+        const int es = prec_earliest<STRIDE>(S, M, po, np);
+        if (COUNT) w_ops += 1 + np;
+        int esr = 0;
+        for (int k = 0; k < Mr; ++k) {
+            const int rk = S.reqk[a * Mr + k];
+            if (rk > 0) {
+                esr = max(esr, M.ld16(ce0 + (int)S.res[2 * k + 1] + (int)S.res[2 * k] - rk));
+                if (COUNT) ++w_ops;
+            }
+        }
+        const int s = max(es, esr);
+        if (d > 0) {
+            for (int k = 0; k < Mr; ++k) {
+                const int rk = S.reqk[a * Mr + k];
+                if (rk == 0) continue;
+                const int cb = ce0 + (int)S.res[2 * k + 1], Rk = (int)S.res[2 * k];
+                int effort = rk * d, ci = 0, newTime = s + d;
+                int lo = 0, hi = Rk;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (M.ld16(cb + mid) < newTime) hi = mid;
+                    else lo = mid + 1;
+                }
+                int ri = lo;
+                if (COUNT) w_ops += lo;
+                while (effort > 0 && ri < Rk) {
+                    if (COUNT) ++w_ops;
+                    const int cv = M.ld16(cb + ri);
+                    if (cv < newTime) {
+                        if (ci >= rk) newTime = M.ld16(pe0 + ((ci - rk) & pmask));
+                        const int td = newTime - max(cv, s);
+                        if (effort - td > 0) {
+                            effort -= td;
+                            M.st16(pe0 + (ci & pmask), cv);
+                            ++ci;
+                            M.st16(cb + ri, newTime);
+                        } else {
+                            M.st16(cb + ri, max(cv, s) + effort);
+                            effort = 0;
+                        }
+                    }
+                    ++ri;
+                }
+            }
+        }
+        M.st16(a, s + d);
+    }
+    if (COUNT) *wk += w_ops;
+    return p1 == D.n ? M.ld16(D.n - 1) : 0;
+}
+
+// Fresh decoder state: capacity-indexed arrays start at zero; the
+// time-indexed profile needs nothing (front = 0).
+template <int DEC, int STRIDE>
+__device__ inline void init_state(const InstDesc &D, uint32_t *lane_base) {
+    if (DEC == kEvalCapacity) {
+        LaneMem<STRIDE> M{lane_base};
+        const int F0 = (D.n + 1) >> 1, Cd = (D.sum_r + 1) >> 1;
+        for (int i = 0; i < Cd; ++i) M.st(F0 + i, 0u);
+    }
+}
+
+// Copy a state (finish times + resource state up to `front`) from a
+// stride-1 area into a lane's storage.
+template <int NW, int DEC, int STRIDE>
+__device__ inline void copy_state(const InstDesc &D, const uint32_t *src, uint32_t *lane_base, int front) {
+    LaneMem<STRIDE> M{lane_base};
+    const int F0 = (D.n + 1) >> 1;
+    const int n = F0 + (DEC == kEvalCapacity ? (D.sum_r + 1) >> 1 : front * NW);
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(src + i);
+        M.st(i, x.x);
+        M.st(i + 1, x.y);
+        M.st(i + 2, x.z);
+        M.st(i + 3, x.w);
+    }
+    for (; i < n; ++i) M.st(i, src[i]);
+}
+
+// One thread decodes W with positions u, v exchanged from scratch, using the
+// whole decode region as its private storage (stride 1): the time-indexed
+// profile then spans long_len >= horizon time units.
+template <int NW, int DEC, bool COUNT = false>
+__device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int u, int v,
+                           long long *wk = nullptr) {
+    init_state<DEC, 1>(D, S.region);
+    if (DEC == kEvalTime) {
+        bool ovf = false;
+        int front = 0;
+        return decode_ti<NW, 1, COUNT>(S, D, S.region, Ly.long_len, u, v, 0, D.n, front, ovf, wk);
+    }
+    return decode_ci<1, COUNT>(S, D, S.region, u, v, 0, D.n, wk);
+}
+
 // Decode every feasible move; return the workgroup's minimum key.
 // out_mk (global, canonical index) receives every makespan when non-null.
-// With COUNT, thread 0 adds the algorithmic operations of all decodes to
-// *work_total (a lane's aborted short-profile decode is not counted).
+//
+// Lanes take the moves in canonical order, T per round.  Before a round,
+// thread 0 extends the decode of W itself (no swap) in the shared base area
+// up to the round's smallest u; every lane copies that state and decodes its
+// candidate from there.  If W's own schedule passes the lane profile length,
+// lanes decode from scratch instead.  Candidates that overflow the lane
+// profile are decoded afterwards by one thread with the long profile.
+// With COUNT every candidate is decoded from scratch and thread 0 adds the
+// algorithmic operations of all decodes to *work_total (a lane's aborted
+// short-profile decode is not counted).
 template <int NW, int T, int DEC, bool COUNT = false>
 __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
                                              int L, int delta, TabuSrc tabu, int asp, int *out_mk,
-                                             long long *ovf_total, long long *work_total = nullptr) {
+                                             long long *ovf_total, long long *work_total = nullptr,
+                                             bool share = true) {
     const int tid = threadIdx.x;
     unsigned long long best = ~0ull;
     long long lw = 0;
-    int *ovf_n = S.scal;
-    if (tid == 0) *ovf_n = 0;
+    int *ovf_n = S.scal;          // overflowed candidates
+    int *bstate = S.scal + 1;     // base decode: positions done, front, overflowed
+    const bool use_base = share && !COUNT;
+    if (tid == 0) {
+        *ovf_n = 0;
+        bstate[0] = 0;
+        bstate[1] = 0;
+        bstate[2] = 0;
+    }
+    if (use_base && tid == 0) init_state<DEC, 1>(D, S.bst);
     __syncthreads();
     uint32_t *lane_base = S.region + tid;
     for (int j0 = 0; j0 < nfeas; j0 += T) {
+        if (use_base) {
+            const int ulo = S.moves[j0] & 0xffff;
+            if (tid == 0 && !bstate[2] && bstate[0] < ulo) {
+                bool bovf = false;
+                int bf = bstate[1];
+                if (DEC == kEvalTime) decode_ti<NW, 1>(S, D, S.bst, L, 0, 0, bstate[0], ulo, bf, bovf);
+                else decode_ci<1>(S, D, S.bst, 0, 0, bstate[0], ulo);
+                bstate[0] = ulo;
+                bstate[1] = bf;
+                bstate[2] = bovf ? 1 : 0;
+            }
+            __syncthreads();
+        }
         const int j = j0 + tid;
         if (j < nfeas) {
             const uint32_t mv = S.moves[j];
             const int u = mv & 0xffff, v = mv >> 16;
+            int p0 = 0, front = 0;
+            if (use_base && !bstate[2]) {
+                p0 = bstate[0];
+                front = bstate[1];
+                copy_state<NW, DEC, T>(D, S.bst, lane_base, front);
+            } else {
+                init_state<DEC, T>(D, lane_base);
+            }
             bool ovf = false;
             int c;
             long long cw = 0;
-            if (DEC == kEvalTime) c = decode_ti<NW, T, COUNT>(S, D, lane_base, L, u, v, ovf, &cw);
-            else c = decode_ci<T, COUNT>(S, D, lane_base, u, v, &cw);
+            if (DEC == kEvalTime) c = decode_ti<NW, T, COUNT>(S, D, lane_base, L, u, v, p0, D.n, front, ovf, &cw);
+            else c = decode_ci<T, COUNT>(S, D, lane_base, u, v, p0, D.n, &cw);
             if (COUNT && !ovf) lw += cw;
             if (ovf) {
                 S.moves[j] = mv | 0x80000000u;
@@ -445,6 +578,7 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
                 if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
             }
         }
+        if (use_base) __syncthreads();
     }
     __syncthreads();
     if (DEC == kEvalTime) {
@@ -479,7 +613,7 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
 
 template <int NW, int T, int DEC>
 __global__ __launch_bounds__(T) void k_eval(EvalArgs A) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const InstDesc &D = A.D;
     const Layout &Ly = A.Ly;
     Sh S = make_sh(lds, D, Ly);
@@ -604,13 +738,15 @@ __global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
 // Makespan of every initial working-set record (buffer 0).
 template <int NW, int T, int DEC>
 __global__ __launch_bounds__(T) void k_decode_records(SearchArgs A) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const InstDesc &D = A.D;
     Sh S = make_sh(lds, D, A.Ly);
     const int k = blockIdx.x, N2 = n2(D.n);
     stage_blob<T>(lds, D, A.Ly);
     const uint32_t *src = reinterpret_cast<const uint32_t *>(A.Fw + (size_t)k * N2);
     for (int i = threadIdx.x; i < N2 / 2; i += T) reinterpret_cast<uint32_t *>(S.W)[i] = src[i];
+    __syncthreads();
+    build_records<T>(S, D);
     __syncthreads();
     if (threadIdx.x == 0) A.Fmeta[k].C = decode_long<NW, DEC>(S, D, A.Ly, 0, 0);
 }
@@ -624,7 +760,7 @@ __device__ inline void copy_dw(uint32_t *dst, const uint32_t *src, int n) {
 // algorithmic operations of every decode to the search's work counter.
 template <int NW, int T, int DEC, bool COUNT>
 __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ SearchScalars sc;
     __shared__ int dirty_best, dirty_imp;
     const InstDesc &D = A.D;
@@ -689,6 +825,8 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
                 }
                 __syncthreads();
             }
+            build_records<T>(S, D);
+            __syncthreads();
             if (tid == 0) sc.C_cur = decode_long<NW, DEC>(S, D, Ly, 0, 0);
         }
         __syncthreads();
@@ -710,6 +848,8 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
                              reinterpret_cast<const uint32_t *>(A.Wimp + (size_t)b * N2), N2 / 2);
         __syncthreads();
         if (flags0 & kFlagInitDecode) {
+            build_records<T>(S, D);
+            __syncthreads();
             if (tid == 0) {
                 sc.C_cur = decode_long<NW, DEC>(S, D, Ly, 0, 0);
                 sc.C_best = sc.C_cur;
@@ -740,7 +880,8 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
             break;
         }
         const unsigned long long key =
-            evaluate_moves<NW, T, DEC, COUNT>(S, D, Ly, nf, A.L, A.delta, tb, asp, nullptr, &sc.overflow, &sc.work);
+            evaluate_moves<NW, T, DEC, COUNT>(S, D, Ly, nf, A.L, A.delta, tb, asp, nullptr, &sc.overflow, &sc.work,
+                                              !A.full_decode);
         if (tid == 0) {
             const int u = (int)((key >> 16) & 0xffff), v = (int)(key & 0xffff);
             const int c = (int)((key >> 32) & 0x7fffffff);

@@ -44,7 +44,7 @@ class rcpsp_move(ctypes.Structure):
 class rcpsp_search_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
-        "profile_len", "record_trajectory", "count_work")] + [("seed", ctypes.c_uint64)]
+        "profile_len", "record_trajectory", "count_work", "full_decode")] + [("seed", ctypes.c_uint64)]
 
 
 class rcpsp_search_result(ctypes.Structure):
@@ -189,9 +189,10 @@ class Instance:
 
 def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                   phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
-                  record_trajectory: bool = True, count_work: bool = False, seed: int = 1) -> rcpsp_search_params:
+                  record_trajectory: bool = True, count_work: bool = False, full_decode: bool = False,
+                  seed: int = 1) -> rcpsp_search_params:
     return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
-                               profile_len, int(record_trajectory), int(count_work), seed)
+                               profile_len, int(record_trajectory), int(count_work), int(full_decode), seed)
 
 
 class SearchPlan:
