@@ -362,8 +362,10 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     Ly.ring = o; o += tl;
     Ly.moves = o; o += std::max(pmax, 1);
     o = (o + 1) & ~1;
-    Ly.prec = o; o += 2 * D.n;
+    o = (o + 3) & ~3;
+    Ly.prec = o; o += 4 * D.n;
     Ly.prq = o; o += D.n * std::max(D.nw, 1);
+    Ly.predT = o; o += std::max(D.n_arcs, 1);
     o = (o + 1) & ~1;
     Ly.red = o; o += 2 * (T / 64);
     Ly.scal = o; o += 4;

@@ -32,7 +32,7 @@ struct Sh {
     const uint32_t *rq, *res;
     uint16_t *W, *Wimp, *pos, *fs, *lp;
     int *cnt;
-    uint32_t *tc, *ring, *moves, *prec, *prq, *bst;
+    uint32_t *tc, *ring, *moves, *prec, *prq, *predT, *bst;
     unsigned long long *red;
     int *scal;
     uint32_t *region;
@@ -62,6 +62,7 @@ __device__ inline Sh make_sh(uint32_t *lds, const InstDesc &D, const Layout &Ly)
     s.moves = lds + Ly.moves;
     s.prec = lds + Ly.prec;
     s.prq = lds + Ly.prq;
+    s.predT = lds + Ly.predT;
     s.bst = lds + Ly.bst;
     s.red = reinterpret_cast<unsigned long long *>(lds + Ly.red);
     s.scal = reinterpret_cast<int *>(lds + Ly.scal);
@@ -86,7 +87,21 @@ struct LaneMem {
     __device__ inline void st16(int e, int v) const {
         reinterpret_cast<uint16_t *>(base + (e >> 1) * STRIDE)[e & 1] = (uint16_t)v;
     }
+    // 16-bit element at a precomputed byte offset from this lane's dword 0
+    __device__ inline int ld16b(uint32_t off) const {
+        return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(base) + off);
+    }
+    __device__ inline void st16b(uint32_t off, int v) const {
+        *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(base) + off) = (uint16_t)v;
+    }
 };
+
+// Byte offset of 16-bit element e of a lane's storage when lanes are
+// interleaved with the given dword stride (stride 1: a single thread).
+template <int STRIDE>
+__device__ inline uint32_t off16(int e) {
+    return (uint32_t)(((e >> 1) * STRIDE) << 2) + (uint32_t)((e & 1) << 1);
+}
 
 // ---------------------------------------------------------------------------
 // Random numbers: counter-based SplitMix64 (Steele, Lea & Flood 2014).
@@ -156,19 +171,26 @@ __device__ inline unsigned long long block_min_u64(unsigned long long x, unsigne
 // ---------------------------------------------------------------------------
 // Neighbourhood (Sections 4.2-4.4)
 
-// Per-position records of the current order W:
-//   prec[2p] = w_p | d << 16, prec[2p+1] = first predecessor index | count << 16,
-//   prq[p*NW + w] = packed requests of w_p (time-indexed profile words).
+// Per-position records of the current order W, one 16-byte load each:
+//   prec[4p..4p+3] = (byte offset of f[w_p] in a lane's storage, d | npred << 16,
+//                     first predecessor index, w_p),
+//   prq[p*NW + w]  = packed requests of w_p (time-indexed profile words),
+//   predT[e]       = byte offset of f[pred[e]] in a lane's storage.
 template <int T>
 __device__ inline void build_records(const Sh &S, const InstDesc &D) {
     const int N = D.n, NW = D.nw;
     for (int p = threadIdx.x; p < N; p += T) {
         const int a = S.W[p];
         const int po = S.predoff[a];
-        S.prec[2 * p] = (uint32_t)a | ((uint32_t)S.dur[a] << 16);
-        S.prec[2 * p + 1] = (uint32_t)po | ((uint32_t)(S.predoff[a + 1] - po) << 16);
+        uint4 r;
+        r.x = off16<T>(a);
+        r.y = (uint32_t)S.dur[a] | ((uint32_t)(S.predoff[a + 1] - po) << 16);
+        r.z = (uint32_t)po;
+        r.w = (uint32_t)a;
+        reinterpret_cast<uint4 *>(S.prec)[p] = r;
         for (int w = 0; w < NW; ++w) S.prq[p * NW + w] = S.rq[a * NW + w];
     }
+    for (int e = threadIdx.x; e < D.n_arcs; e += T) S.predT[e] = off16<T>(S.pred[e]);
 }
 
 // Position of the first successor / last predecessor of each w_p, then the
@@ -274,14 +296,23 @@ __device__ inline long long block_sum_i64(long long x, unsigned long long *red) 
 // that prefix is decoded once (Alg. 7 places activities in list order, and
 // the state after a list prefix depends on that prefix only).
 
-// es_prec: the latest finish time among the predecessors (two reads in flight).
+// es_prec: the latest finish time among the predecessors (two reads in
+// flight).  Lane decodes read the precomputed offsets predT, single-thread
+// decodes (stride 1) the predecessor ids.
 template <int STRIDE>
 __device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int po, int np) {
     int es = 0;
     for (int e = 0; e < np; e += 2) {
-        const int j0 = S.pred[po + e];
-        const int j1 = (e + 1 < np) ? S.pred[po + e + 1] : j0;
-        es = max(es, max(M.ld16(j0), M.ld16(j1)));
+        const int e1 = (e + 1 < np) ? e + 1 : e;
+        uint32_t o0, o1;
+        if (STRIDE == 1) {
+            o0 = 2u * S.pred[po + e];
+            o1 = 2u * S.pred[po + e1];
+        } else {
+            o0 = S.predT[po + e];
+            o1 = S.predT[po + e1];
+        }
+        es = max(es, max(M.ld16b(o0), M.ld16b(o1)));
     }
     return es;
 }
@@ -292,7 +323,9 @@ __device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int p
 // storage has L+4 so the scan may read four units at a time); a candidate
 // whose schedule would pass L reports overflow and is decoded again with a
 // longer profile.  Time units at or beyond `front` have never been written and
-// hold the full capacity, so a scan that reaches `front` ends there.
+// hold the full capacity, so a scan that reaches `front` ends there.  Each
+// scan step tests four units with selects only, so their loads are in flight
+// together.
 // With COUNT, *wk receives the decode's algorithmic operations: one per
 // activity, one per predecessor read, one per time unit examined by Alg. 5
 // and one per time unit updated by Alg. 6 (d of each for an activity that
@@ -308,12 +341,13 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         G[w] = D.guard[w];
         FULL[w] = D.full[w];
     }
-    const uint2 *rec = reinterpret_cast<const uint2 *>(S.prec);
+    const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
+    uint32_t *prof = lane_base + F0 * STRIDE;   // time unit t, word w at prof[(t*NW + w)*STRIDE]
     long long w_ops = 0;
     int fr = front;
     for (int p = p0; p < p1; ++p) {
         const int q = (p == u) ? v : ((p == v) ? u : p);
-        const uint2 r = rec[q];
+        const uint4 r = rec[q];
         uint32_t rq[NW];
         uint32_t any = 0;
 #pragma unroll
@@ -321,33 +355,37 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
             rq[w] = S.prq[q * NW + w];
             any |= rq[w];
         }
-        const int a = r.x & 0xffff, d = r.x >> 16, po = r.y & 0xffff, np = r.y >> 16;
-        const int es = prec_earliest<STRIDE>(S, M, po, np);
+        const int d = r.y & 0xffff, np = r.y >> 16;
+        const uint32_t fo = (STRIDE == 1) ? 2u * r.w : r.x;
+        const int es = prec_earliest<STRIDE>(S, M, (int)r.z, np);
         if (COUNT) w_ops += 1 + np;
         int s = es;
         if (any != 0 && d > 0) {
             int t = es, run = 0;
             s = -1;
-            while (t < fr) {
-                uint32_t A[4][NW];
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) A[k][w] = M.ld(F0 + (t + k) * NW + w);
+            while (s < 0 && t < fr) {
+                const uint32_t *P = prof + t * NW * STRIDE;
+                bool ok[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    bool ok = true;
-                    if (t + k < fr) {
+                    bool o = true;
 #pragma unroll
-                        for (int w = 0; w < NW; ++w) ok = ok && ((((A[k][w] | G[w]) - rq[w]) & G[w]) == G[w]);
+                    for (int w = 0; w < NW; ++w) {
+                        const uint32_t A = P[(k * NW + w) * STRIDE];
+                        o = o && ((((A | G[w]) - rq[w]) & G[w]) == G[w]);
                     }
-                    run = ok ? run + 1 : 0;
-                    if (run == d) {
-                        s = t + k + 1 - d;
-                        break;
-                    }
+                    ok[k] = o || (t + k >= fr);
                 }
-                if (s >= 0) break;
+                const int r0 = ok[0] ? run + 1 : 0;
+                const int r1 = ok[1] ? r0 + 1 : 0;
+                const int r2 = ok[2] ? r1 + 1 : 0;
+                const int r3 = ok[3] ? r2 + 1 : 0;
+                // earliest unit where the run reaches d (selects, no branches)
+                s = (r3 == d) ? t + 4 - d : -1;
+                s = (r2 == d) ? t + 3 - d : s;
+                s = (r1 == d) ? t + 2 - d : s;
+                s = (r0 == d) ? t + 1 - d : s;
+                run = r3;
                 t += 4;
             }
             if (s < 0) s = t - run;  // reached the frontier: all later units are free
@@ -358,27 +396,27 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
             if (COUNT) w_ops += (s + d - es) + d;
             for (int x = fr; x < s; ++x) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) M.st(F0 + x * NW + w, FULL[w]);
+                for (int w = 0; w < NW; ++w) prof[(x * NW + w) * STRIDE] = FULL[w];
             }
             for (int x = s; x < s + d; x += 2) {
+                uint32_t *P = prof + x * NW * STRIDE;
                 uint32_t A0[NW], A1[NW];
-                const bool two = x + 1 < s + d;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    A0[w] = (x < fr) ? M.ld(F0 + x * NW + w) : FULL[w];
-                    A1[w] = (x + 1 < fr) ? M.ld(F0 + (x + 1) * NW + w) : FULL[w];
+                    A0[w] = P[w * STRIDE];
+                    A1[w] = P[(NW + w) * STRIDE];
                 }
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    M.st(F0 + x * NW + w, A0[w] - rq[w]);
-                    if (two) M.st(F0 + (x + 1) * NW + w, A1[w] - rq[w]);
+                    P[w * STRIDE] = ((x < fr) ? A0[w] : FULL[w]) - rq[w];
+                    if (x + 1 < s + d) P[(NW + w) * STRIDE] = ((x + 1 < fr) ? A1[w] : FULL[w]) - rq[w];
                 }
             }
             fr = max(fr, s + d);
         } else if (COUNT) {
             w_ops += 2 * d;
         }
-        M.st16(a, s + d);
+        M.st16b(fo, s + d);
     }
     front = fr;
     if (COUNT) *wk += w_ops;
@@ -404,13 +442,14 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
     const int ce0 = 2 * F0;               // first c_k entry (16-bit element index)
     const int pe0 = 2 * (F0 + Cd);        // first copy ring entry
     const int pmask = D.copy_p - 1;
-    const uint2 *rec = reinterpret_cast<const uint2 *>(S.prec);
+    const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
     long long w_ops = 0;
     for (int p = p0; p < p1; ++p) {
         const int q = (p == u) ? v : ((p == v) ? u : p);
-        const uint2 r = rec[q];
-        const int a = r.x & 0xffff, d = r.x >> 16, po = r.y & 0xffff, np = r.y >> 16;
-        const int es = prec_earliest<STRIDE>(S, M, po, np);
+        const uint4 r = rec[q];
+        const int d = r.y & 0xffff, np = r.y >> 16, a = (int)r.w;
+        const uint32_t fo = (STRIDE == 1) ? 2u * r.w : r.x;
+        const int es = prec_earliest<STRIDE>(S, M, (int)r.z, np);
         if (COUNT) w_ops += 1 + np;
         int esr = 0;
         for (int k = 0; k < Mr; ++k) {
@@ -455,7 +494,7 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 }
             }
         }
-        M.st16(a, s + d);
+        M.st16b(fo, s + d);
     }
     if (COUNT) *wk += w_ops;
     return p1 == D.n ? M.ld16(D.n - 1) : 0;
