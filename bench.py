@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--decoder", choices=["auto", "time", "capacity"], default="auto")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--profile-len", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--full-decode", action="store_true", help="decode every candidate from position 0")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the searches would shard across "
@@ -73,11 +75,21 @@ def main():
     dec_req = {"auto": rcpsp.EVAL_AUTO, "time": rcpsp.EVAL_TIME, "capacity": rcpsp.EVAL_CAPACITY}[args.decoder]
     gi = rcpsp.Instance(inst, eval=dec_req)
     info = gi.info
-    dec = info["eval"]
-    kw = dict(WORKLOAD, threads=args.threads, profile_len=args.profile_len)
+    kw = dict(WORKLOAD, threads=args.threads, profile_len=args.profile_len, full_decode=args.full_decode,
+              eval=dec_req)
+    params = rcpsp.search_params(record_trajectory=False, **kw)
+    tuning = None
+    if not args.no_tune:
+        # decoder and launch shape chosen per instance before the search (outside the timed region)
+        t0 = time.perf_counter()
+        params, tuning = rcpsp.autotune(gi, params, trial_iterations=10, stream=stream)
+        tuning["seconds"] = time.perf_counter() - t0
+        log("autotune", tuning)
+    kw.update(eval=params.eval, threads=params.threads, profile_len=params.profile_len)
 
-    plan = rcpsp.SearchPlan(gi, rcpsp.search_params(record_trajectory=False, **kw), stream)
+    plan = rcpsp.SearchPlan(gi, params, stream)
     cfg = plan.config
+    dec = cfg["eval"]
     log("plan", cfg, "info", info)
     for _ in range(args.warmup):
         plan.run(stream)
@@ -139,6 +151,8 @@ def main():
             "critical_path": cp,
             "cpm_dev_pct": 100.0 * (res["global_best"] - cp) / cp,
             "overflow_decodes_per_step": res["overflow_decodes"],
+            "prefix_reuse": not args.full_decode,
+            "autotune": tuning,
         },
         "roofline": {
             "bound": "alu",

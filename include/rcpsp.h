@@ -59,8 +59,8 @@ typedef struct rcpsp_instance rcpsp_instance;
  *   succ_off   [N+1]  successor lists in CSR form (Table 1 "Successors")
  *   succ       [succ_off[N]] successor ids
  *   eval       decoder; AUTO resolves it from the instance attributes of
- *              Table tab:attr (see rcpsp_instance_info) and may later be
- *              replaced by rcpsp_autotune
+ *              Table tab:attr (see rcpsp_instance_info); a search may
+ *              override it (rcpsp_search_params.eval, rcpsp_autotune)
  *   out        receives the instance (library-owned; free with
  *              rcpsp_destroy_instance)
  * The instance is validated (errors above), derived data is computed on the
@@ -144,6 +144,8 @@ typedef struct {
     int32_t full_decode;      /* 1 = decode every candidate from its first position
                                  instead of continuing from the schedule prefix it
                                  shares with the current order (same results) */
+    int32_t eval;             /* decoder for this search: 0 = the instance's,
+                                 1 time-indexed, 2 capacity-indexed */
     uint64_t seed;            /* seeds the initial orders and diversification */
 } rcpsp_search_params;
 
@@ -198,6 +200,26 @@ typedef struct {
     int32_t iteration_launches, round_launches;
 } rcpsp_search_config;
 rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out);
+
+/* Decoder and launch shape for one instance and search configuration.
+ * Section 5.4 fixes the resource evaluation algorithm per instance before the
+ * search, with rules that were learnt by timing both algorithms for a few
+ * iterations; this entry point does that timing directly: it runs the search
+ * described by params for trial_iterations iterations with every candidate
+ * (decoder x threads per search x profile length) and keeps the one with the
+ * least device time per evaluation.  *out receives params with eval, threads
+ * and profile_len filled in; *info (may be NULL) the choice and its cost.
+ * The decoder changes the schedules and so the search, so the choice is made
+ * once, before the search, and is part of the result's identity.
+ * Synchronous; allocates and frees its own trial plans. */
+typedef struct {
+    int32_t eval, threads, profile_len;
+    int32_t trials;           /* candidates timed */
+    double ns_per_evaluation; /* of the chosen candidate */
+} rcpsp_tuning;
+rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                            int32_t trial_iterations, void *hip_stream, rcpsp_search_params *out,
+                            rcpsp_tuning *info);
 
 const char *rcpsp_last_error(void);
 const char *rcpsp_version(void);

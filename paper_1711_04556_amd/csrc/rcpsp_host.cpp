@@ -384,11 +384,15 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     return Ly;
 }
 
-// Choose the per-lane time-indexed profile length: twice the critical path
-// plus two longest durations (makespans of the neighbourhood rarely exceed
-// it; longer schedules take the exact long-profile path), at least long
-// enough that the whole region holds one profile of the full horizon, and
-// within the LDS budget.
+// Workgroups of `bytes` LDS that fit on one CU.
+static int lds_occupancy(size_t bytes) { return (int)(kMaxLds / (bytes + 256)); }
+
+// Per-lane time-indexed profile length.  Without a request: at least
+// 1.4 x the critical path plus two longest durations (neighbourhood
+// makespans rarely pass it; longer schedules take the exact long-profile
+// path), then as long as possible without lowering the number of
+// workgroups per CU, never beyond the horizon.  The whole region must also
+// hold one profile of the full horizon for the long-profile decode.
 static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw, int tl, int pmax, int L_req,
                                 int *L_out, Layout *Ly_out) {
     const InstDesc &D = I->desc;
@@ -401,23 +405,37 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
         *Ly_out = Ly;
         return RCPSP_OK;
     }
-    int L = L_req > 0 ? L_req : std::min(I->H, ((2 * I->cp + 2 * I->dmax + 15) / 16) * 16);
-    L = std::max(1, std::min(L, std::max(I->H, 1)));
-    for (;;) {
-        Layout Ly = make_layout(D, T, tcw, tl, pmax, L, dec);
-        if (Ly.long_len < I->H) {
-            ++L;
-            continue;
-        }
-        if ((size_t)Ly.total * 4 <= (size_t)budget) {
-            *L_out = L;
-            *Ly_out = Ly;
-            return RCPSP_OK;
-        }
-        if (L_req > 0 || L <= 16)
+    const int H = std::max(I->H, 1);
+    auto fits = [&](int L, Layout *Ly) {
+        *Ly = make_layout(D, T, tcw, tl, pmax, L, dec);
+        return Ly->long_len >= I->H && (size_t)Ly->total * 4 <= (size_t)budget;
+    };
+    Layout Ly;
+    if (L_req > 0) {
+        int L = std::min(L_req, H);
+        while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec).long_len < I->H) ++L;
+        if (!fits(L, &Ly))
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
+        *L_out = L;
+        *Ly_out = Ly;
+        return RCPSP_OK;
+    }
+    int L = std::min(H, ((14 * I->cp + 9) / 10 + 2 * I->dmax + 15) / 16 * 16);
+    L = std::max(L, 1);
+    while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec).long_len < I->H) ++L;
+    while (!fits(L, &Ly)) {
+        if (L <= 16) return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
         L = std::max(16, L * 3 / 4);
     }
+    const int k0 = lds_occupancy((size_t)Ly.total * 4);
+    Layout Ln;
+    while (L + 4 <= H && fits(L + 4, &Ln) && lds_occupancy((size_t)Ln.total * 4) >= k0) {
+        L += 4;
+        Ly = Ln;
+    }
+    *L_out = L;
+    *Ly_out = Ly;
+    return RCPSP_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -634,8 +652,10 @@ static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     const rcpsp_instance *I = s->inst;
     const rcpsp_search_params &p = s->p;
     const int N = I->n, N2 = n2(N), B = p.searches, NF = p.elite;
-    s->dec = I->eval;
+    s->dec = p.eval ? p.eval : I->eval;
     s->nw = I->desc.nw;
+    if (s->dec == kEvalTime && s->nw == 0)
+        return fail(RCPSP_E_TOO_LARGE, "time-indexed profile needs more than %d dwords per time unit", kMaxNW);
     s->tcw = (p.swap_range + 31) / 32;
     s->P = potential_moves(N, p.swap_range);
     int T = p.threads;
@@ -742,6 +762,7 @@ extern "C" rcpsp_status rcpsp_search_create(const rcpsp_instance *inst, const rc
     if (p.searches < 1) return fail(RCPSP_E_ARG, "searches must be >= 1");
     if (p.elite < 0) return fail(RCPSP_E_ARG, "elite must be >= 0");
     if (p.phi_max < 0 || p.phi_steps < 0) return fail(RCPSP_E_ARG, "phi_max and phi_steps must be >= 0");
+    if (p.eval < 0 || p.eval > 2) return fail(RCPSP_E_ARG, "unknown decoder %d", p.eval);
     if ((long long)p.searches * std::max(p.iterations, 1) * 4 > (1ll << 40))
         return fail(RCPSP_E_TOO_LARGE, "trajectory too large");
     rcpsp_search *s = new (std::nothrow) rcpsp_search();
@@ -859,4 +880,83 @@ extern "C" rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcps
     if (st == RCPSP_OK) st = rcpsp_search_results(s, res, hip_stream);
     rcpsp_search_destroy(s);
     return st;
+}
+
+extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                      int32_t trial_iterations, void *hip_stream, rcpsp_search_params *out,
+                                      rcpsp_tuning *info) {
+    if (!inst || !params || !out) return fail(RCPSP_E_ARG, "null pointer");
+    if (trial_iterations < 1) return fail(RCPSP_E_ARG, "trial_iterations must be >= 1");
+    std::vector<int> evals;
+    if (params->eval) evals.push_back(params->eval);
+    else {
+        if (inst->desc.nw) evals.push_back(kEvalTime);
+        evals.push_back(kEvalCapacity);
+    }
+    std::vector<int> threads;
+    if (params->threads) threads.push_back(params->threads);
+    else {
+        threads.push_back(64);
+        threads.push_back(128);
+        if (params->searches < 128) threads.push_back(256);
+    }
+    // profile lengths: the automatic choice, and a shorter one that may fit
+    // more workgroups per CU at the price of more long-profile decodes
+    const int Lshort = std::min(inst->H, ((6 * inst->cp + 4) / 5 + 2 * inst->dmax + 15) / 16 * 16);
+    bool found = false;
+    double best_ns = 0.0;
+    rcpsp_search_params best{};
+    int trials = 0;
+    for (int ev : evals) {
+        for (int T : threads) {
+            std::vector<int> Ls;
+            if (ev == kEvalTime && !params->profile_len) {
+                Ls.push_back(0);
+                Ls.push_back(std::max(Lshort, 16));
+            } else {
+                Ls.push_back(params->profile_len);
+            }
+            for (int L : Ls) {
+                rcpsp_search_params q = *params;
+                q.eval = ev;
+                q.threads = T;
+                q.profile_len = L;
+                q.iterations = trial_iterations;
+                q.record_trajectory = 0;
+                q.count_work = 0;
+                rcpsp_search *s = nullptr;
+                rcpsp_status st = rcpsp_search_create(inst, &q, hip_stream, &s);
+                if (st == RCPSP_E_TOO_LARGE) continue;
+                if (st != RCPSP_OK) return st;
+                double ms = 0.0;
+                rcpsp_search_result r{};
+                st = rcpsp_search_run(s, hip_stream);
+                if (st == RCPSP_OK) st = rcpsp_search_run_timed(s, hip_stream, nullptr, nullptr, &ms);
+                if (st == RCPSP_OK) st = rcpsp_search_results(s, &r, hip_stream);
+                const int Lused = s->L;
+                rcpsp_search_destroy(s);
+                if (st != RCPSP_OK) return st;
+                ++trials;
+                const double ns = r.total_evaluations > 0 ? ms * 1e6 / (double)r.total_evaluations : ms * 1e6;
+                if (!found || ns < best_ns) {
+                    found = true;
+                    best_ns = ns;
+                    best = *params;
+                    best.eval = ev;
+                    best.threads = T;
+                    best.profile_len = ev == kEvalTime ? Lused : 0;
+                }
+            }
+        }
+    }
+    if (!found) return fail(RCPSP_E_TOO_LARGE, "no decoder/launch shape fits this instance");
+    *out = best;
+    if (info) {
+        info->eval = best.eval;
+        info->threads = best.threads;
+        info->profile_len = best.profile_len;
+        info->trials = trials;
+        info->ns_per_evaluation = best_ns;
+    }
+    return RCPSP_OK;
 }

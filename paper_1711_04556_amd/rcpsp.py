@@ -44,7 +44,12 @@ class rcpsp_move(ctypes.Structure):
 class rcpsp_search_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
-        "profile_len", "record_trajectory", "count_work", "full_decode")] + [("seed", ctypes.c_uint64)]
+        "profile_len", "record_trajectory", "count_work", "full_decode", "eval")] + [("seed", ctypes.c_uint64)]
+
+
+class rcpsp_tuning(ctypes.Structure):
+    _fields_ = [("eval", ctypes.c_int32), ("threads", ctypes.c_int32), ("profile_len", ctypes.c_int32),
+                ("trials", ctypes.c_int32), ("ns_per_evaluation", ctypes.c_double)]
 
 
 class rcpsp_search_result(ctypes.Structure):
@@ -102,6 +107,9 @@ def lib():
     L.rcpsp_search_get_config.restype = ctypes.c_int
     L.rcpsp_tabu_search.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), ctypes.POINTER(rcpsp_search_result), vp]
     L.rcpsp_tabu_search.restype = ctypes.c_int
+    L.rcpsp_autotune.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), i32, vp, ctypes.POINTER(rcpsp_search_params),
+                                 ctypes.POINTER(rcpsp_tuning)]
+    L.rcpsp_autotune.restype = ctypes.c_int
     L.rcpsp_last_error.argtypes = []
     L.rcpsp_last_error.restype = ctypes.c_char_p
     L.rcpsp_version.argtypes = []
@@ -190,9 +198,18 @@ class Instance:
 def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                   phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
                   record_trajectory: bool = True, count_work: bool = False, full_decode: bool = False,
-                  seed: int = 1) -> rcpsp_search_params:
+                  eval: int = EVAL_AUTO, seed: int = 1) -> rcpsp_search_params:
     return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
-                               profile_len, int(record_trajectory), int(count_work), int(full_decode), seed)
+                               profile_len, int(record_trajectory), int(count_work), int(full_decode), eval, seed)
+
+
+def autotune(instance: "Instance", params: rcpsp_search_params, trial_iterations: int = 10, stream=None):
+    """rcpsp_autotune: returns (params with eval/threads/profile_len chosen, tuning dict)."""
+    out = rcpsp_search_params()
+    info = rcpsp_tuning()
+    _check(lib().rcpsp_autotune(instance.h, ctypes.byref(params), trial_iterations, _stream_ptr(stream),
+                                ctypes.byref(out), ctypes.byref(info)))
+    return out, {k: getattr(info, k) for k, _ in rcpsp_tuning._fields_}
 
 
 class SearchPlan:

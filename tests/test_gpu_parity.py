@@ -270,3 +270,30 @@ def test_counting_and_timed_runs_match_graph_run(rc, dec):
     assert a["total_work"] == 0 and c["total_work"] > c["total_evaluations"] * inst.n
     plan.close()
     cplan.close()
+
+
+def test_search_decoder_override(rc):
+    """A search may use the other decoder than the instance's default."""
+    inst = synth.generate(30, 4, 10, 0.5, rs=0.4, seed=25)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    g = rc.tabu_search(gi, swap_range=8, tabu_len=40, iterations=30, searches=4, elite=2, phi_steps=4,
+                       eval=CAP, seed=8)
+    o = orc.tabu_search(8, 40, 30, searches=4, elite=2, phi_steps=4, decoder=CAP, seed=8)
+    _compare_search(g, o, elite=2)
+
+
+def test_autotune_choice_is_a_valid_exact_plan(rc):
+    inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=26)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst)
+    base = rc.search_params(14, 110, 20, searches=32, elite=8, phi_steps=10, seed=3)
+    tuned, info = rc.autotune(gi, base, trial_iterations=4)
+    assert tuned.eval in (TIME, CAP) and tuned.threads in (64, 128, 256) and info["trials"] >= 2
+    assert info["ns_per_evaluation"] > 0
+    plan = rc.SearchPlan(gi, tuned)
+    plan.run()
+    g = plan.results()
+    o = orc.tabu_search(14, 110, 20, searches=32, elite=8, phi_steps=10, decoder=tuned.eval, seed=3)
+    _compare_search(g, o, elite=8)
+    plan.close()
