@@ -201,6 +201,34 @@ typedef struct {
 } rcpsp_search_config;
 rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out);
 
+/* Batches (many instances, possibly of different sizes, in one run).
+ * Each instance i gets its own search (params[i]); its results equal those of
+ * rcpsp_tabu_search with the same instance and params (the plan's
+ * profile_len and threads do not change results).  Instances are grouped
+ * by decoder, profile width and threads per search; each group is one
+ * persistent launch in which a workgroup takes the next instance from a queue
+ * (largest first) and runs its whole search, exchange rounds included; the
+ * groups' launches run side by side in one captured graph.
+ *   inst    [count] instances (must outlive the batch)
+ *   params  [count] search parameters (threads 0 = 128 where the instance
+ *           fits, else 64)                                                  */
+typedef struct rcpsp_batch rcpsp_batch;
+rcpsp_status rcpsp_batch_create(const rcpsp_instance *const *inst, int32_t count,
+                                const rcpsp_search_params *params, void *hip_stream, rcpsp_batch **out);
+/* Run every instance's search from its initial state.  Asynchronous. */
+rcpsp_status rcpsp_batch_run(rcpsp_batch *b, void *hip_stream);
+/* Same, bracketed by HIP events; waits and reports device milliseconds. */
+rcpsp_status rcpsp_batch_run_timed(rcpsp_batch *b, void *hip_stream, double *total_ms);
+/* Results of instance `index` (waits for hip_stream). */
+rcpsp_status rcpsp_batch_results(rcpsp_batch *b, int32_t index, rcpsp_search_result *res, void *hip_stream);
+typedef struct {
+    int32_t instances, classes;
+    /* first 8 classes: decoder, threads per search, members, workgroups, LDS bytes */
+    int32_t class_eval[8], class_threads[8], class_instances[8], class_workgroups[8], class_lds_bytes[8];
+} rcpsp_batch_info;
+rcpsp_status rcpsp_batch_get_info(const rcpsp_batch *b, rcpsp_batch_info *out);
+void rcpsp_batch_destroy(rcpsp_batch *b);
+
 /* Decoder and launch shape for one instance and search configuration.
  * Section 5.4 fixes the resource evaluation algorithm per instance before the
  * search, with rules that were learnt by timing both algorithms for a few

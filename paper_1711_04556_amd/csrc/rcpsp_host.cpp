@@ -648,7 +648,8 @@ static hipError_t enqueue_run(rcpsp_search *s, hipStream_t st, RunTimer *tm) {
     return hipSuccess;
 }
 
-static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
+// Layout and device state of a plan (no launches).
+static rcpsp_status alloc_plan(rcpsp_search *s) {
     const rcpsp_instance *I = s->inst;
     const rcpsp_search_params &p = s->p;
     const int N = I->n, N2 = n2(N), B = p.searches, NF = p.elite;
@@ -725,7 +726,13 @@ static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
         HIP_TRY(hipMemset(a.Fwidx, 0, sizeof(int) * 2 * (size_t)NF));
     }
 
-    HIP_TRY(prepare_search(T, s->nw, s->dec, s->lds, B, NF));
+    return RCPSP_OK;
+}
+
+static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
+    rcpsp_status st0 = alloc_plan(s);
+    if (st0 != RCPSP_OK) return st0;
+    HIP_TRY(prepare_search(s->T, s->nw, s->dec, s->lds, s->p.searches, s->p.elite));
     // capture the whole run as one graph
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -957,6 +964,248 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
         info->profile_len = best.profile_len;
         info->trials = trials;
         info->ns_per_evaluation = best_ns;
+    }
+    return RCPSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+
+struct rcpsp_batch {
+    struct Class {
+        int dec = 0, nw = 0, T = 0, grid = 0, count = 0;
+        size_t lds = 0;
+        int *d_order = nullptr;
+    };
+    std::vector<rcpsp_search *> items;
+    std::vector<Class> classes;
+    SearchArgs *d_items = nullptr;
+    BatchQueue *d_queues = nullptr;
+    std::vector<void *> allocs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void rcpsp_batch_destroy(rcpsp_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (rcpsp_search *s : b->items) rcpsp_search_destroy(s);
+    for (void *v : b->allocs) (void)hipFree(v);
+    delete b;
+}
+
+static rcpsp_status validate_params(const rcpsp_search_params &p) {
+    if (p.swap_range < 1 || p.swap_range > kMaxDelta)
+        return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", p.swap_range, kMaxDelta);
+    if (p.tabu_len < 1) return fail(RCPSP_E_ARG, "tabu_len must be >= 1");
+    if (p.iterations < 0) return fail(RCPSP_E_ARG, "iterations must be >= 0");
+    if (p.searches < 1) return fail(RCPSP_E_ARG, "searches must be >= 1");
+    if (p.elite < 0) return fail(RCPSP_E_ARG, "elite must be >= 0");
+    if (p.phi_max < 0 || p.phi_steps < 0) return fail(RCPSP_E_ARG, "phi_max and phi_steps must be >= 0");
+    if (p.eval < 0 || p.eval > 2) return fail(RCPSP_E_ARG, "unknown decoder %d", p.eval);
+    return RCPSP_OK;
+}
+
+static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *inst, int32_t count,
+                                const rcpsp_search_params *params) {
+    // per-instance plans (device state only)
+    for (int i = 0; i < count; ++i) {
+        if (!inst[i]) return fail(RCPSP_E_ARG, "null instance %d", i);
+        rcpsp_search_params p = params[i];
+        rcpsp_status st = validate_params(p);
+        if (st != RCPSP_OK) return st;
+        const bool auto_threads = p.threads == 0;
+        if (auto_threads) p.threads = 128;
+        p.count_work = 0;
+        // the batch sizes each class's LDS by its largest member, so members
+        // use the shortest safe profile rather than one stretched to fill a CU
+        if (p.profile_len == 0)
+            p.profile_len = std::max(16, std::min(inst[i]->H, ((14 * inst[i]->cp + 9) / 10 + 2 * inst[i]->dmax + 15) / 16 * 16));
+        rcpsp_search *s = new (std::nothrow) rcpsp_search();
+        if (!s) return fail(RCPSP_E_NOMEM, "out of host memory");
+        s->inst = inst[i];
+        s->p = p;
+        bt->items.push_back(s);
+        st = alloc_plan(s);
+        if (st == RCPSP_E_TOO_LARGE && auto_threads) {
+            // two waves per search do not fit this instance: one wave
+            bt->items.pop_back();
+            rcpsp_search_destroy(s);
+            s = new (std::nothrow) rcpsp_search();
+            if (!s) return fail(RCPSP_E_NOMEM, "out of host memory");
+            p.threads = 64;
+            s->inst = inst[i];
+            s->p = p;
+            bt->items.push_back(s);
+            st = alloc_plan(s);
+        }
+        if (st != RCPSP_OK) return st;
+        const int need = 6 * p.searches + 5 * p.elite;
+        if (p.elite > 0 && need > s->T * s->Ly.per_lane)
+            return fail(RCPSP_E_TOO_LARGE, "instance %d: exchange bookkeeping does not fit the workgroup's LDS", i);
+    }
+    // classes: same decoder, profile width and threads per search
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < count; ++i) {
+        const rcpsp_search *s = bt->items[i];
+        int c = -1;
+        for (size_t k = 0; k < bt->classes.size(); ++k)
+            if (bt->classes[k].dec == s->dec && bt->classes[k].nw == (s->dec == kEvalTime ? s->nw : 1) &&
+                bt->classes[k].T == s->T)
+                c = (int)k;
+        if (c < 0) {
+            rcpsp_batch::Class cl;
+            cl.dec = s->dec;
+            cl.nw = s->dec == kEvalTime ? s->nw : 1;
+            cl.T = s->T;
+            bt->classes.push_back(cl);
+            members.emplace_back();
+            c = (int)bt->classes.size() - 1;
+        }
+        members[c].push_back(i);
+        bt->classes[c].lds = std::max(bt->classes[c].lds, bt->items[i]->lds);
+    }
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<SearchArgs> host_items(count);
+    for (int i = 0; i < count; ++i) host_items[i] = bt->items[i]->a;
+    void *v = nullptr;
+    HIP_TRY(hipMalloc(&v, sizeof(SearchArgs) * std::max(count, 1)));
+    bt->allocs.push_back(v);
+    bt->d_items = static_cast<SearchArgs *>(v);
+    HIP_TRY(hipMemcpy(bt->d_items, host_items.data(), sizeof(SearchArgs) * count, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&v, batch_queue_bytes() * std::max<size_t>(bt->classes.size(), 1)));
+    bt->allocs.push_back(v);
+    bt->d_queues = static_cast<BatchQueue *>(v);
+    for (size_t c = 0; c < bt->classes.size(); ++c) {
+        rcpsp_batch::Class &cl = bt->classes[c];
+        std::vector<int> &m = members[c];
+        // largest instances first, so that the last ones to finish are short
+        std::stable_sort(m.begin(), m.end(), [&](int x, int y) {
+            const rcpsp_search *a = bt->items[x], *b = bt->items[y];
+            const long long wa = (long long)a->inst->n * a->p.searches * std::max(a->p.iterations, 1);
+            const long long wb = (long long)b->inst->n * b->p.searches * std::max(b->p.iterations, 1);
+            return wa > wb;
+        });
+        cl.count = (int)m.size();
+        HIP_TRY(hipMalloc(&v, sizeof(int) * m.size()));
+        bt->allocs.push_back(v);
+        cl.d_order = static_cast<int *>(v);
+        HIP_TRY(hipMemcpy(cl.d_order, m.data(), sizeof(int) * m.size(), hipMemcpyHostToDevice));
+        HIP_TRY(prepare_batch(cl.T, cl.nw, cl.dec, cl.lds));
+        const int per_cu = std::max(1, (int)(kMaxLds / (cl.lds + 2048)));
+        cl.grid = std::min(cl.count, per_cu * cus);
+    }
+    // one graph: queue reset, then every class's persistent launch on its own
+    // branch so that the classes run side by side
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    std::vector<hipStream_t> side(bt->classes.size());
+    std::vector<hipEvent_t> evs;
+    for (auto &x : side) HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    auto cleanup = [&]() {
+        for (auto x : side) (void)hipStreamDestroy(x);
+        for (auto e : evs) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(cs);
+    };
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = launch_batch_queue_reset(bt->d_queues, (int)bt->classes.size(), cs);
+    hipEvent_t fork = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        evs.push_back(fork);
+        e = hipEventRecord(fork, cs);
+    }
+    for (size_t c = 0; e == hipSuccess && c < bt->classes.size(); ++c) {
+        const rcpsp_batch::Class &cl = bt->classes[c];
+        hipEvent_t done = nullptr;
+        e = hipStreamWaitEvent(side[c], fork, 0);
+        if (e == hipSuccess)
+            e = launch_batch(bt->d_items, cl.d_order, cl.count, reinterpret_cast<BatchQueue *>(
+                                 reinterpret_cast<char *>(bt->d_queues) + c * batch_queue_bytes()),
+                             cl.grid, cl.T, cl.nw, cl.dec, cl.lds, side[c]);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (e == hipSuccess) {
+            evs.push_back(done);
+            e = hipEventRecord(done, side[c]);
+        }
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done, 0);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    cleanup();
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(RCPSP_E_DEVICE, "batch graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    bt->graph = g;
+    HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_batch_create(const rcpsp_instance *const *inst, int32_t count,
+                                           const rcpsp_search_params *params, void *hip_stream,
+                                           rcpsp_batch **out) {
+    if (!inst || !params || !out || count < 1) return fail(RCPSP_E_ARG, "null pointer or empty batch");
+    *out = nullptr;
+    rcpsp_batch *bt = new (std::nothrow) rcpsp_batch();
+    if (!bt) return fail(RCPSP_E_NOMEM, "out of host memory");
+    rcpsp_status st = build_batch(bt, inst, count, params);
+    if (st != RCPSP_OK) {
+        rcpsp_batch_destroy(bt);
+        return st;
+    }
+    (void)hip_stream;
+    *out = bt;
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_batch_run(rcpsp_batch *b, void *hip_stream) {
+    if (!b) return fail(RCPSP_E_ARG, "null batch");
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)hip_stream));
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_batch_run_timed(rcpsp_batch *b, void *hip_stream, double *total_ms) {
+    if (!b) return fail(RCPSP_E_ARG, "null batch");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t t0, t1;
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    hipError_t e = hipEventRecord(t0, st);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(t1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return fail(RCPSP_E_DEVICE, "timed batch run: %s", hipGetErrorString(e));
+    if (total_ms) *total_ms = ms;
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_batch_results(rcpsp_batch *b, int32_t index, rcpsp_search_result *res,
+                                            void *hip_stream) {
+    if (!b || !res) return fail(RCPSP_E_ARG, "null pointer");
+    if (index < 0 || index >= (int32_t)b->items.size()) return fail(RCPSP_E_ARG, "index %d out of range", index);
+    return rcpsp_search_results(b->items[index], res, hip_stream);
+}
+
+extern "C" rcpsp_status rcpsp_batch_get_info(const rcpsp_batch *b, rcpsp_batch_info *out) {
+    if (!b || !out) return fail(RCPSP_E_ARG, "null pointer");
+    *out = rcpsp_batch_info{};
+    out->instances = (int32_t)b->items.size();
+    out->classes = (int32_t)b->classes.size();
+    for (size_t c = 0; c < b->classes.size() && c < 8; ++c) {
+        out->class_eval[c] = b->classes[c].dec;
+        out->class_threads[c] = b->classes[c].T;
+        out->class_instances[c] = b->classes[c].count;
+        out->class_workgroups[c] = b->classes[c].grid;
+        out->class_lds_bytes[c] = (int32_t)b->classes[c].lds;
     }
     return RCPSP_OK;
 }

@@ -715,19 +715,25 @@ __global__ __launch_bounds__(T) void k_eval(EvalArgs A) {
 
 // ---------------------------------------------------------------------------
 // Tabu search
+//
+// The steps below are device functions so that one search plan (one
+// instance, kernels launched per iteration) and a batch (many instances, one
+// persistent workgroup per instance at a time) share them.  Global memory a
+// step writes and a later step of the same workgroup reads is published with
+// a fence before the closing barrier.
 
-// Reset a search plan to its initial state.  Block i: search i (if i < B)
-// and working-set record i (if i < NF).  Initial orders (Section 4.1): the
-// level order (levels ascending, ids ascending) with every level shuffled by
-// Fisher-Yates on the stream (seed, i).
-__global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
-    __shared__ uint16_t w[kMaxN];
+// Reset search i (if i < B) and working-set record i (if i < NF) of a plan.
+// Initial orders (Section 4.1): the level order (levels ascending, ids
+// ascending) with every level shuffled by Fisher-Yates on the stream
+// (seed, i).  w: N 16-bit entries of LDS scratch.
+template <int T>
+__device__ void reset_unit(const SearchArgs &A, int i, uint16_t *w) {
     const InstDesc &D = A.D;
-    const int i = blockIdx.x, tid = threadIdx.x, N = D.n, N2 = n2(N);
+    const int tid = threadIdx.x, N = D.n, N2 = n2(N);
     const uint16_t *base = reinterpret_cast<const uint16_t *>(D.blob + D.off_base);
     const uint16_t *lvl = reinterpret_cast<const uint16_t *>(D.blob + D.off_lvl);
     const bool has_search = i < A.B, has_rec = i < A.NF;
-    for (int p = tid; p < N; p += 64) w[p] = base[p];
+    for (int p = tid; p < N; p += T) w[p] = base[p];
     __syncthreads();
     if (tid == 0) {
         uint64_t ctr = 0;
@@ -745,12 +751,12 @@ __global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
     const int tcn = N * A.tcw;
     if (has_search) {
         if (A.NF == 0)
-            for (int p = tid; p < N2; p += 64) A.Wcur[(size_t)i * N2 + p] = p < N ? w[p] : 0;
-        for (int x = tid; x < A.tl; x += 64) A.ring[(size_t)i * A.tl + x] = 0;
-        for (int x = tid; x < tcn; x += 64) A.tc[(size_t)i * tcn + x] = 0;
+            for (int p = tid; p < N2; p += T) A.Wcur[(size_t)i * N2 + p] = p < N ? w[p] : 0;
+        for (int x = tid; x < A.tl; x += T) A.ring[(size_t)i * A.tl + x] = 0;
+        for (int x = tid; x < tcn; x += T) A.tc[(size_t)i * tcn + x] = 0;
         if (A.record && A.traj) {
             const size_t n4 = (size_t)A.iters * 4;
-            for (size_t x = tid; x < n4; x += 64) A.traj[(size_t)i * n4 + x] = -1;
+            for (size_t x = tid; x < n4; x += T) A.traj[(size_t)i * n4 + x] = -1;
         }
         if (tid == 0) {
             SearchScalars s = {};
@@ -760,9 +766,9 @@ __global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
         }
     }
     if (has_rec) {
-        for (int p = tid; p < N2; p += 64) A.Fw[(size_t)i * N2 + p] = p < N ? w[p] : 0;
-        for (int x = tid; x < A.tl; x += 64) A.Fring[(size_t)i * A.tl + x] = 0;
-        for (int x = tid; x < tcn; x += 64) A.Ftc[(size_t)i * tcn + x] = 0;
+        for (int p = tid; p < N2; p += T) A.Fw[(size_t)i * N2 + p] = p < N ? w[p] : 0;
+        for (int x = tid; x < A.tl; x += T) A.Fring[(size_t)i * A.tl + x] = 0;
+        for (int x = tid; x < tcn; x += T) A.Ftc[(size_t)i * tcn + x] = 0;
         if (tid == 0) {
             A.Fwidx[i] = 0;
             A.Fmeta[i].IC = 0; A.Fmeta[i].reads = 0; A.Fmeta[i].buf = 0; A.Fmeta[i].C = 0x7fffffff;
@@ -772,22 +778,37 @@ __global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
         A.g->Cstar = 0x7fffffff;
         A.g->gstop = 0;
     }
+    __threadfence();
+    __syncthreads();
 }
 
-// Makespan of every initial working-set record (buffer 0).
+__global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
+    __shared__ uint16_t w[kMaxN];
+    reset_unit<64>(A, blockIdx.x, w);
+}
+
+// Makespan of initial working-set record k (buffer 0); the blob is staged.
 template <int NW, int T, int DEC>
-__global__ __launch_bounds__(T) void k_decode_records(SearchArgs A) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+__device__ void decode_record(const SearchArgs &A, const Sh &S, int k) {
     const InstDesc &D = A.D;
-    Sh S = make_sh(lds, D, A.Ly);
-    const int k = blockIdx.x, N2 = n2(D.n);
-    stage_blob<T>(lds, D, A.Ly);
+    const int N2 = n2(D.n);
     const uint32_t *src = reinterpret_cast<const uint32_t *>(A.Fw + (size_t)k * N2);
     for (int i = threadIdx.x; i < N2 / 2; i += T) reinterpret_cast<uint32_t *>(S.W)[i] = src[i];
     __syncthreads();
     build_records<T>(S, D);
     __syncthreads();
     if (threadIdx.x == 0) A.Fmeta[k].C = decode_long<NW, DEC>(S, D, A.Ly, 0, 0);
+    __threadfence();
+    __syncthreads();
+}
+
+template <int NW, int T, int DEC>
+__global__ __launch_bounds__(T) void k_decode_records(SearchArgs A) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    Sh S = make_sh(lds, A.D, A.Ly);
+    stage_blob<T>(lds, A.D, A.Ly);
+    __syncthreads();
+    decode_record<NW, T, DEC>(A, S, blockIdx.x);
 }
 
 template <int T>
@@ -795,25 +816,30 @@ __device__ inline void copy_dw(uint32_t *dst, const uint32_t *src, int n) {
     for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
 }
 
-// One workgroup per search; iterations [it0, it0 + n_it).  COUNT adds the
-// algorithmic operations of every decode to the search's work counter.
+// Per-workgroup scratch of a search step.
+struct StepShared {
+    SearchScalars sc;
+    int dirty_best, dirty_imp;
+};
+
+// Search b, iterations [it0, it0 + n_it): complete a pending read (record
+// or export, diversification), then iterate (neighbourhood, decode, best
+// admissible move, Alg. 3), then export for the next exchange round.  The
+// instance blob must be staged.  COUNT adds the algorithmic operations of
+// every decode to the search's work counter.
 template <int NW, int T, int DEC, bool COUNT>
-__global__ __launch_bounds__(T) void k_search(SearchArgs A) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-    __shared__ SearchScalars sc;
-    __shared__ int dirty_best, dirty_imp;
+__device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, int b, int it0, int n_it) {
     const InstDesc &D = A.D;
     const Layout &Ly = A.Ly;
-    Sh S = make_sh(lds, D, Ly);
-    const int b = blockIdx.x, tid = threadIdx.x, N = D.n, N2 = n2(N);
+    SearchScalars &sc = ss.sc;
+    const int tid = threadIdx.x, N = D.n, N2 = n2(N);
     const int tcn = N * A.tcw;
     const bool coop = A.NF > 0;
     if (tid == 0) {
         sc = A.sc[b];
-        dirty_best = 0;
-        dirty_imp = 0;
+        ss.dirty_best = 0;
+        ss.dirty_imp = 0;
     }
-    stage_blob<T>(lds, D, Ly);
     __syncthreads();
     // control flow below depends on the flags as loaded; thread 0 rewrites
     // sc.flags later, so every thread takes its copy before that can happen.
@@ -821,9 +847,10 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
     // read chosen by the last round is still completed, then nothing runs.
     const int flags0 = sc.flags;
     const bool gstop = A.g->gstop != 0;
-    if (sc.stopped || (gstop && !(flags0 & (kFlagReadPending | kFlagInitDecode)))) return;
-    const int it_end = gstop ? A.it0 : A.it0 + A.n_it;
+    const bool skip = sc.stopped || (gstop && !(flags0 & (kFlagReadPending | kFlagInitDecode)));
+    const int it_end = gstop ? it0 : it0 + n_it;
     __syncthreads();
+    if (skip) return;
     uint32_t *Wd = reinterpret_cast<uint32_t *>(S.W);
     if (flags0 & kFlagReadPending) {
         const uint32_t *sw, *sr, *st;
@@ -874,7 +901,7 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
             sc.C_imp = sc.C_cur;
             if (sc.C_cur < sc.C_best) {
                 sc.C_best = sc.C_cur;
-                dirty_best = 1;
+                ss.dirty_best = 1;
             }
             sc.flags &= ~(kFlagReadPending | kFlagDiversify);
         }
@@ -892,20 +919,20 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
             if (tid == 0) {
                 sc.C_cur = decode_long<NW, DEC>(S, D, Ly, 0, 0);
                 sc.C_best = sc.C_cur;
-                dirty_best = 1;
+                ss.dirty_best = 1;
                 sc.flags &= ~kFlagInitDecode;
             }
             __syncthreads();
         }
     }
-    const int dirty0 = dirty_best;
+    const int dirty0 = ss.dirty_best;
     __syncthreads();
     if (dirty0) copy_dw<T>(reinterpret_cast<uint32_t *>(A.Wbest + (size_t)b * N2), Wd, N2 / 2);
-    if (tid == 0) dirty_best = 0;
+    if (tid == 0) ss.dirty_best = 0;
     __syncthreads();
 
     TabuSrc tb{S.tc, nullptr, A.tcw, N};
-    for (int it = A.it0; it < it_end; ++it) {
+    for (int it = it0; it < it_end; ++it) {
         bool stop = sc.it_done >= A.iters || (!coop && sc.C_best == D.cp);
         const int asp = coop ? min(sc.C_best, A.g->Cstar) : sc.C_best;
         __syncthreads();
@@ -943,7 +970,7 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
             sc.evals += nf;
             if (c < sc.C_best) {
                 sc.C_best = c;
-                dirty_best = 1;
+                ss.dirty_best = 1;
             }
             if (A.record) {
                 int *rec = A.traj + ((size_t)b * A.iters + it) * 4;
@@ -954,25 +981,25 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
                 sc.it_read++;
                 if (c < sc.C_imp) {
                     sc.C_imp = c;
-                    dirty_imp = 1;
+                    ss.dirty_imp = 1;
                 }
                 sc.fired = (sc.C_imp < sc.C_read) || (sc.it_read > sc.I_assigned);
             }
         }
         __syncthreads();
-        const int db = dirty_best, di = dirty_imp;
+        const int db = ss.dirty_best, di = ss.dirty_imp;
         if (db) copy_dw<T>(reinterpret_cast<uint32_t *>(A.Wbest + (size_t)b * N2), Wd, N2 / 2);
         if (di) copy_dw<T>(reinterpret_cast<uint32_t *>(S.Wimp), Wd, N2 / 2);
         __syncthreads();
         if (tid == 0) {
-            dirty_best = 0;
-            dirty_imp = 0;
+            ss.dirty_best = 0;
+            ss.dirty_imp = 0;
         }
         __syncthreads();
     }
     // export for the exchange round
     if (coop && sc.fired && sc.C_imp < sc.C_read) {
-        const int par = A.it0 & 1;
+        const int par = it0 & 1;
         const size_t r = (size_t)par * A.B + b;
         copy_dw<T>(reinterpret_cast<uint32_t *>(A.Xw + r * N2), reinterpret_cast<uint32_t *>(S.Wimp), N2 / 2);
         copy_dw<T>(A.Xring + r * A.tl, S.ring, A.tl);
@@ -987,6 +1014,19 @@ __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
                    N2 / 2);
     __syncthreads();
     if (tid == 0) A.sc[b] = sc;
+    __threadfence();
+    __syncthreads();
+}
+
+// One workgroup per search of a plan; iterations [it0, it0 + n_it).
+template <int NW, int T, int DEC, bool COUNT>
+__global__ __launch_bounds__(T) void k_search(SearchArgs A) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ StepShared ss;
+    Sh S = make_sh(lds, A.D, A.Ly);
+    stage_blob<T>(lds, A.D, A.Ly);
+    __syncthreads();
+    search_step<NW, T, DEC, COUNT>(A, S, ss, blockIdx.x, A.it0, A.n_it);
 }
 
 // eq. 8, read as floor(I_block (4 E[a] + E[b]) / (25 * 2^24)) >= 1 with the
@@ -1000,21 +1040,20 @@ __device__ inline int iterations_assigned(int iblock, int ck, int cstar, int ic,
     return ia < 1 ? 1 : (int)ia;
 }
 
-// Working-set exchange round (Section 6.1), one workgroup.  Searches whose
-// exchange condition fired are taken in ascending id: each writes its best
-// solution since its last read to the record it read (if it improved that
-// solution and beats the record's current content) and reads the next
-// record.  The bookkeeping is sequential; the data moves are done by the
-// readers themselves in the next iteration launch, from the record buffer or
-// from the writer's export buffer they were pointed at.
-__global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int init) {
-    extern __shared__ int rs[];
+// Working-set exchange round (Section 6.1).  Searches whose exchange
+// condition fired are taken in ascending id: each writes its best solution
+// since its last read to the record it read (if it improved that solution and
+// beats the record's current content) and reads the next record.  The
+// bookkeeping is sequential; the data moves are done by the readers
+// themselves in their next step, from the record buffer or from the writer's
+// export buffer they were pointed at.  rs: 6B + 5NF ints of LDS scratch.
+template <int T>
+__device__ void exchange_round(const SearchArgs &A, int parity, int init, int *rs) {
     const int B = A.B, NF = A.NF, tid = threadIdx.x, N2 = n2(A.D.n), tcn = A.D.n * A.tcw;
     int *fired = rs, *slot = rs + B, *itr = rs + 2 * B, *cimp = rs + 3 * B, *cread = rs + 4 * B;
-    int *newr = rs + 5 * B;
+    int *cstar_s = rs + 5 * B;
     int *fC = rs + 6 * B, *fIC = fC + NF, *fR = fIC + NF, *fB = fR + NF, *content = fB + NF;
-    __shared__ int cstar_s;
-    for (int b = tid; b < B; b += 256) {
+    for (int b = tid; b < B; b += T) {
         const SearchScalars &s = A.sc[b];
         if (init) {
             fired[b] = 1;
@@ -1029,9 +1068,8 @@ __global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int ini
             cimp[b] = s.C_imp;
             cread[b] = s.C_read;
         }
-        newr[b] = 0;
     }
-    for (int k = tid; k < NF; k += 256) {
+    for (int k = tid; k < NF; k += T) {
         fC[k] = A.Fmeta[k].C;
         fIC[k] = A.Fmeta[k].IC;
         fR[k] = A.Fmeta[k].reads;
@@ -1072,9 +1110,8 @@ __global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int ini
             s.slot = k2;
             s.it_read = 0;
             s.fired = 0;
-            newr[b] = 1;
         }
-        cstar_s = cstar;
+        *cstar_s = cstar;
     }
     __syncthreads();
     // final content of each written record -> its other buffer
@@ -1083,23 +1120,88 @@ __global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int ini
         if (w < 0) continue;
         const size_t src = (size_t)parity * B + w;
         const size_t dst = (size_t)(fB[k] ^ 1) * NF + k;
-        for (int i = tid; i < N2 / 2; i += 256)
+        for (int i = tid; i < N2 / 2; i += T)
             reinterpret_cast<uint32_t *>(A.Fw + dst * N2)[i] = reinterpret_cast<const uint32_t *>(A.Xw + src * N2)[i];
-        for (int i = tid; i < A.tl; i += 256) A.Fring[dst * A.tl + i] = A.Xring[src * A.tl + i];
-        for (int i = tid; i < tcn; i += 256) A.Ftc[dst * tcn + i] = A.Xtc[src * tcn + i];
+        for (int i = tid; i < A.tl; i += T) A.Fring[dst * A.tl + i] = A.Xring[src * A.tl + i];
+        for (int i = tid; i < tcn; i += T) A.Ftc[dst * tcn + i] = A.Xtc[src * tcn + i];
         if (tid == 0) A.Fwidx[dst] = A.Xwidx[src];
     }
     __syncthreads();
-    for (int k = tid; k < NF; k += 256) {
+    for (int k = tid; k < NF; k += T) {
         A.Fmeta[k].C = fC[k];
         A.Fmeta[k].IC = fIC[k];
         A.Fmeta[k].reads = fR[k];
         A.Fmeta[k].buf = content[k] >= 0 ? (fB[k] ^ 1) : fB[k];
     }
     if (tid == 0) {
-        A.g->Cstar = cstar_s;
-        A.g->gstop = cstar_s == A.D.cp;
+        A.g->Cstar = *cstar_s;
+        A.g->gstop = *cstar_s == A.D.cp;
     }
+    __threadfence();
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int init) {
+    extern __shared__ int rs[];
+    exchange_round<256>(A, parity, init, rs);
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many instances, each with its own search plan, in one persistent
+// launch per decoder/profile-width class.  A workgroup takes the next
+// instance from a queue (instances sorted by size, largest first), runs its
+// whole search (reset, initial records, every iteration of every search and
+// the exchange rounds, the rounds needing only this workgroup), then takes
+// the next one; it exits when the queue is empty.  Every instance's result
+// equals that of its own plan.
+
+struct BatchQueue {
+    int next;
+    int pad[15];
+};
+
+template <int NW, int T, int DEC>
+__global__ __launch_bounds__(T) void k_batch(const SearchArgs *items, const int *order, int count, BatchQueue *q) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ SearchArgs A;
+    __shared__ StepShared ss;
+    __shared__ int cur;
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(&q->next, 1);
+        __syncthreads();
+        const int c = cur;
+        __syncthreads();
+        if (c >= count) break;
+        {
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(items + order[c]);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(&A);
+            for (int i = threadIdx.x; i < (int)(sizeof(SearchArgs) / 4); i += T) dst[i] = src[i];
+        }
+        __syncthreads();
+        Sh S = make_sh(lds, A.D, A.Ly);
+        uint16_t *scratch16 = reinterpret_cast<uint16_t *>(S.region);
+        const int units = A.B > A.NF ? A.B : A.NF;
+        for (int i = 0; i < units; ++i) reset_unit<T>(A, i, scratch16);
+        stage_blob<T>(lds, A.D, A.Ly);
+        __syncthreads();
+        if (A.NF > 0) {
+            for (int k = 0; k < A.NF; ++k) decode_record<NW, T, DEC>(A, S, k);
+            exchange_round<T>(A, 0, 1, reinterpret_cast<int *>(S.region));
+            for (int it = 0; it < A.iters; ++it) {
+                for (int b = 0; b < A.B; ++b) search_step<NW, T, DEC, false>(A, S, ss, b, it, 1);
+                if (it < A.iters - 1) exchange_round<T>(A, it & 1, 0, reinterpret_cast<int *>(S.region));
+            }
+            if (A.iters == 0)
+                for (int b = 0; b < A.B; ++b) search_step<NW, T, DEC, false>(A, S, ss, b, 0, 0);
+        } else {
+            for (int b = 0; b < A.B; ++b) search_step<NW, T, DEC, false>(A, S, ss, b, 0, A.iters);
+        }
+    }
+}
+
+// Queue reset (a kernel, so that graph replays never record a memset).
+__global__ void k_batch_queue_reset(BatchQueue *q, int n) {
+    if (threadIdx.x < n) q[threadIdx.x].next = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1183,6 +1285,29 @@ hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, size_t lds
     });
     return hipGetLastError();
 }
+
+hipError_t prepare_batch(int T, int nw, int dec, size_t lds) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipError_t e = set_lds(k_batch<NW_, T_, DEC_>, lds);
+        if (e != hipSuccess) return e;
+    });
+    return hipSuccess;
+}
+
+hipError_t launch_batch(const SearchArgs *items, const int *order, int count, BatchQueue *q, int grid, int T, int nw,
+                        int dec, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipLaunchKernelGGL((k_batch<NW_, T_, DEC_>), dim3(grid), dim3(T_), lds, st, items, order, count, q);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_queue_reset(BatchQueue *q, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_queue_reset, dim3(1), dim3(64), 0, st, q, n);
+    return hipGetLastError();
+}
+
+size_t batch_queue_bytes() { return sizeof(BatchQueue); }
 
 hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t st) {
     const size_t lds = round_lds_bytes(A.B, A.NF);

@@ -25,4 +25,11 @@ hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t s
 size_t round_lds_bytes(int B, int NF);
 hipError_t prepare_search(int T, int nw, int dec, size_t lds, int B, int NF);
 
+struct BatchQueue;
+size_t batch_queue_bytes();
+hipError_t prepare_batch(int T, int nw, int dec, size_t lds);
+hipError_t launch_batch(const SearchArgs *items, const int *order, int count, BatchQueue *q, int grid, int T, int nw,
+                        int dec, size_t lds, hipStream_t st);
+hipError_t launch_batch_queue_reset(BatchQueue *q, int n, hipStream_t st);
+
 }  // namespace rcpsp

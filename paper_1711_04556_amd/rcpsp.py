@@ -61,6 +61,12 @@ class rcpsp_search_result(ctypes.Structure):
                 ("total_work", ctypes.c_int64)]
 
 
+class rcpsp_batch_info(ctypes.Structure):
+    _fields_ = [("instances", ctypes.c_int32), ("classes", ctypes.c_int32)] + [
+        (n, ctypes.c_int32 * 8) for n in ("class_eval", "class_threads", "class_instances", "class_workgroups",
+                                          "class_lds_bytes")]
+
+
 class rcpsp_search_config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches")]
@@ -110,6 +116,19 @@ def lib():
     L.rcpsp_autotune.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), i32, vp, ctypes.POINTER(rcpsp_search_params),
                                  ctypes.POINTER(rcpsp_tuning)]
     L.rcpsp_autotune.restype = ctypes.c_int
+    L.rcpsp_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(rcpsp_search_params), vp,
+                                     ctypes.POINTER(vp)]
+    L.rcpsp_batch_create.restype = ctypes.c_int
+    L.rcpsp_batch_run.argtypes = [vp, vp]
+    L.rcpsp_batch_run.restype = ctypes.c_int
+    L.rcpsp_batch_run_timed.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.rcpsp_batch_run_timed.restype = ctypes.c_int
+    L.rcpsp_batch_results.argtypes = [vp, i32, ctypes.POINTER(rcpsp_search_result), vp]
+    L.rcpsp_batch_results.restype = ctypes.c_int
+    L.rcpsp_batch_get_info.argtypes = [vp, ctypes.POINTER(rcpsp_batch_info)]
+    L.rcpsp_batch_get_info.restype = ctypes.c_int
+    L.rcpsp_batch_destroy.argtypes = [vp]
+    L.rcpsp_batch_destroy.restype = None
     L.rcpsp_last_error.argtypes = []
     L.rcpsp_last_error.restype = ctypes.c_char_p
     L.rcpsp_version.argtypes = []
@@ -268,6 +287,74 @@ class SearchPlan:
         out["overflow_decodes"] = res.overflow_decodes
         out["total_work"] = res.total_work
         return out
+
+
+def _results(fn, handle_args, params, n, stream, orders=True, trajectory=True) -> dict:
+    p = params
+    B, N, F = p.searches, n, p.elite
+    out = dict(best_makespan=np.zeros(B, np.int32), iterations_done=np.zeros(B, np.int32),
+               evaluations=np.zeros(B, np.int64),
+               best_order=np.zeros((B, N), np.int32) if orders else None,
+               trajectory=np.zeros((B, p.iterations, 4), np.int32) if (trajectory and p.record_trajectory) else None,
+               elite_makespan=np.zeros(max(F, 1), np.int32),
+               elite_order=np.zeros((max(F, 1), N), np.int32) if orders else None)
+    res = rcpsp_search_result(*[out[k].ctypes.data if out[k] is not None else None for k in
+                                ("best_makespan", "best_order", "iterations_done", "evaluations", "trajectory",
+                                 "elite_makespan", "elite_order")])
+    _check(fn(*handle_args, ctypes.byref(res), _stream_ptr(stream)))
+    out["elite_makespan"] = out["elite_makespan"][:F]
+    if out["elite_order"] is not None:
+        out["elite_order"] = out["elite_order"][:F]
+    out["global_best"] = res.global_best
+    out["total_evaluations"] = res.total_evaluations
+    out["overflow_decodes"] = res.overflow_decodes
+    out["total_work"] = res.total_work
+    return out
+
+
+class Batch:
+    """rcpsp_batch_create / _run / _results / _destroy: many instances, each
+    with its own search, in persistent launches."""
+
+    def __init__(self, instances: Sequence[Instance], params, stream=None):
+        if not isinstance(params, (list, tuple)):
+            params = [params] * len(instances)
+        self.instances = list(instances)
+        self.params = list(params)
+        hs = (ctypes.c_void_p * len(instances))(*[i.h.value for i in instances])
+        ps = (rcpsp_search_params * len(instances))(*params)
+        h = ctypes.c_void_p()
+        _check(lib().rcpsp_batch_create(hs, len(instances), ps, _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self) -> None:
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.rcpsp_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def info(self) -> dict:
+        out = rcpsp_batch_info()
+        _check(lib().rcpsp_batch_get_info(self.h, ctypes.byref(out)))
+        d = {"instances": out.instances, "classes": out.classes}
+        for k in ("class_eval", "class_threads", "class_instances", "class_workgroups", "class_lds_bytes"):
+            d[k] = list(getattr(out, k))[:out.classes]
+        return d
+
+    def run(self, stream=None) -> None:
+        _check(lib().rcpsp_batch_run(self.h, _stream_ptr(stream)))
+
+    def run_timed(self, stream=None) -> float:
+        ms = ctypes.c_double()
+        _check(lib().rcpsp_batch_run_timed(self.h, _stream_ptr(stream), ctypes.byref(ms)))
+        return ms.value
+
+    def results(self, index: int, stream=None, orders: bool = True, trajectory: bool = True) -> dict:
+        return _results(lib().rcpsp_batch_results, (self.h, index), self.params[index], self.instances[index].n,
+                        stream, orders, trajectory)
 
 
 def tabu_search(instance: Instance, stream=None, **kw) -> dict:

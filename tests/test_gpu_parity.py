@@ -297,3 +297,46 @@ def test_autotune_choice_is_a_valid_exact_plan(rc):
     o = orc.tabu_search(14, 110, 20, searches=32, elite=8, phi_steps=10, decoder=tuned.eval, seed=3)
     _compare_search(g, o, elite=8)
     plan.close()
+
+
+def _batch_case():
+    insts, params = [], []
+    for i, (n, rs, rf) in enumerate([(30, 0.5, 0.5), (60, 0.3, 0.75), (20, 0.7, 1.0), (40, 0.2, 0.25),
+                                     (30, 0.6, 0.5), (50, 0.4, 0.5)]):
+        insts.append(synth.generate(n, 4, 10, rf, rs=rs, seed=700 + i))
+    insts.append(_wide_instance())
+    return insts
+
+
+def test_batch_matches_oracle_and_plans(rc):
+    """Mixed sizes, decoders, working-set and independent searches in one
+    batch: every instance's results equal the oracle's and its own plan's."""
+    insts = _batch_case()
+    gis, params = [], []
+    for i, inst in enumerate(insts):
+        dec = TIME if i % 3 else CAP
+        gis.append(rc.Instance(inst, eval=dec))
+        elite = 0 if i % 4 == 1 else 4
+        params.append(rc.search_params(6 + i % 3, 30, 15, searches=6 + i, elite=elite, phi_max=2, phi_steps=4,
+                                       threads=64, seed=11 + i))
+    bt = rc.Batch(gis, params)
+    info = bt.info
+    assert info["instances"] == len(insts) and info["classes"] >= 2
+    bt.run()
+    for i, inst in enumerate(insts):
+        g = bt.results(i)
+        p = params[i]
+        o = oracle.Oracle(inst).tabu_search(p.swap_range, p.tabu_len, p.iterations, searches=p.searches,
+                                            elite=p.elite, phi_max=p.phi_max, phi_steps=p.phi_steps,
+                                            decoder=gis[i].info["eval"], seed=p.seed)
+        _compare_search(g, o, elite=p.elite)
+        plan = rc.tabu_search(gis[i], swap_range=p.swap_range, tabu_len=p.tabu_len, iterations=p.iterations,
+                              searches=p.searches, elite=p.elite, phi_max=p.phi_max, phi_steps=p.phi_steps,
+                              threads=64, seed=p.seed)
+        _compare_search(g, plan, elite=p.elite)
+    # a second run gives the same results
+    first = [bt.results(i)["trajectory"] for i in range(len(insts))]
+    bt.run()
+    for i in range(len(insts)):
+        assert np.array_equal(first[i], bt.results(i)["trajectory"])
+    bt.close()
