@@ -205,13 +205,19 @@ rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config 
  * Each instance i gets its own search (params[i]); its results equal those of
  * rcpsp_tabu_search with the same instance and params (the plan's
  * profile_len and threads do not change results).  Instances are grouped
- * by decoder, profile width and threads per search; each group is one
- * persistent launch in which a workgroup takes the next instance from a queue
- * (largest first) and runs its whole search, exchange rounds included; the
- * groups' launches run side by side in one captured graph.
+ * by decoder, profile width, threads per search and workgroups per CU; each
+ * group is one persistent launch whose workgroups take tasks from a queue:
+ * one set-up task per instance, then, iteration by iteration, one task per
+ * (instance, search).  A search task waits for its instance's previous
+ * exchange round, which the task finishing the instance's last search of an
+ * iteration runs.  The groups' launches run side by side in one captured
+ * graph.
  *   inst    [count] instances (must outlive the batch)
- *   params  [count] search parameters (threads 0 = 128 where the instance
- *           fits, else 64)                                                  */
+ *   params  [count] search parameters (threads 0 = 64)
+ * Errors: RCPSP_E_TOO_LARGE when an instance's workgroup does not fit a CU;
+ * RCPSP_E_DEVICE from run_timed or results when a run ended early because
+ * one wait inside the kernel exceeded its limit (20 s), which leaves the
+ * results undefined. */
 typedef struct rcpsp_batch rcpsp_batch;
 rcpsp_status rcpsp_batch_create(const rcpsp_instance *const *inst, int32_t count,
                                 const rcpsp_search_params *params, void *hip_stream, rcpsp_batch **out);
@@ -219,7 +225,7 @@ rcpsp_status rcpsp_batch_create(const rcpsp_instance *const *inst, int32_t count
 rcpsp_status rcpsp_batch_run(rcpsp_batch *b, void *hip_stream);
 /* Same, bracketed by HIP events; waits and reports device milliseconds. */
 rcpsp_status rcpsp_batch_run_timed(rcpsp_batch *b, void *hip_stream, double *total_ms);
-/* Results of instance `index` (waits for hip_stream). */
+/* Results of instance `index` (waits for hip_stream; checks the run ended normally). */
 rcpsp_status rcpsp_batch_results(rcpsp_batch *b, int32_t index, rcpsp_search_result *res, void *hip_stream);
 typedef struct {
     int32_t instances, classes;

@@ -83,6 +83,7 @@ struct rcpsp_search {
     const rcpsp_instance *inst = nullptr;
     rcpsp_search_params p{};
     int T = 64, L = 0, nw = 1, dec = 1, tcw = 1, P = 0;
+    int reserve = 256;    // static LDS of the kernel the plan runs in
     Layout Ly{};
     size_t lds = 0;
     SearchArgs a{};
@@ -384,8 +385,8 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     return Ly;
 }
 
-// Workgroups of `bytes` LDS that fit on one CU.
-static int lds_occupancy(size_t bytes) { return (int)(kMaxLds / (bytes + 256)); }
+// Workgroups of `bytes` dynamic LDS (and `reserve` static) that fit on one CU.
+static int lds_occupancy(size_t bytes, int reserve) { return (int)(kMaxLds / (bytes + (size_t)reserve)); }
 
 // Per-lane time-indexed profile length.  Without a request: at least
 // 1.4 x the critical path plus two longest durations (neighbourhood
@@ -394,7 +395,7 @@ static int lds_occupancy(size_t bytes) { return (int)(kMaxLds / (bytes + 256)); 
 // workgroups per CU, never beyond the horizon.  The whole region must also
 // hold one profile of the full horizon for the long-profile decode.
 static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw, int tl, int pmax, int L_req,
-                                int *L_out, Layout *Ly_out) {
+                                int reserve, int *L_out, Layout *Ly_out) {
     const InstDesc &D = I->desc;
     const int budget = kMaxLds - 1024;  // static shared variables
     if (dec == kEvalCapacity) {
@@ -427,9 +428,9 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
         if (L <= 16) return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
         L = std::max(16, L * 3 / 4);
     }
-    const int k0 = lds_occupancy((size_t)Ly.total * 4);
+    const int k0 = lds_occupancy((size_t)Ly.total * 4, reserve);
     Layout Ln;
-    while (L + 4 <= H && fits(L + 4, &Ln) && lds_occupancy((size_t)Ln.total * 4) >= k0) {
+    while (L + 4 <= H && fits(L + 4, &Ln) && lds_occupancy((size_t)Ln.total * 4, reserve) >= k0) {
         L += 4;
         Ly = Ln;
     }
@@ -448,10 +449,10 @@ static rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, i
     int T = 256;
     int L = 0;
     Layout Ly;
-    rcpsp_status s = plan_layout(I, I->eval, T, 0, 0, P, 0, &L, &Ly);
+    rcpsp_status s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly);
     while (s == RCPSP_E_TOO_LARGE && T > 64) {
         T /= 2;
-        s = plan_layout(I, I->eval, T, 0, 0, P, 0, &L, &Ly);
+        s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly);
     }
     if (s != RCPSP_OK) return s;
     EvalArgs A{};
@@ -662,10 +663,10 @@ static rcpsp_status alloc_plan(rcpsp_search *s) {
     int T = p.threads;
     if (T == 0) T = B >= 256 ? 64 : (B >= 64 ? 128 : 256);
     if (T != 64 && T != 128 && T != 256) return fail(RCPSP_E_ARG, "threads must be 0, 64, 128 or 256");
-    rcpsp_status st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, &s->L, &s->Ly);
+    rcpsp_status st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, s->reserve, &s->L, &s->Ly);
     while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
         T /= 2;
-        st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, &s->L, &s->Ly);
+        st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, s->reserve, &s->L, &s->Ly);
     }
     if (st != RCPSP_OK) return st;
     s->T = T;
@@ -973,14 +974,15 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
 
 struct rcpsp_batch {
     struct Class {
-        int dec = 0, nw = 0, T = 0, grid = 0, count = 0;
+        int dec = 0, nw = 0, T = 0, per_cu = 0, grid = 0, count = 0;
         size_t lds = 0;
-        int *d_order = nullptr;
+        BatchClassArgs args{};
     };
     std::vector<rcpsp_search *> items;
     std::vector<Class> classes;
     SearchArgs *d_items = nullptr;
-    BatchQueue *d_queues = nullptr;
+    int *d_state = nullptr;        // queues, then per-class epoch and done counters
+    long long state_ints = 0;
     std::vector<void *> allocs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1007,6 +1009,9 @@ static rcpsp_status validate_params(const rcpsp_search_params &p) {
     return RCPSP_OK;
 }
 
+// Limit of one dependency wait inside the batch kernel (wall clock, 100 MHz).
+constexpr long long kBatchWaitTicks = 20ll * 100 * 1000 * 1000;
+
 static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *inst, int32_t count,
                                 const rcpsp_search_params *params) {
     // per-instance plans (device state only)
@@ -1015,56 +1020,45 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         rcpsp_search_params p = params[i];
         rcpsp_status st = validate_params(p);
         if (st != RCPSP_OK) return st;
-        const bool auto_threads = p.threads == 0;
-        if (auto_threads) p.threads = 128;
+        if (p.threads == 0) p.threads = 64;
         p.count_work = 0;
-        // the batch sizes each class's LDS by its largest member, so members
-        // use the shortest safe profile rather than one stretched to fill a CU
-        if (p.profile_len == 0)
-            p.profile_len = std::max(16, std::min(inst[i]->H, ((14 * inst[i]->cp + 9) / 10 + 2 * inst[i]->dmax + 15) / 16 * 16));
         rcpsp_search *s = new (std::nothrow) rcpsp_search();
         if (!s) return fail(RCPSP_E_NOMEM, "out of host memory");
         s->inst = inst[i];
         s->p = p;
+        s->reserve = kBatchStaticLds;
         bt->items.push_back(s);
         st = alloc_plan(s);
-        if (st == RCPSP_E_TOO_LARGE && auto_threads) {
-            // two waves per search do not fit this instance: one wave
-            bt->items.pop_back();
-            rcpsp_search_destroy(s);
-            s = new (std::nothrow) rcpsp_search();
-            if (!s) return fail(RCPSP_E_NOMEM, "out of host memory");
-            p.threads = 64;
-            s->inst = inst[i];
-            s->p = p;
-            bt->items.push_back(s);
-            st = alloc_plan(s);
-        }
         if (st != RCPSP_OK) return st;
         const int need = 6 * p.searches + 5 * p.elite;
         if (p.elite > 0 && need > s->T * s->Ly.per_lane)
             return fail(RCPSP_E_TOO_LARGE, "instance %d: exchange bookkeeping does not fit the workgroup's LDS", i);
     }
-    // classes: same decoder, profile width and threads per search
+    // classes: same decoder, profile width, threads per search and workgroups per CU
     std::vector<std::vector<int>> members;
     for (int i = 0; i < count; ++i) {
         const rcpsp_search *s = bt->items[i];
+        const int nw = s->dec == kEvalTime ? s->nw : 1;
+        int per_cu = 0;
+        HIP_TRY(batch_occupancy(s->T, nw, s->dec, s->lds, &per_cu));
+        if (per_cu < 1) return fail(RCPSP_E_TOO_LARGE, "instance %d: batch workgroup does not fit a CU", i);
         int c = -1;
-        for (size_t k = 0; k < bt->classes.size(); ++k)
-            if (bt->classes[k].dec == s->dec && bt->classes[k].nw == (s->dec == kEvalTime ? s->nw : 1) &&
-                bt->classes[k].T == s->T)
-                c = (int)k;
+        for (size_t k = 0; k < bt->classes.size(); ++k) {
+            const rcpsp_batch::Class &cl = bt->classes[k];
+            if (cl.dec == s->dec && cl.nw == nw && cl.T == s->T && cl.per_cu == per_cu) c = (int)k;
+        }
         if (c < 0) {
             rcpsp_batch::Class cl;
             cl.dec = s->dec;
-            cl.nw = s->dec == kEvalTime ? s->nw : 1;
+            cl.nw = nw;
             cl.T = s->T;
+            cl.per_cu = per_cu;
             bt->classes.push_back(cl);
             members.emplace_back();
             c = (int)bt->classes.size() - 1;
         }
         members[c].push_back(i);
-        bt->classes[c].lds = std::max(bt->classes[c].lds, bt->items[i]->lds);
+        bt->classes[c].lds = std::max(bt->classes[c].lds, s->lds);
     }
     int dev = 0, cus = 256;
     HIP_TRY(hipGetDevice(&dev));
@@ -1076,30 +1070,75 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
     bt->allocs.push_back(v);
     bt->d_items = static_cast<SearchArgs *>(v);
     HIP_TRY(hipMemcpy(bt->d_items, host_items.data(), sizeof(SearchArgs) * count, hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&v, batch_queue_bytes() * std::max<size_t>(bt->classes.size(), 1)));
+    // counters: the queues first (aligned), then epoch and done per class
+    const int nc = (int)bt->classes.size();
+    const long long qints = (long long)(batch_queue_bytes() / sizeof(int)) * nc;
+    bt->state_ints = qints + 2ll * count;
+    HIP_TRY(hipMalloc(&v, sizeof(int) * bt->state_ints));
     bt->allocs.push_back(v);
-    bt->d_queues = static_cast<BatchQueue *>(v);
-    for (size_t c = 0; c < bt->classes.size(); ++c) {
+    bt->d_state = static_cast<int *>(v);
+    long long cursor = qints;
+    auto steps_of = [&](int i) {
+        const rcpsp_search_params &p = bt->items[i]->p;
+        return p.elite > 0 ? std::max(p.iterations, 1) : 1;
+    };
+    for (int c = 0; c < nc; ++c) {
         rcpsp_batch::Class &cl = bt->classes[c];
         std::vector<int> &m = members[c];
-        // largest instances first, so that the last ones to finish are short
+        // members with more iterations first (those of an iteration are a
+        // prefix), larger searches first within equal iteration counts
         std::stable_sort(m.begin(), m.end(), [&](int x, int y) {
+            const int sx = steps_of(x), sy = steps_of(y);
+            if (sx != sy) return sx > sy;
             const rcpsp_search *a = bt->items[x], *b = bt->items[y];
-            const long long wa = (long long)a->inst->n * a->p.searches * std::max(a->p.iterations, 1);
-            const long long wb = (long long)b->inst->n * b->p.searches * std::max(b->p.iterations, 1);
-            return wa > wb;
+            return (long long)a->inst->n * a->p.searches > (long long)b->inst->n * b->p.searches;
         });
         cl.count = (int)m.size();
+        const int max_steps = steps_of(m[0]);
+        std::vector<int> cumB(cl.count + 1, 0), act(max_steps, 0);
+        for (int j = 0; j < cl.count; ++j) cumB[j + 1] = cumB[j] + bt->items[m[j]]->p.searches;
+        for (int j = 0; j < cl.count; ++j)
+            for (int it = 0; it < steps_of(m[j]); ++it) act[it] = j + 1;
+        std::vector<long long> off(max_steps + 1);
+        off[0] = cl.count;
+        for (int it = 0; it < max_steps; ++it) off[it + 1] = off[it] + cumB[act[it]];
+        BatchClassArgs &A = cl.args;
+        A.items = bt->d_items;
+        A.count = cl.count;
+        A.max_steps = max_steps;
+        A.total = off[max_steps];
+        A.wait_ticks = kBatchWaitTicks;
+        int *d_order = nullptr, *d_cumB = nullptr, *d_act = nullptr;
+        long long *d_off = nullptr;
         HIP_TRY(hipMalloc(&v, sizeof(int) * m.size()));
         bt->allocs.push_back(v);
-        cl.d_order = static_cast<int *>(v);
-        HIP_TRY(hipMemcpy(cl.d_order, m.data(), sizeof(int) * m.size(), hipMemcpyHostToDevice));
+        d_order = static_cast<int *>(v);
+        HIP_TRY(hipMemcpy(d_order, m.data(), sizeof(int) * m.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc(&v, sizeof(int) * cumB.size()));
+        bt->allocs.push_back(v);
+        d_cumB = static_cast<int *>(v);
+        HIP_TRY(hipMemcpy(d_cumB, cumB.data(), sizeof(int) * cumB.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc(&v, sizeof(int) * act.size()));
+        bt->allocs.push_back(v);
+        d_act = static_cast<int *>(v);
+        HIP_TRY(hipMemcpy(d_act, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc(&v, sizeof(long long) * off.size()));
+        bt->allocs.push_back(v);
+        d_off = static_cast<long long *>(v);
+        HIP_TRY(hipMemcpy(d_off, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice));
+        A.order = d_order;
+        A.cumB = d_cumB;
+        A.act = d_act;
+        A.off = d_off;
+        A.q = reinterpret_cast<BatchQueue *>(reinterpret_cast<char *>(bt->d_state) + c * batch_queue_bytes());
+        A.epoch = bt->d_state + cursor;
+        A.done = bt->d_state + cursor + cl.count;
+        cursor += 2ll * cl.count;
         HIP_TRY(prepare_batch(cl.T, cl.nw, cl.dec, cl.lds));
-        const int per_cu = std::max(1, (int)(kMaxLds / (cl.lds + 2048)));
-        cl.grid = std::min(cl.count, per_cu * cus);
+        cl.grid = (int)std::min<long long>(A.total, (long long)cl.per_cu * cus);
     }
-    // one graph: queue reset, then every class's persistent launch on its own
-    // branch so that the classes run side by side
+    // one graph: clear the counters, then every class's persistent launch on
+    // its own branch so that the classes run side by side
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     std::vector<hipStream_t> side(bt->classes.size());
@@ -1111,7 +1150,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         (void)hipStreamDestroy(cs);
     };
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_batch_queue_reset(bt->d_queues, (int)bt->classes.size(), cs);
+    if (e == hipSuccess) e = launch_fill_zero(bt->d_state, bt->state_ints, cs);
     hipEvent_t fork = nullptr;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
     if (e == hipSuccess) {
@@ -1122,10 +1161,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         const rcpsp_batch::Class &cl = bt->classes[c];
         hipEvent_t done = nullptr;
         e = hipStreamWaitEvent(side[c], fork, 0);
-        if (e == hipSuccess)
-            e = launch_batch(bt->d_items, cl.d_order, cl.count, reinterpret_cast<BatchQueue *>(
-                                 reinterpret_cast<char *>(bt->d_queues) + c * batch_queue_bytes()),
-                             cl.grid, cl.T, cl.nw, cl.dec, cl.lds, side[c]);
+        if (e == hipSuccess) e = launch_batch(cl.args, cl.grid, cl.T, cl.nw, cl.dec, cl.lds, side[c]);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
         if (e == hipSuccess) {
             evs.push_back(done);
@@ -1143,6 +1179,20 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
     }
     bt->graph = g;
     HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+    return RCPSP_OK;
+}
+
+// Whether a run of the batch ended early (a dependency wait hit its limit).
+static rcpsp_status batch_check(rcpsp_batch *b, hipStream_t st) {
+    const size_t qb = batch_queue_bytes() * b->classes.size();
+    std::vector<char> q(qb);
+    HIP_TRY(hipMemcpyAsync(q.data(), b->d_state, qb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (size_t c = 0; c < b->classes.size(); ++c) {
+        int abort = 0;
+        std::memcpy(&abort, q.data() + c * batch_queue_bytes() + sizeof(unsigned long long), sizeof(int));
+        if (abort) return fail(RCPSP_E_DEVICE, "batch class %d: a dependency wait exceeded its limit", (int)c);
+    }
     return RCPSP_OK;
 }
 
@@ -1185,13 +1235,15 @@ extern "C" rcpsp_status rcpsp_batch_run_timed(rcpsp_batch *b, void *hip_stream, 
     (void)hipEventDestroy(t1);
     if (e != hipSuccess) return fail(RCPSP_E_DEVICE, "timed batch run: %s", hipGetErrorString(e));
     if (total_ms) *total_ms = ms;
-    return RCPSP_OK;
+    return batch_check(b, st);
 }
 
 extern "C" rcpsp_status rcpsp_batch_results(rcpsp_batch *b, int32_t index, rcpsp_search_result *res,
                                             void *hip_stream) {
     if (!b || !res) return fail(RCPSP_E_ARG, "null pointer");
     if (index < 0 || index >= (int32_t)b->items.size()) return fail(RCPSP_E_ARG, "index %d out of range", index);
+    rcpsp_status st = batch_check(b, (hipStream_t)hip_stream);
+    if (st != RCPSP_OK) return st;
     return rcpsp_search_results(b->items[index], res, hip_stream);
 }
 

@@ -1148,60 +1148,133 @@ __global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int ini
 
 // ---------------------------------------------------------------------------
 // Batches: many instances, each with its own search plan, in one persistent
-// launch per decoder/profile-width class.  A workgroup takes the next
-// instance from a queue (instances sorted by size, largest first), runs its
-// whole search (reset, initial records, every iteration of every search and
-// the exchange rounds, the rounds needing only this workgroup), then takes
-// the next one; it exits when the queue is empty.  Every instance's result
-// equals that of its own plan.
+// launch per class (decoder, profile width, threads, workgroups per CU).
+// Work is split into tasks taken from a queue in a fixed order: first one
+// set-up task per instance (reset, initial working-set records, first
+// exchange round), then, iteration by iteration, one task per (instance,
+// search) running that search's iteration.  A search task waits until the
+// instance's previous exchange round is done; the task that completes the
+// last search of an iteration runs the instance's next round.  Every task a
+// task waits for comes earlier in the queue and is held by a running
+// workgroup, so the waits always end; a wait that exceeds a time limit sets
+// the abort flag, and every workgroup then leaves.  Every instance's result
+// equals that of its own plan: the searches and rounds see the same states
+// in the same order.
 
 struct BatchQueue {
-    int next;
-    int pad[15];
+    unsigned long long next;
+    int abort;
+    int pad[13];
 };
 
+__device__ inline int upper_index_ll(const long long *a, int n, long long x) {
+    // largest i in [0, n) with a[i] <= x (a ascending, a[0] <= x)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int upper_index(const int *a, int n, int x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+static_assert(sizeof(SearchArgs) + sizeof(StepShared) + 4 * sizeof(int) + 64 <= kBatchStaticLds,
+              "batch kernel static LDS");
+
 template <int NW, int T, int DEC>
-__global__ __launch_bounds__(T) void k_batch(const SearchArgs *items, const int *order, int count, BatchQueue *q) {
+__global__ __launch_bounds__(T) void k_batch(BatchClassArgs C) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ SearchArgs A;
     __shared__ StepShared ss;
-    __shared__ int cur;
+    __shared__ int task[4];
+    const int tid = threadIdx.x;
     for (;;) {
-        if (threadIdx.x == 0) cur = atomicAdd(&q->next, 1);
+        if (tid == 0) {
+            const long long t = (long long)atomicAdd(&C.q->next, 1ull);
+            int ok = t < C.total && __hip_atomic_load(&C.q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+            int j = 0, it = -1, b = 0;
+            if (ok && t >= C.count) {
+                it = upper_index_ll(C.off, C.max_steps + 1, t);
+                const int r = (int)(t - C.off[it]);
+                j = upper_index(C.cumB, C.act[it] + 1, r);
+                b = r - C.cumB[j];
+                // the instance's previous exchange round (or its set-up)
+                const long long t0 = (long long)wall_clock64();
+                while (__hip_atomic_load(&C.epoch[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < it + 1) {
+                    if ((long long)wall_clock64() - t0 > C.wait_ticks ||
+                        __hip_atomic_load(&C.q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        atomicExch(&C.q->abort, 1);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            } else if (ok) {
+                j = (int)t;
+            }
+            task[0] = ok; task[1] = j; task[2] = it; task[3] = b;
+        }
         __syncthreads();
-        const int c = cur;
-        __syncthreads();
-        if (c >= count) break;
+        const int ok = task[0], j = task[1], it = task[2], b = task[3];
+        if (!ok) break;
+        __threadfence();
         {
-            const uint32_t *src = reinterpret_cast<const uint32_t *>(items + order[c]);
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(C.items + C.order[j]);
             uint32_t *dst = reinterpret_cast<uint32_t *>(&A);
-            for (int i = threadIdx.x; i < (int)(sizeof(SearchArgs) / 4); i += T) dst[i] = src[i];
+            for (int i = tid; i < (int)(sizeof(SearchArgs) / 4); i += T) dst[i] = src[i];
         }
         __syncthreads();
         Sh S = make_sh(lds, A.D, A.Ly);
-        uint16_t *scratch16 = reinterpret_cast<uint16_t *>(S.region);
-        const int units = A.B > A.NF ? A.B : A.NF;
-        for (int i = 0; i < units; ++i) reset_unit<T>(A, i, scratch16);
+        const int steps = A.NF > 0 ? (A.iters > 0 ? A.iters : 1) : 1;
+        if (it < 0) {
+            // set-up: reset every search and record, decode the records, first round
+            uint16_t *scratch16 = reinterpret_cast<uint16_t *>(S.region);
+            const int units = A.B > A.NF ? A.B : A.NF;
+            for (int i = 0; i < units; ++i) reset_unit<T>(A, i, scratch16);
+            stage_blob<T>(lds, A.D, A.Ly);
+            __syncthreads();
+            if (A.NF > 0) {
+                for (int k = 0; k < A.NF; ++k) decode_record<NW, T, DEC>(A, S, k);
+                exchange_round<T>(A, 0, 1, reinterpret_cast<int *>(S.region));
+            }
+            if (tid == 0) __hip_atomic_store(&C.epoch[j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            continue;
+        }
         stage_blob<T>(lds, A.D, A.Ly);
         __syncthreads();
-        if (A.NF > 0) {
-            for (int k = 0; k < A.NF; ++k) decode_record<NW, T, DEC>(A, S, k);
-            exchange_round<T>(A, 0, 1, reinterpret_cast<int *>(S.region));
-            for (int it = 0; it < A.iters; ++it) {
-                for (int b = 0; b < A.B; ++b) search_step<NW, T, DEC, false>(A, S, ss, b, it, 1);
-                if (it < A.iters - 1) exchange_round<T>(A, it & 1, 0, reinterpret_cast<int *>(S.region));
-            }
-            if (A.iters == 0)
-                for (int b = 0; b < A.B; ++b) search_step<NW, T, DEC, false>(A, S, ss, b, 0, 0);
-        } else {
-            for (int b = 0; b < A.B; ++b) search_step<NW, T, DEC, false>(A, S, ss, b, 0, A.iters);
+        if (A.NF > 0) search_step<NW, T, DEC, false>(A, S, ss, b, it, A.iters > 0 ? 1 : 0);
+        else search_step<NW, T, DEC, false>(A, S, ss, b, 0, A.iters);
+        if (tid == 0) {
+            const int old = __hip_atomic_fetch_add(&C.done[j], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            task[0] = old + 1 == (it + 1) * A.B && A.NF > 0 && it < steps - 1;
+        }
+        __syncthreads();
+        const int last = task[0];
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            exchange_round<T>(A, it & 1, 0, reinterpret_cast<int *>(S.region));
+            if (tid == 0) __hip_atomic_store(&C.epoch[j], it + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
         }
     }
 }
 
-// Queue reset (a kernel, so that graph replays never record a memset).
-__global__ void k_batch_queue_reset(BatchQueue *q, int n) {
-    if (threadIdx.x < n) q[threadIdx.x].next = 0;
+// Clear n ints (a kernel, so that graph replays never record a memset).
+__global__ void k_fill_zero(int *p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1294,16 +1367,27 @@ hipError_t prepare_batch(int T, int nw, int dec, size_t lds) {
     return hipSuccess;
 }
 
-hipError_t launch_batch(const SearchArgs *items, const int *order, int count, BatchQueue *q, int grid, int T, int nw,
-                        int dec, size_t lds, hipStream_t st) {
+hipError_t batch_occupancy(int T, int nw, int dec, size_t lds, int *per_cu) {
+    *per_cu = 0;
     RCPSP_DISPATCH(nw, T, dec, {
-        hipLaunchKernelGGL((k_batch<NW_, T_, DEC_>), dim3(grid), dim3(T_), lds, st, items, order, count, q);
+        hipError_t e = set_lds(k_batch<NW_, T_, DEC_>, lds);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<NW_, T_, DEC_>, T_, lds);
+        if (e != hipSuccess) return e;
+    });
+    return hipSuccess;
+}
+
+hipError_t launch_batch(const BatchClassArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipLaunchKernelGGL((k_batch<NW_, T_, DEC_>), dim3(grid), dim3(T_), lds, st, C);
     });
     return hipGetLastError();
 }
 
-hipError_t launch_batch_queue_reset(BatchQueue *q, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_queue_reset, dim3(1), dim3(64), 0, st, q, n);
+hipError_t launch_fill_zero(int *p, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

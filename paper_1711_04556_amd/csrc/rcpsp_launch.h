@@ -26,10 +26,29 @@ size_t round_lds_bytes(int B, int NF);
 hipError_t prepare_search(int T, int nw, int dec, size_t lds, int B, int NF);
 
 struct BatchQueue;
+
+// Static LDS of the batch kernel (its plan arguments and step scratch) is below this.
+constexpr int kBatchStaticLds = 1024;
+
+// One class of a batch: the tasks of its members (see k_batch).
+struct BatchClassArgs {
+    const SearchArgs *items;   // every plan of the batch
+    const int *order;          // [count] plan index of member j; members sorted by steps, descending
+    const int *cumB;           // [count + 1] searches of members before j
+    const long long *off;      // [max_steps + 1] first task of each iteration (set-up tasks come first)
+    const int *act;            // [max_steps] members taking part in iteration it (a prefix of order)
+    int *epoch;                // [count] 1 + exchange rounds completed (0: not set up)
+    int *done;                 // [count] search tasks completed
+    BatchQueue *q;             // next task, abort flag
+    int count, max_steps;
+    long long total;           // tasks
+    long long wait_ticks;      // limit of one wait, in wall-clock ticks (100 MHz)
+};
+
 size_t batch_queue_bytes();
 hipError_t prepare_batch(int T, int nw, int dec, size_t lds);
-hipError_t launch_batch(const SearchArgs *items, const int *order, int count, BatchQueue *q, int grid, int T, int nw,
-                        int dec, size_t lds, hipStream_t st);
-hipError_t launch_batch_queue_reset(BatchQueue *q, int n, hipStream_t st);
+hipError_t batch_occupancy(int T, int nw, int dec, size_t lds, int *per_cu);
+hipError_t launch_batch(const BatchClassArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t launch_fill_zero(int *p, long long n, hipStream_t st);
 
 }  // namespace rcpsp

@@ -309,16 +309,19 @@ def _batch_case():
 
 
 def test_batch_matches_oracle_and_plans(rc):
-    """Mixed sizes, decoders, working-set and independent searches in one
-    batch: every instance's results equal the oracle's and its own plan's."""
+    """Mixed sizes, decoders, iteration counts (0 and 1 included), threads,
+    working-set and independent searches in one batch: every instance's
+    results equal the oracle's and its own plan's."""
     insts = _batch_case()
     gis, params = [], []
     for i, inst in enumerate(insts):
         dec = TIME if i % 3 else CAP
         gis.append(rc.Instance(inst, eval=dec))
         elite = 0 if i % 4 == 1 else 4
-        params.append(rc.search_params(6 + i % 3, 30, 15, searches=6 + i, elite=elite, phi_max=2, phi_steps=4,
-                                       threads=64, seed=11 + i))
+        iters = [15, 9, 15, 1, 0, 15, 4][i]
+        threads = [64, 64, 128, 64, 64, 128, 64][i]
+        params.append(rc.search_params(6 + i % 3, 30, iters, searches=6 + i, elite=elite, phi_max=2, phi_steps=4,
+                                       threads=threads, seed=11 + i))
     bt = rc.Batch(gis, params)
     info = bt.info
     assert info["instances"] == len(insts) and info["classes"] >= 2
@@ -332,7 +335,7 @@ def test_batch_matches_oracle_and_plans(rc):
         _compare_search(g, o, elite=p.elite)
         plan = rc.tabu_search(gis[i], swap_range=p.swap_range, tabu_len=p.tabu_len, iterations=p.iterations,
                               searches=p.searches, elite=p.elite, phi_max=p.phi_max, phi_steps=p.phi_steps,
-                              threads=64, seed=p.seed)
+                              threads=p.threads, seed=p.seed)
         _compare_search(g, plan, elite=p.elite)
     # a second run gives the same results
     first = [bt.results(i)["trajectory"] for i in range(len(insts))]
