@@ -1,11 +1,19 @@
 """Benchmark: SSGS neighbour evaluations per second of the tabu search on one
-MI355X, for 480 seeded searches x 1000 iterations on one 120-activity
-instance (4 resources, resource strength 0.3, swap range 20, tabu list 329,
-working set of 16 records, phi_max 3, phi_steps 20).
+MI355X.
 
-One step = one whole search run from its initial state (every iteration of
-every search plus the working-set exchange rounds), replayed from a captured
-HIP graph; the instance and all search state are resident in HBM.
+Headline (plain form): 480 seeded searches x 1000 iterations on one
+120-activity instance (4 resources, resource strength 0.3, swap range 20,
+tabu list 329, working set of 16 records, phi_max 3, phi_steps 20).  One step
+= one whole search run from its initial state (every iteration of every
+search plus the working-set exchange rounds), replayed from a captured HIP
+graph; the instance and all search state are resident in HBM.
+
+Batched leg: 1024 instances of 30/60/120 activities (resource factor and
+strength varied), 32 searches each with a working set of 16, in one
+persistent launch per class under a captured graph, against the plain form
+(one plan per instance: a workgroup per search, a launch per iteration and
+exchange round) on an evenly spaced sample of the same instances, with the
+results of both compared.
 
 Prints one JSON line on stdout (details on stderr)."""
 import argparse
@@ -22,6 +30,10 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit 
 
 WORKLOAD = dict(swap_range=20, tabu_len=329, iterations=1000, searches=480, elite=16, phi_max=3, phi_steps=20,
                 seed=2)
+# batched leg: swap range and tabu list by size (N incl. dummies); the tabu
+# list is max(60, 0.15 x potential swaps), as for the plain workload
+BATCH = dict(count=1024, base_seed=3000, searches=32, elite=16, phi_max=3, phi_steps=20, iterations=100)
+BATCH_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329)}
 
 
 def log(*a):
@@ -46,6 +58,83 @@ def cpu_baseline(inst, decoder, iters=2):
                        f"({ev} evaluations in {dt:.1f} s, one host thread)")
 
 
+def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
+    import torch
+    t0 = time.perf_counter()
+    insts = synth.mixed_batch(BATCH["count"], BATCH["base_seed"])
+    gis = [rcpsp.Instance(i) for i in insts]
+    params = []
+    for k, inst in enumerate(insts):
+        d, tl = BATCH_DELTA_TL[inst.n]
+        params.append(rcpsp.search_params(d, tl, BATCH["iterations"], searches=BATCH["searches"],
+                                          elite=BATCH["elite"], phi_max=BATCH["phi_max"],
+                                          phi_steps=BATCH["phi_steps"], record_trajectory=False,
+                                          seed=BATCH["base_seed"] + k))
+    t1 = time.perf_counter()
+    params, tuning = rcpsp.batch_autotune(gis, params, trial_iterations=5, sample=64, stream=stream)
+    tuning["seconds"] = time.perf_counter() - t1
+    log("batch autotune", tuning)
+    bt = rcpsp.Batch(gis, params, stream)
+    info = bt.info
+    log("batch", info, f"set-up {time.perf_counter() - t0:.1f} s")
+    for _ in range(warmup):
+        bt.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bt.run(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = [bt.results(k, stream, orders=False, trajectory=False) for k in range(len(insts))]
+    evals = sum(r["total_evaluations"] for r in res)
+    device_ms = bt.run_timed(stream)
+    value = evals * steps / dt
+    log(f"batched: {dt / steps * 1e3:.1f} ms/step, {evals} evaluations/step, {value:.4g} evals/s, "
+        f"device {device_ms:.1f} ms")
+    # plain form on an evenly spaced sample: one plan per instance, run one after the other
+    sample = list(range(0, len(insts), max(1, len(insts) // plain_sample)))[:plain_sample]
+    p_ms = 0.0
+    p_ev = 0
+    exact = True
+    for k in sample:
+        q = type(params[k]).from_buffer_copy(params[k])
+        q.threads = 0
+        q.profile_len = 0
+        plan = rcpsp.SearchPlan(gis[k], q, stream)
+        plan.run(stream)
+        timed = plan.run_timed(stream)
+        r = plan.results(stream, orders=False, trajectory=False)
+        plan.close()
+        p_ms += timed["total_ms"]
+        p_ev += r["total_evaluations"]
+        exact = exact and r["total_evaluations"] == res[k]["total_evaluations"] and \
+            r["global_best"] == res[k]["global_best"] and (r["best_makespan"] == res[k]["best_makespan"]).all()
+    plain = p_ev / (p_ms * 1e-3)
+    sample_ev = sum(res[k]["total_evaluations"] for k in sample)
+    log(f"plain sample: {len(sample)} instances, {p_ms:.1f} ms, {plain:.4g} evals/s, results equal: {exact}")
+    cp = [g.info["critical_path"] for g in gis]
+    dev = [100.0 * (r["global_best"] - c) / c for r, c in zip(res, cp)]
+    return {
+        "workload": f"{len(insts)} instances of 30/60/120 activities (4 resources, RF in .25..1, RS in .2..0.7), "
+                    f"{BATCH['searches']} searches each, working set {BATCH['elite']}, {BATCH['iterations']} "
+                    f"iterations, swap range 8/14/20, tabu list 60/110/329, phi_max 3, phi_steps 20",
+        "value": value,
+        "unit": "evals/s",
+        "ms_per_step": dt / steps * 1e3,
+        "steps": steps,
+        "evaluations_per_step": evals,
+        "device_ms_per_step": device_ms,
+        "plain_value": plain,
+        "plain_sample": f"{len(sample)} evenly spaced instances ({sample_ev} evaluations), one plan each, "
+                        f"device time summed",
+        "batched_vs_plain": value / plain,
+        "results_equal_plain": bool(exact),
+        "mean_cpm_dev_pct": sum(dev) / len(dev),
+        "classes": info,
+        "autotune": tuning,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +146,8 @@ def main():
     ap.add_argument("--profile-len", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--full-decode", action="store_true", help="decode every candidate from position 0")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--batch-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the searches would shard across "
@@ -166,9 +257,12 @@ def main():
             "ops_per_evaluation": work / evals,
             "launches_per_step": n_launch,
         },
+        "batched": None,
         "cpu_baseline": None,
     }
     plan.close()
+    if not args.no_batch:
+        out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, min(args.warmup, 1))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, dec)
         log("cpu baseline", out["cpu_baseline"])

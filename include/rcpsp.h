@@ -255,6 +255,27 @@ rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_param
                             int32_t trial_iterations, void *hip_stream, rcpsp_search_params *out,
                             rcpsp_tuning *info);
 
+/* Decoder and threads per search for every instance of a batch (the batch
+ * counterpart of rcpsp_autotune).  Instances are grouped by (N, M); for each
+ * group, up to `sample` evenly spaced members run as a batch of
+ * trial_iterations iterations under every candidate (decoder time- or
+ * capacity-indexed where the instance allows it, threads 64/128/256; a
+ * nonzero eval or threads in params fixes that choice), and the candidate
+ * with the most evaluations per device second is written to every member of
+ * the group.  Results never depend on the choice of threads; the decoder is
+ * part of the result (the two decoders are different functions).
+ *   out   [count] params[i] with eval and threads filled in
+ *   info  optional: the first 8 groups and their choices
+ * Errors: RCPSP_E_TOO_LARGE when no candidate fits a group. */
+typedef struct {
+    int32_t groups, trials;
+    int32_t group_n[8], group_m[8], group_members[8], group_eval[8], group_threads[8];
+    double group_evals_per_s[8];
+} rcpsp_batch_tuning;
+rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, int32_t count,
+                                  const rcpsp_search_params *params, int32_t trial_iterations, int32_t sample,
+                                  void *hip_stream, rcpsp_search_params *out, rcpsp_batch_tuning *info);
+
 const char *rcpsp_last_error(void);
 const char *rcpsp_version(void);
 

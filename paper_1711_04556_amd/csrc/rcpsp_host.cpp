@@ -1261,3 +1261,107 @@ extern "C" rcpsp_status rcpsp_batch_get_info(const rcpsp_batch *b, rcpsp_batch_i
     }
     return RCPSP_OK;
 }
+
+extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, int32_t count,
+                                            const rcpsp_search_params *params, int32_t trial_iterations,
+                                            int32_t sample, void *hip_stream, rcpsp_search_params *out,
+                                            rcpsp_batch_tuning *info) {
+    if (!inst || !params || !out || count < 1) return fail(RCPSP_E_ARG, "null pointer or empty batch");
+    if (trial_iterations < 1 || sample < 1) return fail(RCPSP_E_ARG, "trial_iterations and sample must be >= 1");
+    for (int i = 0; i < count; ++i)
+        if (!inst[i]) return fail(RCPSP_E_ARG, "null instance %d", i);
+    // groups by (N, M), in order of first appearance
+    std::vector<std::pair<int, int>> keys;
+    std::vector<std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) {
+        const std::pair<int, int> k(inst[i]->n, inst[i]->m);
+        size_t g = 0;
+        while (g < keys.size() && keys[g] != k) ++g;
+        if (g == keys.size()) {
+            keys.push_back(k);
+            groups.emplace_back();
+        }
+        groups[g].push_back(i);
+        out[i] = params[i];
+    }
+    if (info) *info = rcpsp_batch_tuning{};
+    int trials = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const std::vector<int> &mem = groups[g];
+        const int ns = std::min<int>(sample, (int)mem.size());
+        std::vector<const rcpsp_instance *> si(ns);
+        std::vector<rcpsp_search_params> sp(ns);
+        for (int k = 0; k < ns; ++k) {
+            const int i = mem[(size_t)k * mem.size() / ns];
+            si[k] = inst[i];
+            sp[k] = params[i];
+            sp[k].iterations = trial_iterations;
+            sp[k].record_trajectory = 0;
+            sp[k].count_work = 0;
+        }
+        const rcpsp_search_params &p0 = params[mem[0]];
+        bool time_ok = true;
+        for (int k = 0; k < ns; ++k) time_ok = time_ok && si[k]->desc.nw > 0;
+        std::vector<int> evals, threads;
+        if (p0.eval) evals.push_back(p0.eval);
+        else {
+            if (time_ok) evals.push_back(kEvalTime);
+            evals.push_back(kEvalCapacity);
+        }
+        if (p0.threads) threads.push_back(p0.threads);
+        else threads = {64, 128, 256};
+        bool found = false;
+        double best_rate = 0.0;
+        int best_eval = 0, best_T = 0;
+        for (int ev : evals) {
+            for (int T : threads) {
+                for (auto &q : sp) {
+                    q.eval = ev;
+                    q.threads = T;
+                }
+                rcpsp_batch *bt = nullptr;
+                rcpsp_status st = rcpsp_batch_create(si.data(), ns, sp.data(), hip_stream, &bt);
+                if (st == RCPSP_E_TOO_LARGE) continue;
+                if (st != RCPSP_OK) return st;
+                double ms = 0.0;
+                long long ev_total = 0;
+                st = rcpsp_batch_run(bt, hip_stream);
+                if (st == RCPSP_OK) st = rcpsp_batch_run_timed(bt, hip_stream, &ms);
+                for (int k = 0; st == RCPSP_OK && k < ns; ++k) {
+                    rcpsp_search_result r{};
+                    st = rcpsp_batch_results(bt, k, &r, hip_stream);
+                    ev_total += r.total_evaluations;
+                }
+                rcpsp_batch_destroy(bt);
+                if (st != RCPSP_OK) return st;
+                ++trials;
+                const double rate = ms > 0.0 ? (double)ev_total / (ms * 1e-3) : 0.0;
+                if (!found || rate > best_rate) {
+                    found = true;
+                    best_rate = rate;
+                    best_eval = ev;
+                    best_T = T;
+                }
+            }
+        }
+        if (!found) return fail(RCPSP_E_TOO_LARGE, "no decoder/threads candidate fits instances of N=%d, M=%d",
+                                keys[g].first, keys[g].second);
+        for (int i : mem) {
+            out[i].eval = best_eval;
+            out[i].threads = best_T;
+        }
+        if (info && g < 8) {
+            info->group_n[g] = keys[g].first;
+            info->group_m[g] = keys[g].second;
+            info->group_members[g] = (int32_t)mem.size();
+            info->group_eval[g] = best_eval;
+            info->group_threads[g] = best_T;
+            info->group_evals_per_s[g] = best_rate;
+        }
+    }
+    if (info) {
+        info->groups = (int32_t)groups.size();
+        info->trials = trials;
+    }
+    return RCPSP_OK;
+}

@@ -67,6 +67,12 @@ class rcpsp_batch_info(ctypes.Structure):
                                           "class_lds_bytes")]
 
 
+class rcpsp_batch_tuning(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int32), ("trials", ctypes.c_int32)] + [
+        (n, ctypes.c_int32 * 8) for n in ("group_n", "group_m", "group_members", "group_eval", "group_threads")] + [
+        ("group_evals_per_s", ctypes.c_double * 8)]
+
+
 class rcpsp_search_config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches")]
@@ -129,6 +135,9 @@ def lib():
     L.rcpsp_batch_get_info.restype = ctypes.c_int
     L.rcpsp_batch_destroy.argtypes = [vp]
     L.rcpsp_batch_destroy.restype = None
+    L.rcpsp_batch_autotune.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(rcpsp_search_params), i32, i32, vp,
+                                       ctypes.POINTER(rcpsp_search_params), ctypes.POINTER(rcpsp_batch_tuning)]
+    L.rcpsp_batch_autotune.restype = ctypes.c_int
     L.rcpsp_last_error.argtypes = []
     L.rcpsp_last_error.restype = ctypes.c_char_p
     L.rcpsp_version.argtypes = []
@@ -310,6 +319,30 @@ def _results(fn, handle_args, params, n, stream, orders=True, trajectory=True) -
     out["overflow_decodes"] = res.overflow_decodes
     out["total_work"] = res.total_work
     return out
+
+
+def batch_autotune(instances: Sequence["Instance"], params, trial_iterations: int = 5, sample: int = 64,
+                   stream=None):
+    """rcpsp_batch_autotune: returns (params list with eval/threads chosen, tuning dict)."""
+    if not isinstance(params, (list, tuple)):
+        params = [params] * len(instances)
+    n = len(instances)
+    hs = (ctypes.c_void_p * n)(*[i.h.value for i in instances])
+    ps = (rcpsp_search_params * n)(*params)
+    out = (rcpsp_search_params * n)()
+    info = rcpsp_batch_tuning()
+    _check(lib().rcpsp_batch_autotune(hs, n, ps, trial_iterations, sample, _stream_ptr(stream), out,
+                                      ctypes.byref(info)))
+    g = info.groups
+    d = {"groups": g, "trials": info.trials}
+    for k in ("group_n", "group_m", "group_members", "group_eval", "group_threads", "group_evals_per_s"):
+        d[k] = list(getattr(info, k))[:min(g, 8)]
+    res = []
+    for i in range(n):
+        q = rcpsp_search_params()
+        ctypes.memmove(ctypes.byref(q), ctypes.byref(out[i]), ctypes.sizeof(q))
+        res.append(q)
+    return res, d
 
 
 class Batch:
