@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSGS neighbour evals/s (batched vs plain) at bit-exact makespan; p50/p99 latency"
 PEAK_INT_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
+TRAFFIC_PROBE_BYTES = 1 << 30
 
 WORKLOAD = dict(swap_range=20, tabu_len=329, iterations=1000, searches=480, elite=16, phi_max=3, phi_steps=20,
                 seed=2)
@@ -38,6 +39,33 @@ BATCH_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329)}
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_search_plain480_ti_hbm.txt")
+TRAFFIC_SOURCES = ["paper_1711_04556_amd/csrc/rcpsp_kernels.hip", "paper_1711_04556_amd/csrc/rcpsp_internal.h",
+                   "paper_1711_04556_amd/csrc/rcpsp_host.cpp"]
+
+
+def measured_traffic(cfg):
+    """HBM bytes per iteration-kernel launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the kernel
+    sources or the plan differ from those the counters were taken on."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if ": " in line and not line.startswith((" ", "#", "|")):
+                k, v = line.rstrip("\n").split(": ", 1)
+                kv[k] = v
+        h = hashlib.sha256()
+        for f in TRAFFIC_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        plan = f"eval={cfg['eval']} threads={cfg['threads']} profile_len={cfg['profile_len']}"
+        if kv.get("sources_sha256") != h.hexdigest() or kv.get("plan") != plan:
+            return None
+        return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(inst, decoder, iters=2):
@@ -147,6 +175,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--full-decode", action="store_true", help="decode every candidate from position 0")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for HBM counter runs: one elementwise kernel over 1 GiB (read 1 GiB, write 1 GiB), "
+                         "then one run of the headline plan")
     ap.add_argument("--batch-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -177,6 +208,22 @@ def main():
         tuning["seconds"] = time.perf_counter() - t0
         log("autotune", tuning)
     kw.update(eval=params.eval, threads=params.threads, profile_len=params.profile_len)
+
+    if args.traffic_probe:
+        # calibration kernel of known traffic, then the plan's kernels once
+        x = torch.zeros(TRAFFIC_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.bitwise_not(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        plan = rcpsp.SearchPlan(gi, params, stream)
+        plan.run(stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": TRAFFIC_PROBE_BYTES, "plan": plan.config}),
+              flush=True)
+        plan.close()
+        return
 
     plan = rcpsp.SearchPlan(gi, params, stream)
     cfg = plan.config
@@ -251,7 +298,8 @@ def main():
             "peak": PEAK_INT_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved / PEAK_INT_OPS,
-            "traffic": None,
+            "traffic": measured_traffic(cfg),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "kernel": "k_search (iteration kernel)",
             "avg_launch_ms": avg_ms,
             "ops_per_evaluation": work / evals,
