@@ -488,7 +488,8 @@ static void read_record(const orc_inst *I, const orc_params *p, int b, search_t 
     S->C_imp = S->C_cur;
     if (S->C_cur < S->C_best) { S->C_best = S->C_cur; memcpy(S->W_best, S->W_cur, sizeof(int) * n); }
     S->it_read = 0;
-    S->I_assigned = orc_iterations_assigned(p->iterations, R->C, elite_min(F, p->elite), R->IC);
+    S->I_assigned = orc_iterations_assigned(p->i_block > 0 ? p->i_block : p->iterations, R->C,
+                                            elite_min(F, p->elite), R->IC);
     S->slot = k;
 }
 

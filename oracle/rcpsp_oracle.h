@@ -102,6 +102,8 @@ typedef struct {
     int phi_steps;    /* random feasible swaps per diversification */
     int decoder;      /* 1 time-indexed, 2 capacity-indexed */
     uint64_t seed;
+    int i_block;      /* I_block of eq. 8 when the search is cut short (a time
+                         budget) before its iteration allowance; 0 = iterations */
 } orc_params;
 
 typedef struct {

@@ -469,3 +469,26 @@ def test_cooperative_search_invariants(dec):
     for k in range(4):
         assert r1["elite_makespan"][k] == o.decode(r1["elite_order"][k], dec)
         assert o.is_feasible_order(r1["elite_order"][k])
+
+
+@pytest.mark.parametrize("dec", [oracle.TIME, oracle.CAPACITY])
+def test_cut_short_search_is_prefix_of_full_allowance(dec):
+    """A search stopped after K iterations (a time budget) while eq. 8 keeps
+    the full allowance I_block = M: its trajectory is the first K rows of the
+    search run for all M iterations, and i_block = iterations is the default."""
+    inst = synth.generate(30, 4, 10, 0.5, rs=0.3, seed=22)
+    o = oracle.Oracle(inst)
+    kw = dict(delta=8, tabu_len=40, searches=10, elite=4, phi_max=2, phi_steps=5, decoder=dec, seed=4)
+    full = o.tabu_search(iterations=60, **kw)
+    same = o.tabu_search(iterations=60, i_block=60, **kw)
+    for k in full:
+        if full[k] is not None:
+            assert np.array_equal(full[k], same[k]), k
+    differs = False
+    for K in (1, 7, 23, 59):
+        cut = o.tabu_search(iterations=K, i_block=60, **kw)
+        assert np.array_equal(cut["trajectory"], full["trajectory"][:, :K])
+        plain = o.tabu_search(iterations=K, **kw)
+        differs = differs or not np.array_equal(plain["trajectory"], cut["trajectory"])
+    # the allowance changes eq. 8's assignment, hence the exchange pattern
+    assert differs
