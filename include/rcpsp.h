@@ -255,6 +255,71 @@ rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_param
                             int32_t trial_iterations, void *hip_stream, rcpsp_search_params *out,
                             rcpsp_tuning *info);
 
+/* Serving (requests admitted as they arrive).  A server owns a device arena
+ * for search state and a host thread that runs the device in time slices:
+ * at each slice boundary it admits queued requests in arrival order while
+ * the arena has room for their state and fewer than max_active are
+ * resident, then launches one persistent kernel per class (decoder, profile
+ * width, threads per search) that sets up the new requests and advances
+ * every resident request iteration by iteration, each at its own pace.  A
+ * request ends at the first iteration boundary where its iteration
+ * allowance is used up, its time budget (counted from admission) has passed,
+ * every search has stopped, the working set reached the critical path, or
+ * it was cancelled.  Its results equal those of a plain run with
+ * iterations = the request's `iterations` status field, except that eq. 8
+ * keeps the full allowance (params.iterations) as I_block.  State stays
+ * resident until rcpsp_server_release.  All entry points are thread-safe.
+ * Errors: RCPSP_E_TOO_LARGE (submit) for a request whose state or
+ * workgroup can never fit; RCPSP_E_DEVICE when a slice failed, after which
+ * the server accepts nothing more. */
+typedef struct rcpsp_server rcpsp_server;
+typedef struct {
+    int32_t max_active;     /* resident requests at most (0 = 256) */
+    int32_t slice_us;       /* device time between admission points (0 = 2000) */
+    int64_t arena_bytes;    /* device memory for search state (0 = 2 GiB) */
+} rcpsp_server_params;
+enum { RCPSP_REQ_QUEUED = 0, RCPSP_REQ_RUNNING = 1, RCPSP_REQ_DONE = 2, RCPSP_REQ_FAILED = 3 };
+typedef struct {
+    int32_t state;            /* RCPSP_REQ_* */
+    int32_t best_makespan;    /* done: minimum over searches and working set */
+    int32_t iterations;       /* done: search steps per search (see above) */
+    int32_t error;            /* failed: status */
+    int64_t evaluations;      /* done */
+    int64_t submit_ns, admit_ns, done_ns;  /* rcpsp_server_now_ns clock; done_ns = end
+                                              of the iteration that ended the search */
+    int64_t seen_ns;          /* when the host loop saw the end (result available) */
+} rcpsp_request_status;
+typedef struct {
+    int64_t submitted, admitted, completed, slices;
+    double busy_ms;           /* summed wall time of slices */
+    int64_t evaluations;      /* of completed requests */
+    int32_t resident, queued;
+    int64_t arena_used, arena_bytes;
+} rcpsp_server_stats;
+rcpsp_status rcpsp_server_create(const rcpsp_server_params *params, rcpsp_server **out);
+/* Queue a solve (non-blocking).  params: as for a search plan
+ * (record_trajectory allowed; count_work, threads and profile_len as
+ * usual); budget_us: wall-time budget from admission (0 = none).
+ * The instance must outlive the request. */
+rcpsp_status rcpsp_server_submit(rcpsp_server *s, const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                 int64_t budget_us, int64_t *ticket);
+rcpsp_status rcpsp_server_poll(rcpsp_server *s, int64_t ticket, rcpsp_request_status *out);
+/* Full results of a finished request (as rcpsp_search_results). */
+rcpsp_status rcpsp_server_results(rcpsp_server *s, int64_t ticket, rcpsp_search_result *res);
+/* Cancel: a queued request is dropped (state FAILED, error RCPSP_E_ARG); a
+ * running one ends at its next iteration boundary. */
+rcpsp_status rcpsp_server_cancel(rcpsp_server *s, int64_t ticket);
+/* Free a finished or failed request's state and forget its ticket. */
+rcpsp_status rcpsp_server_release(rcpsp_server *s, int64_t ticket);
+/* Block until no request is queued or running; RCPSP_E_DEVICE if a slice
+ * failed, RCPSP_E_ARG if timeout_ms (> 0) passed first. */
+rcpsp_status rcpsp_server_drain(rcpsp_server *s, int64_t timeout_ms);
+rcpsp_status rcpsp_server_get_stats(rcpsp_server *s, rcpsp_server_stats *out);
+int64_t rcpsp_server_now_ns(void);
+/* Stops the host thread after the running slice; requests still queued or
+ * running are dropped. */
+void rcpsp_server_destroy(rcpsp_server *s);
+
 /* Decoder and threads per search for every instance of a batch (the batch
  * counterpart of rcpsp_autotune).  Instances are grouped by (N, M); for each
  * group, up to `sample` evenly spaced members run as a batch of

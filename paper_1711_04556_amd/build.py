@@ -9,9 +9,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librcpsp.so")
-SOURCES = [os.path.join(CSRC, "rcpsp_host.cpp"), os.path.join(CSRC, "rcpsp_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "rcpsp_host.cpp"), os.path.join(CSRC, "rcpsp_serve.cpp"),
+           os.path.join(CSRC, "rcpsp_kernels.hip")]
 HEADERS = [os.path.join(ROOT, "include", "rcpsp.h"), os.path.join(CSRC, "rcpsp_internal.h"),
-           os.path.join(CSRC, "rcpsp_launch.h")]
+           os.path.join(CSRC, "rcpsp_launch.h"), os.path.join(CSRC, "rcpsp_runtime.h")]
 
 
 def hipcc() -> str:
@@ -24,7 +25,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 into paper_1711_04556_amd/librcpsp.so."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-o", tmp] + SOURCES
     if verbose:

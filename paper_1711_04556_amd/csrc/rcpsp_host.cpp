@@ -14,10 +14,11 @@
 #include "rcpsp.h"
 #include "rcpsp_internal.h"
 #include "rcpsp_launch.h"
+#include "rcpsp_runtime.h"
 
 using namespace rcpsp;
 
-namespace {
+namespace rcpsp {
 
 thread_local std::string g_err;
 
@@ -31,20 +32,16 @@ rcpsp_status fail(rcpsp_status st, const char *fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(expr)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail(e_ == hipErrorOutOfMemory ? RCPSP_E_NOMEM : RCPSP_E_DEVICE, "%s: %s (%s:%d)", #expr, \
-                        hipGetErrorString(e_), __FILE__, __LINE__);                            \
-    } while (0)
-
 int potential_moves(int n, int delta) {
     const int Lp = n - 2;
     if (Lp < 2 || delta < 1) return 0;
     const int dd = std::min(delta, Lp - 1);
     return dd * Lp - dd * (dd + 1) / 2;
 }
+
+}  // namespace rcpsp
+
+namespace {
 
 int next_pow2(int x) {
     int p = 1;
@@ -69,29 +66,6 @@ struct Blob {
 };
 
 }  // namespace
-
-struct rcpsp_instance {
-    int n = 0, m = 0, n_arcs = 0, H = 0, cp = 0, eval = 0, dmax = 0;
-    std::vector<int> d, R, r, succ_off, succ, pred_off, pred;
-    InstDesc desc{};
-    uint32_t *d_blob = nullptr;
-    int device = 0;
-    rcpsp_info info{};
-};
-
-struct rcpsp_search {
-    const rcpsp_instance *inst = nullptr;
-    rcpsp_search_params p{};
-    int T = 64, L = 0, nw = 1, dec = 1, tcw = 1, P = 0;
-    int reserve = 256;    // static LDS of the kernel the plan runs in
-    Layout Ly{};
-    size_t lds = 0;
-    SearchArgs a{};
-    std::vector<void *> allocs;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int iteration_launches = 0, round_launches = 0;
-};
 
 // ---------------------------------------------------------------------------
 // instances
@@ -547,7 +521,7 @@ extern "C" rcpsp_status rcpsp_evaluate_neighbourhood(const rcpsp_instance *inst,
 
 // eq. 8 decay table: E[0] = 2^24, E[j] = floor(E[j-1] K / 2^32) with
 // K = round(2^32 exp(-1/256)), until it reaches 0.
-static std::vector<uint32_t> decay_table() {
+std::vector<uint32_t> rcpsp::decay_table() {
     const uint64_t K = 4278222805ull;
     std::vector<uint32_t> t;
     uint64_t e = 1ull << 24;
@@ -561,7 +535,8 @@ static std::vector<uint32_t> decay_table() {
 template <typename P>
 static hipError_t dalloc(rcpsp_search *s, P **ptr, size_t bytes) {
     void *v = nullptr;
-    hipError_t e = hipMalloc(&v, std::max<size_t>(bytes, 4));
+    const size_t nb = std::max<size_t>(bytes, 4);
+    hipError_t e = s->allocator ? s->allocator->alloc(&v, nb) : hipMalloc(&v, nb);
     if (e == hipSuccess) {
         s->allocs.push_back(v);
         *ptr = static_cast<P *>(v);
@@ -573,7 +548,10 @@ extern "C" void rcpsp_search_destroy(rcpsp_search *s) {
     if (!s) return;
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
-    for (void *v : s->allocs) (void)hipFree(v);
+    for (void *v : s->allocs) {
+        if (s->allocator) s->allocator->release(v);
+        else (void)hipFree(v);
+    }
     delete s;
 }
 
@@ -650,7 +628,7 @@ static hipError_t enqueue_run(rcpsp_search *s, hipStream_t st, RunTimer *tm) {
 }
 
 // Layout and device state of a plan (no launches).
-static rcpsp_status alloc_plan(rcpsp_search *s) {
+rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     const rcpsp_instance *I = s->inst;
     const rcpsp_search_params &p = s->p;
     const int N = I->n, N2 = n2(N), B = p.searches, NF = p.elite;
@@ -711,7 +689,10 @@ static rcpsp_status alloc_plan(rcpsp_search *s) {
     }
     HIP_TRY(dalloc(s, &a.g, sizeof(Global)));
     if (a.record) HIP_TRY(dalloc(s, &a.traj, sizeof(int) * 4 * (size_t)B * std::max(p.iterations, 1)));
-    {
+    if (s->shared_decay) {
+        a.decay = s->shared_decay;
+        a.decay_len = s->shared_decay_len;
+    } else {
         std::vector<uint32_t> E = decay_table();
         uint32_t *dE = nullptr;
         HIP_TRY(dalloc(s, &dE, sizeof(uint32_t) * E.size()));
@@ -719,6 +700,9 @@ static rcpsp_status alloc_plan(rcpsp_search *s) {
         a.decay = dE;
         a.decay_len = (int)E.size();
     }
+    // the set-up kernels initialise every state a run reads; the clears
+    // below only keep never-written buffers from being copied uninitialised
+    if (s->allocator) return RCPSP_OK;
     HIP_TRY(hipMemset(a.g, 0, sizeof(Global)));
     if (NF > 0) {
         // export and record buffers are always written before they are read;
@@ -997,7 +981,7 @@ extern "C" void rcpsp_batch_destroy(rcpsp_batch *b) {
     delete b;
 }
 
-static rcpsp_status validate_params(const rcpsp_search_params &p) {
+rcpsp_status rcpsp::validate_params(const rcpsp_search_params &p) {
     if (p.swap_range < 1 || p.swap_range > kMaxDelta)
         return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", p.swap_range, kMaxDelta);
     if (p.tabu_len < 1) return fail(RCPSP_E_ARG, "tabu_len must be >= 1");

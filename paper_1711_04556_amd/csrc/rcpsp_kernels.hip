@@ -1278,6 +1278,164 @@ __global__ void k_fill_zero(int *p, long long n) {
 }
 
 // ---------------------------------------------------------------------------
+// Serving: requests arrive over time; each keeps its search state in device
+// memory and advances in time slices.  A slice is one persistent launch per
+// class over a task queue that grows while it runs: the host queues a set-up
+// task for every new request and the tasks of the next iteration of every
+// running one; the task that completes the last search of an iteration ends
+// the request (allowance, deadline, global stop, cancel) or runs its exchange
+// round and, while the slice lasts, queues the next iteration's tasks.  A
+// task is counted in `pending` from being queued until it finishes, so
+// pending = 0 means no task can be queued any more: waiting workgroups then
+// leave.  Tasks only ever wait for the queue, never for each other.
+
+template <int NW, int T, int DEC>
+__global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ SearchArgs A;
+    __shared__ StepShared ss;
+    __shared__ long long tk;
+    __shared__ int flag;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            long long task = -1;
+            const unsigned long long h = atomicAdd(&C.q->head, 1ull);
+            if ((long long)h < C.cap) {
+                const long long t0 = (long long)wall_clock64();
+                for (;;) {
+                    const unsigned long long v =
+                        __hip_atomic_load(&C.tasks[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (v != 0ull) {
+                        task = (long long)(v - 1ull);
+                        break;
+                    }
+                    if (__hip_atomic_load(&C.q->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+                    if ((long long)wall_clock64() - t0 > C.wait_ticks ||
+                        __hip_atomic_load(&C.q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        atomicExch(&C.q->abort, 1);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            tk = task;
+        }
+        __syncthreads();
+        const long long task = tk;
+        __syncthreads();
+        if (task < 0) break;
+        __threadfence();
+        const int slot = (int)((unsigned long long)task >> 44);
+        const int kind = (int)(((unsigned long long)task >> 43) & 1ull);
+        const int b = (int)(((unsigned long long)task >> 27) & 0xffffull);
+        const int it = (int)((unsigned long long)task & 0x7ffffffull);
+        {
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(C.items + slot);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(&A);
+            for (int i = tid; i < (int)(sizeof(SearchArgs) / 4); i += T) dst[i] = src[i];
+        }
+        __syncthreads();
+        Sh S = make_sh(lds, A.D, A.Ly);
+        ServeReq *R = C.req + slot;
+        int next = -1;
+        if (kind == 0) {
+            uint16_t *scratch16 = reinterpret_cast<uint16_t *>(S.region);
+            const int units = A.B > A.NF ? A.B : A.NF;
+            for (int i = 0; i < units; ++i) reset_unit<T>(A, i, scratch16);
+            stage_blob<T>(lds, A.D, A.Ly);
+            __syncthreads();
+            if (A.NF > 0) {
+                for (int k = 0; k < A.NF; ++k) decode_record<NW, T, DEC>(A, S, k);
+                exchange_round<T>(A, 0, 1, reinterpret_cast<int *>(S.region));
+            }
+            next = 0;
+        } else {
+            stage_blob<T>(lds, A.D, A.Ly);
+            __syncthreads();
+            search_step<NW, T, DEC, false>(A, S, ss, b, it, 1);
+            if (tid == 0) {
+                const int old = __hip_atomic_fetch_add(&R->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                int fin = -1;
+                if (old + 1 == A.B) {
+                    // every search finished iteration `it`: end here or continue
+                    R->done = 0;
+                    const long long now = (long long)wall_clock64();
+                    int all_stopped = 1, best = 0x7fffffff;
+                    long long evals = 0;
+                    for (int s = 0; s < A.B; ++s) {
+                        all_stopped &= A.sc[s].stopped != 0;
+                        best = min(best, A.sc[s].C_best);
+                        evals += A.sc[s].evals;
+                    }
+                    for (int k = 0; k < A.NF; ++k) best = min(best, A.Fmeta[k].C);
+                    const int gstop = A.NF > 0 && A.g->gstop != 0;
+                    const int cancel = __hip_atomic_load(&R->cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    fin = it + 1 >= R->max_iters || now >= R->deadline || all_stopped || gstop || cancel;
+                    if (fin) {
+                        R->best = best;
+                        R->evals = evals;
+                        R->replay_iters = it + 1;
+                        R->done_ticks = now;
+                        R->next_iter = -1;
+                        __hip_atomic_store(&R->finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                flag = fin;
+            }
+            __syncthreads();
+            const int fin = flag;
+            __syncthreads();
+            if (fin == 0) {
+                __threadfence();
+                if (A.NF > 0) exchange_round<T>(A, it & 1, 0, reinterpret_cast<int *>(S.region));
+                next = it + 1;
+            }
+        }
+        if (tid == 0) {
+            if (next >= 0) {
+                // queue the next iteration while the slice lasts, else leave it to the next slice
+                bool queued = false;
+                if ((long long)wall_clock64() < C.slice_end) {
+                    const unsigned long long t = atomicAdd(&C.q->tail, (unsigned long long)A.B);
+                    if ((long long)(t + A.B) <= C.cap) {
+                        R->next_iter = -2;
+                        __hip_atomic_fetch_add(&C.q->pending, (long long)A.B, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        for (int s = 0; s < A.B; ++s)
+                            __hip_atomic_store(&C.tasks[t + s], serve_task(slot, 1, s, next) + 1ull, __ATOMIC_RELEASE,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        queued = true;
+                    }
+                }
+                if (!queued) R->next_iter = next;
+            }
+            __threadfence();
+            __hip_atomic_fetch_add(&C.q->pending, -1ll, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+// Slice start: queue header (n0 tasks already copied to tasks[0, n0)) and the
+// rest of the task array cleared.
+__global__ void k_serve_begin(ServeQueue *q, unsigned long long *tasks, long long cap, long long n0) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n0 && i < cap) tasks[i] = 0ull;
+    if (i == 0) {
+        q->head = 0ull;
+        q->tail = (unsigned long long)n0;
+        q->pending = n0;
+        q->abort = 0;
+    }
+}
+
+// Device wall clock (ticks) for the host's clock mapping.
+__global__ void k_clock(long long *out) {
+    if (threadIdx.x == 0) out[0] = (long long)wall_clock64();
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 
 #define RCPSP_DISPATCH(NWV, TV, DECV, CALL)                                                 \
@@ -1392,6 +1550,36 @@ hipError_t launch_fill_zero(int *p, long long n, hipStream_t st) {
 }
 
 size_t batch_queue_bytes() { return sizeof(BatchQueue); }
+
+hipError_t serve_occupancy(int T, int nw, int dec, size_t lds, int *per_cu) {
+    *per_cu = 0;
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipError_t e = set_lds(k_serve<NW_, T_, DEC_>, lds);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_serve<NW_, T_, DEC_>, T_, lds);
+        if (e != hipSuccess) return e;
+    });
+    return hipSuccess;
+}
+
+hipError_t launch_serve(const ServeArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, {
+        hipLaunchKernelGGL((k_serve<NW_, T_, DEC_>), dim3(grid), dim3(T_), lds, st, C);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_begin(ServeQueue *q, unsigned long long *tasks, long long cap, long long n0,
+                              hipStream_t st) {
+    const long long n = cap > 1 ? cap : 1;
+    hipLaunchKernelGGL(k_serve_begin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, tasks, cap, n0);
+    return hipGetLastError();
+}
+
+hipError_t launch_clock(long long *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, st, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t st) {
     const size_t lds = round_lds_bytes(A.B, A.NF);

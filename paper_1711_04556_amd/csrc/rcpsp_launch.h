@@ -51,4 +51,50 @@ hipError_t batch_occupancy(int T, int nw, int dec, size_t lds, int *per_cu);
 hipError_t launch_batch(const BatchClassArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st);
 hipError_t launch_fill_zero(int *p, long long n, hipStream_t st);
 
+// Serving: per-request control block in device memory (64 bytes).
+struct ServeReq {
+    int next_iter;       // iteration the next slice starts; -1 set-up, -2 queued on the device
+    int done;            // searches done in the current iteration
+    int finished;        // 1 once the request's search has ended
+    int replay_iters;    // search steps run per search (iterations of an equal plain run)
+    int best;            // global best at the end
+    int max_iters;       // iteration allowance (eq. 8's I_block)
+    int cancel;          // set by the host: end at the next iteration boundary
+    int pad0;
+    long long deadline;  // wall-clock ticks: no iteration starts after it
+    long long done_ticks;
+    long long evals;
+    long long pad1;
+};
+
+struct ServeQueue {
+    unsigned long long head, tail;
+    long long pending;   // tasks published and not finished
+    int abort;
+    int pad[9];
+};
+
+// One class of a serving slice (see k_serve).
+struct ServeArgs {
+    const SearchArgs *items;    // [slots] plan arguments per request slot
+    ServeReq *req;              // [slots]
+    unsigned long long *tasks;  // [cap] 0 = empty, else task + 1
+    ServeQueue *q;
+    long long cap;
+    long long slice_end;        // wall-clock ticks: no new iteration is queued after it
+    long long wait_ticks;       // limit of one wait
+};
+
+// task: slot (20 bits) | kind (1: search step, 0: set-up) | search (16 bits) | iteration (27 bits)
+__host__ __device__ inline unsigned long long serve_task(int slot, int kind, int b, int it) {
+    return ((unsigned long long)slot << 44) | ((unsigned long long)kind << 43) | ((unsigned long long)b << 27) |
+           (unsigned long long)it;
+}
+
+hipError_t serve_occupancy(int T, int nw, int dec, size_t lds, int *per_cu);
+hipError_t launch_serve(const ServeArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t launch_serve_begin(ServeQueue *q, unsigned long long *tasks, long long cap, long long n0,
+                              hipStream_t st);
+hipError_t launch_clock(long long *out, hipStream_t st);
+
 }  // namespace rcpsp

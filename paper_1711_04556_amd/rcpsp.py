@@ -73,6 +73,26 @@ class rcpsp_batch_tuning(ctypes.Structure):
         ("group_evals_per_s", ctypes.c_double * 8)]
 
 
+class rcpsp_server_params(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("slice_us", ctypes.c_int32), ("arena_bytes", ctypes.c_int64)]
+
+
+class rcpsp_request_status(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("best_makespan", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("error", ctypes.c_int32), ("evaluations", ctypes.c_int64), ("submit_ns", ctypes.c_int64),
+                ("admit_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64), ("seen_ns", ctypes.c_int64)]
+
+
+class rcpsp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("slices", ctypes.c_int64), ("busy_ms", ctypes.c_double), ("evaluations", ctypes.c_int64),
+                ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("arena_used", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
 class rcpsp_search_config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches")]
@@ -138,6 +158,27 @@ def lib():
     L.rcpsp_batch_autotune.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(rcpsp_search_params), i32, i32, vp,
                                        ctypes.POINTER(rcpsp_search_params), ctypes.POINTER(rcpsp_batch_tuning)]
     L.rcpsp_batch_autotune.restype = ctypes.c_int
+    L.rcpsp_server_create.argtypes = [ctypes.POINTER(rcpsp_server_params), ctypes.POINTER(vp)]
+    L.rcpsp_server_create.restype = ctypes.c_int
+    L.rcpsp_server_submit.argtypes = [vp, vp, ctypes.POINTER(rcpsp_search_params), ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    L.rcpsp_server_submit.restype = ctypes.c_int
+    L.rcpsp_server_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(rcpsp_request_status)]
+    L.rcpsp_server_poll.restype = ctypes.c_int
+    L.rcpsp_server_results.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(rcpsp_search_result)]
+    L.rcpsp_server_results.restype = ctypes.c_int
+    L.rcpsp_server_cancel.argtypes = [vp, ctypes.c_int64]
+    L.rcpsp_server_cancel.restype = ctypes.c_int
+    L.rcpsp_server_release.argtypes = [vp, ctypes.c_int64]
+    L.rcpsp_server_release.restype = ctypes.c_int
+    L.rcpsp_server_drain.argtypes = [vp, ctypes.c_int64]
+    L.rcpsp_server_drain.restype = ctypes.c_int
+    L.rcpsp_server_get_stats.argtypes = [vp, ctypes.POINTER(rcpsp_server_stats)]
+    L.rcpsp_server_get_stats.restype = ctypes.c_int
+    L.rcpsp_server_now_ns.argtypes = []
+    L.rcpsp_server_now_ns.restype = ctypes.c_int64
+    L.rcpsp_server_destroy.argtypes = [vp]
+    L.rcpsp_server_destroy.restype = None
     L.rcpsp_last_error.argtypes = []
     L.rcpsp_last_error.restype = ctypes.c_char_p
     L.rcpsp_version.argtypes = []
@@ -298,7 +339,7 @@ class SearchPlan:
         return out
 
 
-def _results(fn, handle_args, params, n, stream, orders=True, trajectory=True) -> dict:
+def _results(fn, handle_args, params, n, stream, orders=True, trajectory=True, sync=True) -> dict:
     p = params
     B, N, F = p.searches, n, p.elite
     out = dict(best_makespan=np.zeros(B, np.int32), iterations_done=np.zeros(B, np.int32),
@@ -310,7 +351,10 @@ def _results(fn, handle_args, params, n, stream, orders=True, trajectory=True) -
     res = rcpsp_search_result(*[out[k].ctypes.data if out[k] is not None else None for k in
                                 ("best_makespan", "best_order", "iterations_done", "evaluations", "trajectory",
                                  "elite_makespan", "elite_order")])
-    _check(fn(*handle_args, ctypes.byref(res), _stream_ptr(stream)))
+    if sync:
+        _check(fn(*handle_args, ctypes.byref(res), _stream_ptr(stream)))
+    else:
+        _check(fn(*handle_args, ctypes.byref(res)))
     out["elite_makespan"] = out["elite_makespan"][:F]
     if out["elite_order"] is not None:
         out["elite_order"] = out["elite_order"][:F]
@@ -388,6 +432,64 @@ class Batch:
     def results(self, index: int, stream=None, orders: bool = True, trajectory: bool = True) -> dict:
         return _results(lib().rcpsp_batch_results, (self.h, index), self.params[index], self.instances[index].n,
                         stream, orders, trajectory)
+
+
+class Server:
+    """rcpsp_server_*: requests admitted as they arrive, state resident on the
+    device, advanced in time slices by a host thread of the library."""
+
+    def __init__(self, max_active: int = 256, slice_us: int = 2000, arena_bytes: int = 2 << 30):
+        prm = rcpsp_server_params(max_active, slice_us, arena_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().rcpsp_server_create(ctypes.byref(prm), ctypes.byref(h)))
+        self.h = h
+        self._params = {}
+        self._inst = {}
+
+    def close(self) -> None:
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.rcpsp_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    @staticmethod
+    def now_ns() -> int:
+        return lib().rcpsp_server_now_ns()
+
+    def submit(self, instance: Instance, params: rcpsp_search_params, budget_us: int = 0) -> int:
+        t = ctypes.c_int64()
+        _check(lib().rcpsp_server_submit(self.h, instance.h, ctypes.byref(params), budget_us, ctypes.byref(t)))
+        self._params[t.value] = params
+        self._inst[t.value] = instance
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        st = rcpsp_request_status()
+        _check(lib().rcpsp_server_poll(self.h, ticket, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in rcpsp_request_status._fields_}
+
+    def results(self, ticket: int, orders: bool = True, trajectory: bool = True) -> dict:
+        return _results(lib().rcpsp_server_results, (self.h, ticket), self._params[ticket],
+                        self._inst[ticket].n, None, orders, trajectory, sync=False)
+
+    def cancel(self, ticket: int) -> None:
+        _check(lib().rcpsp_server_cancel(self.h, ticket))
+
+    def release(self, ticket: int) -> None:
+        _check(lib().rcpsp_server_release(self.h, ticket))
+        self._params.pop(ticket, None)
+        self._inst.pop(ticket, None)
+
+    def drain(self, timeout_ms: int = 0) -> None:
+        _check(lib().rcpsp_server_drain(self.h, timeout_ms))
+
+    @property
+    def stats(self) -> dict:
+        st = rcpsp_server_stats()
+        _check(lib().rcpsp_server_get_stats(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in rcpsp_server_stats._fields_}
 
 
 def tabu_search(instance: Instance, stream=None, **kw) -> dict:

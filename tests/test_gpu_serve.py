@@ -1,0 +1,111 @@
+"""GPU serving: requests through rcpsp_server_* (C ABI) against the CPU
+oracle.  A request stops at a timing-dependent iteration boundary; its
+results must equal the oracle run for exactly that many iterations with
+eq. 8's allowance kept at the request's iteration allowance."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_04556_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TIME, CAP = 1, 2
+
+
+@pytest.fixture(scope="module")
+def rc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_04556_amd import rcpsp
+    rcpsp.lib()
+    return rcpsp
+
+
+def _check_against_oracle(rc, srv, ticket, inst, dec, p):
+    st = srv.poll(ticket)
+    assert st["state"] == rc.REQ_DONE, st
+    k = st["iterations"]
+    assert 1 <= k <= p.iterations
+    g = srv.results(ticket)
+    o = oracle.Oracle(inst).tabu_search(p.swap_range, p.tabu_len, k, searches=p.searches, elite=p.elite,
+                                        phi_max=p.phi_max, phi_steps=p.phi_steps, decoder=dec, seed=p.seed,
+                                        i_block=p.iterations)
+    assert np.array_equal(g["trajectory"][:, :k], o["trajectory"])
+    assert (g["trajectory"][:, k:] == -1).all()
+    for key in ("best_makespan", "iterations_done", "evaluations", "best_order"):
+        assert np.array_equal(g[key], o[key]), key
+    if p.elite:
+        assert np.array_equal(g["elite_makespan"], o["elite_makespan"])
+        assert np.array_equal(g["elite_order"], o["elite_order"])
+    assert st["best_makespan"] == g["global_best"]
+    assert st["evaluations"] == g["total_evaluations"]
+    assert st["submit_ns"] <= st["admit_ns"] <= st["seen_ns"]
+    return st
+
+
+def _cases():
+    out = []
+    for i, (n, rs, dec, elite, iters, budget) in enumerate([
+            (30, 0.5, TIME, 4, 40, 0), (25, 0.3, CAP, 4, 500, 3000), (40, 0.4, TIME, 0, 30, 0),
+            (20, 0.6, TIME, 4, 2000, 2000), (35, 0.2, CAP, 0, 300, 1500), (30, 0.4, TIME, 8, 5000, 4000)]):
+        inst = synth.generate(n, 4, 10, 0.5, rs=rs, seed=900 + i)
+        out.append((inst, dec, elite, iters, budget))
+    return out
+
+
+def test_server_requests_match_oracle_replay(rc):
+    srv = rc.Server(max_active=4, slice_us=500)
+    tickets = []
+    for i, (inst, dec, elite, iters, budget) in enumerate(_cases()):
+        gi = rc.Instance(inst, eval=dec)
+        p = rc.search_params(6 + i % 3, 25, iters, searches=5 + i, elite=elite, phi_max=2, phi_steps=4,
+                             threads=64, seed=31 + i)
+        tickets.append((srv.submit(gi, p, budget), inst, gi, dec, p, budget))
+    # max_active 4: later requests wait for a released slot
+    pending = list(tickets)
+    t_end = time.time() + 60
+    while pending and time.time() < t_end:
+        for item in list(pending):
+            t, inst, gi, dec, p, budget = item
+            if srv.poll(t)["state"] == rc.REQ_DONE:
+                st = _check_against_oracle(rc, srv, t, inst, dec, p)
+                if budget == 0:
+                    assert st["iterations"] == p.iterations or (st["best_makespan"] == gi.info["critical_path"])
+                srv.release(t)
+                pending.remove(item)
+        time.sleep(0.002)
+    assert not pending, [srv.poll(x[0]) for x in pending]
+    s = srv.stats
+    assert s["completed"] == len(tickets) and s["resident"] == 0 and s["arena_used"] == 0
+    srv.close()
+
+
+def test_server_cancel_and_footprint(rc):
+    inst = synth.generate(30, 4, 10, 0.5, rs=0.3, seed=950)
+    gi = rc.Instance(inst, eval=TIME)
+    p = rc.search_params(8, 30, 100000, searches=4, elite=4, phi_max=2, phi_steps=4, threads=64,
+                         record_trajectory=False, seed=5)
+    # an arena too small for the request: refused at submission
+    tiny = rc.Server(max_active=2, slice_us=500, arena_bytes=4096)
+    with pytest.raises(rc.RcpspError) as e:
+        tiny.submit(gi, p, 0)
+    assert e.value.status == -9
+    tiny.close()
+    srv = rc.Server(max_active=2, slice_us=500)
+    t = srv.submit(gi, p, 0)
+    time.sleep(0.05)
+    srv.cancel(t)
+    srv.drain(30000)
+    st = srv.poll(t)
+    assert st["state"] == rc.REQ_DONE and 1 <= st["iterations"] < p.iterations
+    g = srv.results(t, trajectory=False)
+    o = oracle.Oracle(inst).tabu_search(8, 30, st["iterations"], searches=4, elite=4, phi_max=2, phi_steps=4,
+                                        decoder=TIME, seed=5, trajectory=False, i_block=p.iterations)
+    for key in ("best_makespan", "iterations_done", "evaluations", "best_order"):
+        assert np.array_equal(g[key], o[key]), key
+    srv.release(t)
+    srv.close()
