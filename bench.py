@@ -35,6 +35,10 @@ WORKLOAD = dict(swap_range=20, tabu_len=329, iterations=1000, searches=480, elit
 # list is max(60, 0.15 x potential swaps), as for the plain workload
 BATCH = dict(count=1024, base_seed=3000, searches=32, elite=16, phi_max=3, phi_steps=20, iterations=100)
 BATCH_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329)}
+# serving leg: open-loop Poisson arrivals, 50 ms budget from admission
+SERVE = dict(rate=2000.0, warmup_s=2.0, measure_s=10.0, budget_us=50000, searches=16, elite=16, iterations=1000,
+             phi_max=3, phi_steps=20, seed=5, pool=256)
+SERVE_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329), 302: (20, 869)}
 
 
 def log(*a):
@@ -163,6 +167,107 @@ def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
     }
 
 
+def pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
+    """Config: Poisson arrivals at `rate`/s, sizes uniform over 30/60/120/300
+    activities, 16 searches and a working set of 16 per request, 50 ms
+    budget from admission.  Latency = time the result is available to the
+    caller minus the scheduled arrival."""
+    import numpy as np
+    t0 = time.perf_counter()
+    pool = synth.serving_pool(SERVE["pool"])
+    gis = {n: [rcpsp.Instance(i) for i in lst] for n, lst in pool.items()}
+    params = {}
+    for n, lst in gis.items():
+        d, tl = SERVE_DELTA_TL[n + 2]
+        # decoder: the library's automatic choice per instance; one wave per search
+        params[n] = rcpsp.search_params(d, tl, SERVE["iterations"], searches=SERVE["searches"],
+                                        elite=SERVE["elite"], phi_max=SERVE["phi_max"],
+                                        phi_steps=SERVE["phi_steps"], threads=64, record_trajectory=False,
+                                        seed=SERVE["seed"])
+    log("serving set-up", f"{time.perf_counter() - t0:.1f} s")
+    arrivals = synth.serving_arrivals(rate, warmup_s + measure_s, SERVE["seed"])
+    sizes = synth.SERVING_SIZES
+    srv = rcpsp.Server(max_active=1024, slice_us=1000, arena_bytes=8 << 30)
+    counters = {n: 0 for n in sizes}
+    info_of = {}
+    start = srv.now_ns() + 50_000_000
+    j = 0
+    recs = []
+    deadline = start + int((warmup_s + measure_s + 30.0) * 1e9)
+    next_log = start + 1_000_000_000
+    while (j < len(arrivals) or info_of) and srv.now_ns() < deadline:
+        now = srv.now_ns()
+        if now >= next_log:
+            next_log += 1_000_000_000
+            log(f"serving t={(now - start) * 1e-9:.0f} s: submitted {j}, finished {len(recs)}, "
+                f"in flight {len(info_of)}")
+        while j < len(arrivals) and start + int(arrivals[j][0] * 1e9) <= now:
+            n = sizes[arrivals[j][1]]
+            k = counters[n]
+            counters[n] += 1
+            p = type(params[n]).from_buffer_copy(params[n])
+            p.seed = SERVE["seed"] + j
+            t = srv.submit(gis[n][k % len(gis[n])], p, SERVE["budget_us"])
+            info_of[t] = (j, n, start + int(arrivals[j][0] * 1e9))
+            j += 1
+        done = srv.take_finished()
+        for t in done:
+            st = srv.poll(t)
+            jj, n, sched = info_of.pop(t)
+            recs.append((jj, n, sched, st))
+            srv.release(t)
+        if not done:
+            nxt = start + int(arrivals[j][0] * 1e9) if j < len(arrivals) else now + 200_000
+            wait = min(nxt - srv.now_ns(), 200_000)
+            if wait > 50_000:
+                time.sleep(wait * 1e-9 * 0.5)
+    unfinished = len(info_of)
+    stats = srv.stats
+    srv.close()
+    lo, hi = start + int(warmup_s * 1e9), start + int((warmup_s + measure_s) * 1e9)
+    meas = [r for r in recs if lo <= r[2] < hi]
+    ok = [r for r in meas if r[3]["state"] == rcpsp.REQ_DONE]
+    lat = [(r[3]["seen_ns"] - r[2]) * 1e-6 for r in ok]
+    lat_dev = [(r[3]["done_ns"] - r[2]) * 1e-6 for r in ok]
+    queue = [(r[3]["admit_ns"] - r[2]) * 1e-6 for r in ok]
+    evals = sum(r[3]["evaluations"] for r in ok)
+    per_size = {}
+    for n in sizes:
+        rs = [r for r in ok if r[1] == n]
+        if rs:
+            per_size[str(n)] = dict(requests=len(rs), p50_ms=pct([(r[3]["seen_ns"] - r[2]) * 1e-6 for r in rs], 50),
+                                    p99_ms=pct([(r[3]["seen_ns"] - r[2]) * 1e-6 for r in rs], 99),
+                                    iterations_p50=pct([r[3]["iterations"] for r in rs], 50),
+                                    evals_per_request=sum(r[3]["evaluations"] for r in rs) / len(rs))
+    out = {
+        "workload": f"open-loop Poisson arrivals at {rate:g}/s for {warmup_s + measure_s:g} s "
+                    f"({len(arrivals)} requests; latency over the {measure_s:g} s after a {warmup_s:g} s "
+                    f"warm-up), sizes uniform over 30/60/120/300 activities ({SERVE['pool']} distinct instances "
+                    f"per size, cycled), {SERVE['searches']} searches and working set {SERVE['elite']} per "
+                    f"request, {SERVE['budget_us'] // 1000} ms budget from admission, allowance "
+                    f"{SERVE['iterations']} iterations",
+        "requests_measured": len(meas),
+        "completed": len(ok),
+        "unfinished_at_cutoff": unfinished,
+        "p50_ms": pct(lat, 50),
+        "p99_ms": pct(lat, 99),
+        "p50_ms_device_end": pct(lat_dev, 50),
+        "p99_ms_device_end": pct(lat_dev, 99),
+        "queueing_p99_ms": pct(queue, 99),
+        "evals_per_s": evals / measure_s,
+        "per_size": per_size,
+        "slices": stats["slices"],
+        "slice_busy_ms_mean": stats["busy_ms"] / max(stats["slices"], 1),
+    }
+    log("serving", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +284,9 @@ def main():
                     help="for HBM counter runs: one elementwise kernel over 1 GiB (read 1 GiB, write 1 GiB), "
                          "then one run of the headline plan")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=SERVE["rate"])
+    ap.add_argument("--serve-seconds", type=float, default=SERVE["measure_s"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the searches would shard across "
@@ -306,11 +414,14 @@ def main():
             "launches_per_step": n_launch,
         },
         "batched": None,
+        "serving": None,
         "cpu_baseline": None,
     }
     plan.close()
     if not args.no_batch:
         out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, min(args.warmup, 1))
+    if not args.no_serve:
+        out["serving"] = serving_leg(rcpsp, synth, stream, args.serve_rate, SERVE["warmup_s"], args.serve_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, dec)
         log("cpu baseline", out["cpu_baseline"])

@@ -137,7 +137,10 @@ typedef struct {
     int32_t phi_max;          /* diversify when a record was read more than phi_max times */
     int32_t phi_steps;        /* random feasible swaps per diversification */
     int32_t threads;          /* threads per search: 0 = auto, else 64, 128, 256 */
-    int32_t profile_len;      /* time-indexed LDS profile slots per lane, 0 = auto */
+    int32_t profile_len;      /* time-indexed LDS profile slots per lane, 0 = auto
+                                 (about 1.4 x critical path, stretched while the
+                                 workgroups per CU stay the same, never below
+                                 critical path + longest duration) */
     int32_t record_trajectory;/* 1 = keep (u, v, C_after, C_best) per iteration on the device */
     int32_t count_work;       /* 1 = also count the decodes' algorithmic operations
                                  (instrumented kernels; for measurement runs) */
@@ -145,7 +148,12 @@ typedef struct {
                                  instead of continuing from the schedule prefix it
                                  shares with the current order (same results) */
     int32_t eval;             /* decoder for this search: 0 = the instance's,
-                                 1 time-indexed, 2 capacity-indexed */
+                                 or capacity-indexed when the instance's is
+                                 time-indexed and its LDS profile (at least
+                                 critical path + longest duration slots) does
+                                 not fit; 1 time-indexed, 2 capacity-indexed.
+                                 The resolved decoder is reported by
+                                 rcpsp_search_get_config and decides results. */
     uint64_t seed;            /* seeds the initial orders and diversification */
 } rcpsp_search_params;
 
@@ -314,6 +322,9 @@ rcpsp_status rcpsp_server_release(rcpsp_server *s, int64_t ticket);
 /* Block until no request is queued or running; RCPSP_E_DEVICE if a slice
  * failed, RCPSP_E_ARG if timeout_ms (> 0) passed first. */
 rcpsp_status rcpsp_server_drain(rcpsp_server *s, int64_t timeout_ms);
+/* Tickets of requests that finished (done or failed) since the last call,
+ * in the order the host loop saw them end; at most cap, *n set to the count. */
+rcpsp_status rcpsp_server_take_finished(rcpsp_server *s, int64_t *tickets, int32_t cap, int32_t *n);
 rcpsp_status rcpsp_server_get_stats(rcpsp_server *s, rcpsp_server_stats *out);
 int64_t rcpsp_server_now_ns(void);
 /* Stops the host thread after the running slice; requests still queued or

@@ -398,9 +398,15 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
     int L = std::min(H, ((14 * I->cp + 9) / 10 + 2 * I->dmax + 15) / 16 * 16);
     L = std::max(L, 1);
     while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec).long_len < I->H) ++L;
+    // shorter profiles trade LDS for long-profile decodes; below the critical
+    // path plus the longest duration nearly every candidate would take that
+    // path, so the decoder does not fit
+    const int Lfloor = std::max(16, std::min(H, I->cp + I->dmax));
     while (!fits(L, &Ly)) {
-        if (L <= 16) return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
-        L = std::max(16, L * 3 / 4);
+        if (L <= Lfloor)
+            return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget,
+                        T, L);
+        L = std::max(Lfloor, L * 3 / 4);
     }
     const int k0 = lds_occupancy((size_t)Ly.total * 4, reserve);
     Layout Ln;
@@ -638,13 +644,23 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
         return fail(RCPSP_E_TOO_LARGE, "time-indexed profile needs more than %d dwords per time unit", kMaxNW);
     s->tcw = (p.swap_range + 31) / 32;
     s->P = potential_moves(N, p.swap_range);
-    int T = p.threads;
-    if (T == 0) T = B >= 256 ? 64 : (B >= 64 ? 128 : 256);
-    if (T != 64 && T != 128 && T != 256) return fail(RCPSP_E_ARG, "threads must be 0, 64, 128 or 256");
+    const int T0 = p.threads ? p.threads : (B >= 256 ? 64 : (B >= 64 ? 128 : 256));
+    if (T0 != 64 && T0 != 128 && T0 != 256) return fail(RCPSP_E_ARG, "threads must be 0, 64, 128 or 256");
+    int T = T0;
     rcpsp_status st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, s->reserve, &s->L, &s->Ly);
     while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
         T /= 2;
         st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, s->reserve, &s->L, &s->Ly);
+    }
+    if (st == RCPSP_E_TOO_LARGE && p.eval == RCPSP_EVAL_AUTO && s->dec == kEvalTime) {
+        // automatic choice: the time-indexed profile does not fit, take the capacity-indexed decoder
+        s->dec = kEvalCapacity;
+        T = T0;
+        st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, 0, s->reserve, &s->L, &s->Ly);
+        while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
+            T /= 2;
+            st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, 0, s->reserve, &s->L, &s->Ly);
+        }
     }
     if (st != RCPSP_OK) return st;
     s->T = T;

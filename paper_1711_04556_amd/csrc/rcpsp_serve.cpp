@@ -144,6 +144,7 @@ struct rcpsp_server {
     rcpsp_status fail_st = RCPSP_OK;
     std::string fail_msg;
     std::deque<Req *> queue;
+    std::deque<int64_t> finished;   // tickets not yet taken by the caller
     std::unordered_map<int64_t, Req *> reqs;
     int64_t next_ticket = 1;
     std::vector<Req *> slot_req;
@@ -211,6 +212,7 @@ void admit(rcpsp_server *s, std::vector<Req *> &fresh) {
             s->queue.pop_front();
             r->state = RCPSP_REQ_FAILED;
             r->error = RCPSP_E_ARG;
+            s->finished.push_back(r->ticket);
             continue;
         }
         rcpsp_search *plan = new (std::nothrow) rcpsp_search();
@@ -234,6 +236,7 @@ void admit(rcpsp_server *s, std::vector<Req *> &fresh) {
             rcpsp_search_destroy(plan);
             r->state = RCPSP_REQ_FAILED;
             r->error = st;
+            s->finished.push_back(r->ticket);
             continue;
         }
         const int slot = s->free_slots.back();
@@ -350,6 +353,7 @@ rcpsp_status run_slice(rcpsp_server *s, const std::vector<Req *> &fresh) {
             --s->running;
             ++s->stats.completed;
             s->stats.evaluations += q.evals;
+            s->finished.push_back(r->ticket);
         } else if (q.next_iter >= 0) {
             r->next_iter = q.next_iter;
         } else {
@@ -590,6 +594,11 @@ extern "C" rcpsp_status rcpsp_server_release(rcpsp_server *s, int64_t ticket) {
         if (r->state != RCPSP_REQ_DONE && r->state != RCPSP_REQ_FAILED)
             return fail(RCPSP_E_ARG, "request %lld is still queued or running", (long long)ticket);
         s->reqs.erase(it);
+        for (auto f = s->finished.begin(); f != s->finished.end(); ++f)
+            if (*f == ticket) {
+                s->finished.erase(f);
+                break;
+            }
         if (r->slot >= 0) {
             s->slot_req[r->slot] = nullptr;
             s->free_slots.push_back(r->slot);
@@ -612,6 +621,18 @@ extern "C" rcpsp_status rcpsp_server_drain(rcpsp_server *s, int64_t timeout_ms) 
         s->cv_idle.wait(g, idle);
     }
     if (s->failed) return fail(s->fail_st, "server failed: %s", s->fail_msg.c_str());
+    return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_server_take_finished(rcpsp_server *s, int64_t *tickets, int32_t cap, int32_t *n) {
+    if (!s || !n || (cap > 0 && !tickets)) return fail(RCPSP_E_ARG, "null pointer");
+    std::lock_guard<std::mutex> g(s->mu);
+    int32_t k = 0;
+    while (k < cap && !s->finished.empty()) {
+        tickets[k++] = s->finished.front();
+        s->finished.pop_front();
+    }
+    *n = k;
     return RCPSP_OK;
 }
 

@@ -173,6 +173,8 @@ def lib():
     L.rcpsp_server_release.restype = ctypes.c_int
     L.rcpsp_server_drain.argtypes = [vp, ctypes.c_int64]
     L.rcpsp_server_drain.restype = ctypes.c_int
+    L.rcpsp_server_take_finished.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32, ctypes.POINTER(i32)]
+    L.rcpsp_server_take_finished.restype = ctypes.c_int
     L.rcpsp_server_get_stats.argtypes = [vp, ctypes.POINTER(rcpsp_server_stats)]
     L.rcpsp_server_get_stats.restype = ctypes.c_int
     L.rcpsp_server_now_ns.argtypes = []
@@ -481,6 +483,12 @@ class Server:
         _check(lib().rcpsp_server_release(self.h, ticket))
         self._params.pop(ticket, None)
         self._inst.pop(ticket, None)
+
+    def take_finished(self, cap: int = 4096) -> list:
+        buf = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int32()
+        _check(lib().rcpsp_server_take_finished(self.h, buf, cap, ctypes.byref(n)))
+        return list(buf[:n.value])
 
     def drain(self, timeout_ms: int = 0) -> None:
         _check(lib().rcpsp_server_drain(self.h, timeout_ms))

@@ -21,6 +21,7 @@ all arithmetic modulo 2**64.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -198,6 +199,44 @@ def large_batch(count: int = 256, base_seed: int = 4000) -> List[Instance]:
     """300 activities, 8 resources, durations 1..20, capacities 10..60."""
     return [generate(300, 8, 20, 0.5, rs=None, cap_range=(10, 60), seed=base_seed + i,
                      name=f"big{i}") for i in range(count)]
+
+
+SERVING_SIZES = (30, 60, 120, 300)
+
+
+def serving_pool(per_size: int = 256, base_seed: int = 5000) -> dict:
+    """Instances for the serving workload, per size in SERVING_SIZES: 30, 60
+    and 120 activities as in mixed_batch (4 resources, RF and RS varied), 300
+    with the large generator (8 resources, durations 1..20, capacities
+    10..60).  Entry j of size index s has seed base_seed + 4 j + s."""
+    out = {}
+    for si, n in enumerate(SERVING_SIZES):
+        lst = []
+        for j in range(per_size):
+            seed = base_seed + 4 * j + si
+            if n == 300:
+                lst.append(generate(300, 8, 20, 0.5, rs=None, cap_range=(10, 60), seed=seed, name=f"srv{seed}"))
+            else:
+                st = Stream(seed, 1)
+                rf = (0.25, 0.5, 0.75, 1.0)[st.next() % 4]
+                rs = (0.2, 0.3, 0.4, 0.5, 0.6, 0.7)[st.next() % 6]
+                lst.append(generate(n, 4, 10, rf, rs=rs, seed=seed, name=f"srv{seed}"))
+        out[n] = lst
+    return out
+
+
+def serving_arrivals(rate: float, duration_s: float, seed: int = 5) -> List[tuple]:
+    """Open-loop arrivals over [0, duration_s): exponential inter-arrival
+    times of mean 1/rate and a size index uniform over SERVING_SIZES, from
+    streams 0 and 1 of `seed`.  Returns [(time_s, size_index)]."""
+    a, z = Stream(seed, 0), Stream(seed, 1)
+    t, out = 0.0, []
+    while True:
+        u = ((a.next() >> 11) + 0.5) / float(1 << 53)
+        t += -math.log(u) / rate
+        if t >= duration_s:
+            return out
+        out.append((t, z.below(len(SERVING_SIZES))))
 
 
 def table1_instance() -> Instance:
