@@ -154,6 +154,10 @@ typedef struct {
                                  not fit; 1 time-indexed, 2 capacity-indexed.
                                  The resolved decoder is reported by
                                  rcpsp_search_get_config and decides results. */
+    int32_t lanes;            /* lanes per candidate decode: 0 = auto (1, or 16
+                                 when a per-lane time-indexed profile does not
+                                 fit), 1, or 16 (time-indexed only: 16 lanes
+                                 test 16 time units per step); same results */
     uint64_t seed;            /* seeds the initial orders and diversification */
 } rcpsp_search_params;
 
@@ -206,6 +210,7 @@ rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcpsp_search_pa
 typedef struct {
     int32_t threads, profile_len, lds_bytes, eval;
     int32_t iteration_launches, round_launches;
+    int32_t lanes;
 } rcpsp_search_config;
 rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out);
 
@@ -248,15 +253,16 @@ void rcpsp_batch_destroy(rcpsp_batch *b);
  * search, with rules that were learnt by timing both algorithms for a few
  * iterations; this entry point does that timing directly: it runs the search
  * described by params for trial_iterations iterations with every candidate
- * (decoder x threads per search x profile length) and keeps the one with the
- * least device time per evaluation.  *out receives params with eval, threads
- * and profile_len filled in; *info (may be NULL) the choice and its cost.
+ * (decoder x lanes per candidate x threads per search x profile length) and
+ * keeps the one with the least device time per evaluation.  *out receives
+ * params with eval, threads, profile_len and lanes filled in; *info (may be NULL) the choice and its cost.
  * The decoder changes the schedules and so the search, so the choice is made
  * once, before the search, and is part of the result's identity.
  * Synchronous; allocates and frees its own trial plans. */
 typedef struct {
     int32_t eval, threads, profile_len;
     int32_t trials;           /* candidates timed */
+    int32_t lanes;            /* lanes per candidate */
     double ns_per_evaluation; /* of the chosen candidate */
 } rcpsp_tuning;
 rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_params *params,
@@ -335,17 +341,18 @@ void rcpsp_server_destroy(rcpsp_server *s);
  * counterpart of rcpsp_autotune).  Instances are grouped by (N, M); for each
  * group, up to `sample` evenly spaced members run as a batch of
  * trial_iterations iterations under every candidate (decoder time- or
- * capacity-indexed where the instance allows it, threads 64/128/256; a
- * nonzero eval or threads in params fixes that choice), and the candidate
+ * capacity-indexed where the instance allows it, threads 64/128/256, lanes
+ * per candidate 1/16 for the time-indexed decoder; a nonzero eval, threads or
+ * lanes in params fixes that choice), and the candidate
  * with the most evaluations per device second is written to every member of
  * the group.  Results never depend on the choice of threads; the decoder is
  * part of the result (the two decoders are different functions).
- *   out   [count] params[i] with eval and threads filled in
+ *   out   [count] params[i] with eval, threads and lanes filled in
  *   info  optional: the first 8 groups and their choices
  * Errors: RCPSP_E_TOO_LARGE when no candidate fits a group. */
 typedef struct {
     int32_t groups, trials;
-    int32_t group_n[8], group_m[8], group_members[8], group_eval[8], group_threads[8];
+    int32_t group_n[8], group_m[8], group_members[8], group_eval[8], group_threads[8], group_lanes[8];
     double group_evals_per_s[8];
 } rcpsp_batch_tuning;
 rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, int32_t count,

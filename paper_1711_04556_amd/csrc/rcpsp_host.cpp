@@ -321,7 +321,9 @@ extern "C" void rcpsp_destroy_instance(rcpsp_instance *inst) {
 // ---------------------------------------------------------------------------
 // LDS layout
 
-static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, int L, int dec) {
+// G = 1: one candidate per lane, lane-interleaved state; G > 1 (time-indexed
+// only): one candidate per group of G lanes, contiguous state per candidate.
+static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, int L, int dec, int G = 1) {
     Layout Ly{};
     const int N2h = n2(D.n) / 2;
     const int F0 = (D.n + 1) / 2;
@@ -347,14 +349,16 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     // per candidate: finish times, then the time-indexed profile (L units
     // plus 4 of slack for the 4-wide scan) or the capacity arrays and the
     // copy ring
-    if (dec == kEvalTime) Ly.per_lane = F0 + (L + 4) * D.nw;
+    if (dec == kEvalTime && G > 1) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
+    else if (dec == kEvalTime) Ly.per_lane = F0 + (L + 4) * D.nw;
     else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
+    Ly.cands = G > 1 ? T / G : T;
     o = (o + 3) & ~3;
     Ly.bst = o; o += Ly.per_lane;
     o = (o + 3) & ~3;
     Ly.region = o;
-    o += T * Ly.per_lane;
-    Ly.long_len = dec == kEvalTime ? (T * Ly.per_lane - F0) / D.nw - 4 : 0;
+    o += Ly.cands * Ly.per_lane;
+    Ly.long_len = dec == kEvalTime ? (Ly.cands * Ly.per_lane - F0) / D.nw - 4 : 0;
     Ly.total = o;
     return Ly;
 }
@@ -369,11 +373,11 @@ static int lds_occupancy(size_t bytes, int reserve) { return (int)(kMaxLds / (by
 // workgroups per CU, never beyond the horizon.  The whole region must also
 // hold one profile of the full horizon for the long-profile decode.
 static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw, int tl, int pmax, int L_req,
-                                int reserve, int *L_out, Layout *Ly_out) {
+                                int reserve, int *L_out, Layout *Ly_out, int G = 1) {
     const InstDesc &D = I->desc;
     const int budget = kMaxLds - 1024;  // static shared variables
     if (dec == kEvalCapacity) {
-        Layout Ly = make_layout(D, T, tcw, tl, pmax, 0, dec);
+        Layout Ly = make_layout(D, T, tcw, tl, pmax, 0, dec, 1);
         if ((size_t)Ly.total * 4 > (size_t)budget)
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d)", Ly.total * 4, budget, T);
         *L_out = 0;
@@ -382,13 +386,13 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
     }
     const int H = std::max(I->H, 1);
     auto fits = [&](int L, Layout *Ly) {
-        *Ly = make_layout(D, T, tcw, tl, pmax, L, dec);
+        *Ly = make_layout(D, T, tcw, tl, pmax, L, dec, G);
         return Ly->long_len >= I->H && (size_t)Ly->total * 4 <= (size_t)budget;
     };
     Layout Ly;
     if (L_req > 0) {
         int L = std::min(L_req, H);
-        while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec).long_len < I->H) ++L;
+        while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec, G).long_len < I->H) ++L;
         if (!fits(L, &Ly))
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
         *L_out = L;
@@ -397,7 +401,7 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
     }
     int L = std::min(H, ((14 * I->cp + 9) / 10 + 2 * I->dmax + 15) / 16 * 16);
     L = std::max(L, 1);
-    while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec).long_len < I->H) ++L;
+    while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec, G).long_len < I->H) ++L;
     // shorter profiles trade LDS for long-profile decodes; below the critical
     // path plus the longest duration nearly every candidate would take that
     // path, so the decoder does not fit
@@ -426,13 +430,18 @@ static rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, i
                                 int32_t asp, int32_t *makespan, rcpsp_move *best, hipStream_t st) {
     if (delta < 1 || delta > kMaxDelta) return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", delta, kMaxDelta);
     const int P = potential_moves(I->n, delta);
-    int T = 256;
+    int T = 256, G = 1;
     int L = 0;
     Layout Ly;
-    rcpsp_status s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly);
-    while (s == RCPSP_E_TOO_LARGE && T > 64) {
-        T /= 2;
-        s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly);
+    rcpsp_status s = RCPSP_E_TOO_LARGE;
+    for (int g : {1, 16}) {
+        if (g > 1 && I->eval != kEvalTime) break;
+        for (T = 256; T >= 64; T /= 2) {
+            s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly, g);
+            if (s != RCPSP_E_TOO_LARGE) break;
+        }
+        G = g;
+        if (s != RCPSP_E_TOO_LARGE) break;
     }
     if (s != RCPSP_OK) return s;
     EvalArgs A{};
@@ -446,7 +455,7 @@ static rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, i
     A.tabu = tabu;
     A.makespan = makespan;
     A.best = reinterpret_cast<int32_t *>(best);
-    HIP_TRY(launch_eval(A, T, I->desc.nw, I->eval, (size_t)Ly.total * 4, st));
+    HIP_TRY(launch_eval(A, T, I->desc.nw, I->eval, G, (size_t)Ly.total * 4, st));
     return RCPSP_OK;
 }
 
@@ -595,7 +604,7 @@ static hipError_t enqueue_run(rcpsp_search *s, hipStream_t st, RunTimer *tm) {
         ai.n_it = n_it;
         hipError_t r;
         if (tm && (r = tm->mark(tm->it_ev, tm->it_n, st)) != hipSuccess) return r;
-        if ((r = launch_search(ai, T, s->nw, s->dec, s->lds, st)) != hipSuccess) return r;
+        if ((r = launch_search(ai, T, s->nw, s->dec, s->G, s->lds, st)) != hipSuccess) return r;
         if (tm && (r = tm->mark(tm->it_ev, tm->it_n, st)) != hipSuccess) return r;
         return hipSuccess;
     };
@@ -646,21 +655,27 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     s->P = potential_moves(N, p.swap_range);
     const int T0 = p.threads ? p.threads : (B >= 256 ? 64 : (B >= 64 ? 128 : 256));
     if (T0 != 64 && T0 != 128 && T0 != 256) return fail(RCPSP_E_ARG, "threads must be 0, 64, 128 or 256");
+    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 16) return fail(RCPSP_E_ARG, "lanes must be 0, 1 or 16");
+    if (p.lanes == 16 && s->dec != kEvalTime) return fail(RCPSP_E_ARG, "16 lanes per candidate needs the time-indexed decoder");
     int T = T0;
-    rcpsp_status st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, s->reserve, &s->L, &s->Ly);
-    while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
-        T /= 2;
-        st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, p.profile_len, s->reserve, &s->L, &s->Ly);
-    }
-    if (st == RCPSP_E_TOO_LARGE && p.eval == RCPSP_EVAL_AUTO && s->dec == kEvalTime) {
-        // automatic choice: the time-indexed profile does not fit, take the capacity-indexed decoder
-        s->dec = kEvalCapacity;
+    rcpsp_status st = RCPSP_E_TOO_LARGE;
+    auto try_shape = [&](int G, int Lreq) {
         T = T0;
-        st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, 0, s->reserve, &s->L, &s->Ly);
+        st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, Lreq, s->reserve, &s->L, &s->Ly, G);
         while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
             T /= 2;
-            st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, 0, s->reserve, &s->L, &s->Ly);
+            st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, Lreq, s->reserve, &s->L, &s->Ly, G);
         }
+        s->G = G;
+    };
+    // one candidate per lane unless requested otherwise; when its profile
+    // does not fit, one candidate per 16 lanes (time-indexed)
+    try_shape(p.lanes == 16 ? 16 : 1, p.profile_len);
+    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0 && s->dec == kEvalTime) try_shape(16, p.profile_len);
+    if (st == RCPSP_E_TOO_LARGE && p.eval == RCPSP_EVAL_AUTO && s->dec == kEvalTime) {
+        // automatic choice: no time-indexed profile fits, take the capacity-indexed decoder
+        s->dec = kEvalCapacity;
+        try_shape(1, 0);
     }
     if (st != RCPSP_OK) return st;
     s->T = T;
@@ -733,7 +748,7 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
 static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     rcpsp_status st0 = alloc_plan(s);
     if (st0 != RCPSP_OK) return st0;
-    HIP_TRY(prepare_search(s->T, s->nw, s->dec, s->lds, s->p.searches, s->p.elite));
+    HIP_TRY(prepare_search(s->T, s->nw, s->dec, s->G, s->lds, s->p.searches, s->p.elite));
     // capture the whole run as one graph
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -827,6 +842,7 @@ extern "C" rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_sea
     out->eval = s->dec;
     out->iteration_launches = s->iteration_launches;
     out->round_launches = s->round_launches;
+    out->lanes = s->G;
     return RCPSP_OK;
 }
 
@@ -915,7 +931,12 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
     double best_ns = 0.0;
     rcpsp_search_params best{};
     int trials = 0;
+    std::vector<int> lanes_c;
+    if (params->lanes) lanes_c.push_back(params->lanes);
+    else lanes_c = {1, 16};
     for (int ev : evals) {
+      for (int G : lanes_c) {
+        if (G > 1 && ev != kEvalTime) continue;
         for (int T : threads) {
             std::vector<int> Ls;
             if (ev == kEvalTime && !params->profile_len) {
@@ -929,6 +950,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
                 q.eval = ev;
                 q.threads = T;
                 q.profile_len = L;
+                q.lanes = G;
                 q.iterations = trial_iterations;
                 q.record_trajectory = 0;
                 q.count_work = 0;
@@ -952,10 +974,12 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
                     best = *params;
                     best.eval = ev;
                     best.threads = T;
+                    best.lanes = G;
                     best.profile_len = ev == kEvalTime ? Lused : 0;
                 }
             }
         }
+      }
     }
     if (!found) return fail(RCPSP_E_TOO_LARGE, "no decoder/launch shape fits this instance");
     *out = best;
@@ -963,6 +987,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
         info->eval = best.eval;
         info->threads = best.threads;
         info->profile_len = best.profile_len;
+        info->lanes = best.lanes;
         info->trials = trials;
         info->ns_per_evaluation = best_ns;
     }
@@ -974,7 +999,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
 
 struct rcpsp_batch {
     struct Class {
-        int dec = 0, nw = 0, T = 0, per_cu = 0, grid = 0, count = 0;
+        int dec = 0, nw = 0, T = 0, G = 1, per_cu = 0, grid = 0, count = 0;
         size_t lds = 0;
         BatchClassArgs args{};
     };
@@ -1031,7 +1056,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         st = alloc_plan(s);
         if (st != RCPSP_OK) return st;
         const int need = 6 * p.searches + 5 * p.elite;
-        if (p.elite > 0 && need > s->T * s->Ly.per_lane)
+        if (p.elite > 0 && need > s->Ly.cands * s->Ly.per_lane)
             return fail(RCPSP_E_TOO_LARGE, "instance %d: exchange bookkeeping does not fit the workgroup's LDS", i);
     }
     // classes: same decoder, profile width, threads per search and workgroups per CU
@@ -1040,18 +1065,19 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         const rcpsp_search *s = bt->items[i];
         const int nw = s->dec == kEvalTime ? s->nw : 1;
         int per_cu = 0;
-        HIP_TRY(batch_occupancy(s->T, nw, s->dec, s->lds, &per_cu));
+        HIP_TRY(batch_occupancy(s->T, nw, s->dec, s->G, s->lds, &per_cu));
         if (per_cu < 1) return fail(RCPSP_E_TOO_LARGE, "instance %d: batch workgroup does not fit a CU", i);
         int c = -1;
         for (size_t k = 0; k < bt->classes.size(); ++k) {
             const rcpsp_batch::Class &cl = bt->classes[k];
-            if (cl.dec == s->dec && cl.nw == nw && cl.T == s->T && cl.per_cu == per_cu) c = (int)k;
+            if (cl.dec == s->dec && cl.nw == nw && cl.T == s->T && cl.G == s->G && cl.per_cu == per_cu) c = (int)k;
         }
         if (c < 0) {
             rcpsp_batch::Class cl;
             cl.dec = s->dec;
             cl.nw = nw;
             cl.T = s->T;
+            cl.G = s->G;
             cl.per_cu = per_cu;
             bt->classes.push_back(cl);
             members.emplace_back();
@@ -1134,7 +1160,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         A.epoch = bt->d_state + cursor;
         A.done = bt->d_state + cursor + cl.count;
         cursor += 2ll * cl.count;
-        HIP_TRY(prepare_batch(cl.T, cl.nw, cl.dec, cl.lds));
+        HIP_TRY(prepare_batch(cl.T, cl.nw, cl.dec, cl.G, cl.lds));
         cl.grid = (int)std::min<long long>(A.total, (long long)cl.per_cu * cus);
     }
     // one graph: clear the counters, then every class's persistent launch on
@@ -1161,7 +1187,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         const rcpsp_batch::Class &cl = bt->classes[c];
         hipEvent_t done = nullptr;
         e = hipStreamWaitEvent(side[c], fork, 0);
-        if (e == hipSuccess) e = launch_batch(cl.args, cl.grid, cl.T, cl.nw, cl.dec, cl.lds, side[c]);
+        if (e == hipSuccess) e = launch_batch(cl.args, cl.grid, cl.T, cl.nw, cl.dec, cl.G, cl.lds, side[c]);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
         if (e == hipSuccess) {
             evs.push_back(done);
@@ -1310,14 +1336,20 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         }
         if (p0.threads) threads.push_back(p0.threads);
         else threads = {64, 128, 256};
+        std::vector<int> lanes_c;
+        if (p0.lanes) lanes_c.push_back(p0.lanes);
+        else lanes_c = {1, 16};
         bool found = false;
         double best_rate = 0.0;
-        int best_eval = 0, best_T = 0;
+        int best_eval = 0, best_T = 0, best_G = 1;
         for (int ev : evals) {
+          for (int G : lanes_c) {
+            if (G > 1 && ev != kEvalTime) continue;
             for (int T : threads) {
                 for (auto &q : sp) {
                     q.eval = ev;
                     q.threads = T;
+                    q.lanes = G;
                 }
                 rcpsp_batch *bt = nullptr;
                 rcpsp_status st = rcpsp_batch_create(si.data(), ns, sp.data(), hip_stream, &bt);
@@ -1341,14 +1373,17 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
                     best_rate = rate;
                     best_eval = ev;
                     best_T = T;
+                    best_G = G;
                 }
             }
+          }
         }
         if (!found) return fail(RCPSP_E_TOO_LARGE, "no decoder/threads candidate fits instances of N=%d, M=%d",
                                 keys[g].first, keys[g].second);
         for (int i : mem) {
             out[i].eval = best_eval;
             out[i].threads = best_T;
+            out[i].lanes = best_G;
         }
         if (info && g < 8) {
             info->group_n[g] = keys[g].first;
@@ -1356,6 +1391,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
             info->group_members[g] = (int32_t)mem.size();
             info->group_eval[g] = best_eval;
             info->group_threads[g] = best_T;
+            info->group_lanes[g] = best_G;
             info->group_evals_per_s[g] = best_rate;
         }
     }

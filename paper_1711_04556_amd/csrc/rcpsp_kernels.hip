@@ -648,9 +648,241 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
 }
 
 // ---------------------------------------------------------------------------
+// Group decode (time-indexed): G consecutive lanes of a wave share one
+// candidate.  Its state is contiguous: finish times (16-bit, by activity),
+// then the profile (unit t, word w at prof[t*NW + w]).  Per activity the
+// lanes read up to G predecessor finish times and combine them with DPP
+// row operations; the Alg. 5 scan tests G consecutive units at once (one per
+// lane) and two ballots give the earliest unit from which d units are free;
+// the Alg. 6 update writes the d units with d lanes.  Every branch depends
+// only on values the whole group shares, so the group stays converged.  The
+// lanes of other groups in the wave may have left a loop: ballots are masked
+// to the group's own bits.
+
+// Maximum over the G lanes of a group (G in {4, 8, 16}) with DPP moves that
+// stay inside a row of 16 lanes: quad swaps, then half-row and row mirrors.
+template <int G>
+__device__ inline int group_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    if (G >= 8) x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    if (G >= 16) x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x140, 0xF, 0xF, false)); // row_mirror
+    return x;
+}
+
+template <int NW, int G, bool COUNT = false>
+__device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, int u, int v, int p0, int p1,
+                         int &front, bool &ovf, long long *wk = nullptr) {
+    static_assert(G == 4 || G == 8 || G == 16, "lanes per candidate");
+    const int g = threadIdx.x & (G - 1);
+    const int gbase = threadIdx.x & 63 & ~(G - 1);
+    constexpr unsigned long long gm = (1ull << G) - 1ull;
+    uint16_t *F = reinterpret_cast<uint16_t *>(cb);
+    uint32_t *prof = cb + ((D.n + 1) >> 1);
+    uint32_t Gd[NW], FULL[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        Gd[w] = D.guard[w];
+        FULL[w] = D.full[w];
+    }
+    const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
+    long long w_ops = 0;
+    int fr = front;
+    for (int p = p0; p < p1; ++p) {
+        const int q = (p == u) ? v : ((p == v) ? u : p);
+        const uint4 r = rec[q];
+        const int d = r.y & 0xffff, np = r.y >> 16, a = (int)r.w;
+        int es = 0;
+        for (int e0 = 0; e0 < np; e0 += G) {
+            const int e = e0 + g;
+            if (e < np) es = max(es, (int)F[S.pred[r.z + e]]);
+        }
+        es = group_max<G>(es);
+        uint32_t rq[NW];
+        uint32_t any = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            rq[w] = S.prq[q * NW + w];
+            any |= rq[w];
+        }
+        int s = es;
+        if (any != 0 && d > 0) {
+            int t = es, c = 0;  // c: free units just before t
+            s = -1;
+            while (t < fr) {
+                const int x = t + g;
+                bool ok = true;
+                if (x < fr) {
+                    const uint32_t *P = prof + x * NW;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) ok = ok && ((((P[w] | Gd[w]) - rq[w]) & Gd[w]) == Gd[w]);
+                }
+                const unsigned long long m = (__ballot(ok) >> gbase) & gm;
+                const uint32_t mz = (uint32_t)(~m & gm);          // units that do not fit
+                const uint32_t below = mz & ((2u << g) - 1u);     // ... at or below this lane's unit
+                const int run = below ? g - (31 - __clz(below)) : c + g + 1;
+                const unsigned long long hm = (__ballot(run >= d) >> gbase) & gm;
+                if (hm != 0ull) {
+                    s = t + (__ffsll(hm) - 1) - d + 1;
+                    break;
+                }
+                c = mz ? (G - 1) - (31 - __clz(mz)) : c + G;
+                t += G;
+            }
+            if (s < 0) s = t - c;  // reached the frontier: every later unit is free
+            if (s + d > L) {
+                ovf = true;
+                return -1;
+            }
+            if (COUNT && g == 0) w_ops += (s + d - es) + d;
+            const int lo = min(s, fr), hi = s + d;
+            for (int x0 = lo; x0 < hi; x0 += G) {
+                const int x = x0 + g;
+                if (x < hi) {
+                    uint32_t *P = prof + x * NW;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        const uint32_t A = (x < fr) ? P[w] : FULL[w];
+                        P[w] = (x < s) ? FULL[w] : A - rq[w];
+                    }
+                }
+            }
+            fr = max(fr, hi);
+        } else if (COUNT && g == 0) {
+            w_ops += 2 * d;
+        }
+        if (COUNT && g == 0) w_ops += 1 + np;
+        if (g == 0) F[a] = (uint16_t)(s + d);
+        __builtin_amdgcn_wave_barrier();
+    }
+    front = fr;
+    if (COUNT && g == 0) *wk += w_ops;
+    return p1 == D.n ? (int)F[D.n - 1] : 0;
+}
+
+// Group version of evaluate_moves: T/G candidates per round, one per group
+// of G lanes.  The shared prefix is decoded by group 0 into the base area;
+// candidates that overflow their profile are decoded afterwards by group 0
+// over the whole candidate region (>= horizon units).
+template <int NW, int T, int G, bool COUNT = false>
+__device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
+                                               int L, int delta, TabuSrc tabu, int asp, int *out_mk,
+                                               long long *ovf_total, long long *work_total = nullptr,
+                                               bool share = true) {
+    constexpr int C = T / G;
+    const int tid = threadIdx.x, grp = tid / G, g = tid & (G - 1);
+    unsigned long long best = ~0ull;
+    long long lw = 0;
+    int *ovf_n = S.scal;
+    int *bstate = S.scal + 1;
+    const bool use_base = share && !COUNT;
+    if (tid == 0) {
+        *ovf_n = 0;
+        bstate[0] = 0;
+        bstate[1] = 0;
+        bstate[2] = 0;
+    }
+    __syncthreads();
+    uint32_t *cb = S.region + grp * Ly.per_lane;
+    const int F0 = (D.n + 1) >> 1;
+    for (int j0 = 0; j0 < nfeas; j0 += C) {
+        if (use_base) {
+            const int ulo = S.moves[j0] & 0xffff;
+            if (grp == 0 && !bstate[2] && bstate[0] < ulo) {
+                bool bovf = false;
+                int bf = bstate[1];
+                decode_tg<NW, G>(S, D, S.bst, L, 0, 0, bstate[0], ulo, bf, bovf);
+                if (g == 0) {
+                    bstate[0] = ulo;
+                    bstate[1] = bf;
+                    bstate[2] = bovf ? 1 : 0;
+                }
+            }
+            __syncthreads();
+        }
+        const int j = j0 + grp;
+        if (j < nfeas) {
+            const uint32_t mv = S.moves[j];
+            const int u = mv & 0xffff, v = mv >> 16;
+            int p0 = 0, front = 0;
+            if (use_base && !bstate[2]) {
+                p0 = bstate[0];
+                front = bstate[1];
+                const int nd = F0 + front * NW;
+                const uint4 *src = reinterpret_cast<const uint4 *>(S.bst);
+                uint4 *dst = reinterpret_cast<uint4 *>(cb);
+                for (int i = g; i < (nd >> 2); i += G) dst[i] = src[i];
+                for (int i = (nd & ~3) + g; i < nd; i += G) cb[i] = S.bst[i];
+                __builtin_amdgcn_wave_barrier();
+            }
+            bool ovf = false;
+            long long cw = 0;
+            const int c = decode_tg<NW, G, COUNT>(S, D, cb, L, u, v, p0, D.n, front, ovf, &cw);
+            if (g == 0) {
+                if (COUNT && !ovf) lw += cw;
+                if (ovf) {
+                    S.moves[j] = mv | 0x80000000u;
+                    atomicAdd(ovf_n, 1);
+                } else {
+                    const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
+                    best = k < best ? k : best;
+                    if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+                }
+            }
+        }
+        if (use_base) __syncthreads();
+    }
+    __syncthreads();
+    if (*ovf_n > 0) {
+        if (grp == 0) {
+            for (int j = 0; j < nfeas; ++j) {
+                const uint32_t mv = S.moves[j];
+                if (mv & 0x80000000u) {
+                    const int u = mv & 0xffff, v = (mv >> 16) & 0x7fff;
+                    bool ovf = false;
+                    int front = 0;
+                    long long cw = 0;
+                    const int c = decode_tg<NW, G, COUNT>(S, D, S.region, Ly.long_len, u, v, 0, D.n, front, ovf, &cw);
+                    if (g == 0) {
+                        if (COUNT) lw += cw;
+                        const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
+                        best = k < best ? k : best;
+                        if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+                        S.moves[j] = mv & 0x7fffffffu;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            if (tid == 0 && ovf_total) *ovf_total += *ovf_n;
+        }
+        __syncthreads();
+    }
+    if (COUNT) {
+        const long long tot = block_sum_i64<T>(lw, S.red);
+        if (tid == 0) *work_total += tot;
+    }
+    return block_min_u64<T>(best, S.red);
+}
+
+// Lane-per-candidate (G = 1) or group decode (G > 1, time-indexed only).
+template <int NW, int T, int DEC, int G, bool COUNT = false>
+__device__ inline unsigned long long evaluate_any(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas, int L,
+                                                  int delta, TabuSrc tabu, int asp, int *out_mk, long long *ovf_total,
+                                                  long long *work_total = nullptr, bool share = true) {
+    if constexpr (G > 1) {
+        static_assert(DEC == kEvalTime, "group decode is time-indexed");
+        return evaluate_moves_g<NW, T, G, COUNT>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk, ovf_total, work_total,
+                                                 share);
+    } else {
+        return evaluate_moves<NW, T, DEC, COUNT>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk, ovf_total,
+                                                 work_total, share);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // rcpsp_evaluate_neighbourhood
 
-template <int NW, int T, int DEC>
+template <int NW, int T, int DEC, int G>
 __global__ __launch_bounds__(T) void k_eval(EvalArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const InstDesc &D = A.D;
@@ -700,7 +932,7 @@ __global__ __launch_bounds__(T) void k_eval(EvalArgs A) {
     __syncthreads();
     TabuSrc tb{nullptr, A.tabu, 0, N};
     const unsigned long long k =
-        evaluate_moves<NW, T, DEC>(S, D, Ly, nf, A.L, A.delta, tb, A.aspiration, A.makespan, nullptr);
+        evaluate_any<NW, T, DEC, G>(S, D, Ly, nf, A.L, A.delta, tb, A.aspiration, A.makespan, nullptr);
     if (tid == 0) {
         if (nf == 0) {
             A.best[0] = 0; A.best[1] = 0; A.best[2] = -1; A.best[3] = 0;
@@ -827,7 +1059,7 @@ struct StepShared {
 // admissible move, Alg. 3), then export for the next exchange round.  The
 // instance blob must be staged.  COUNT adds the algorithmic operations of
 // every decode to the search's work counter.
-template <int NW, int T, int DEC, bool COUNT>
+template <int NW, int T, int DEC, int G, bool COUNT>
 __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, int b, int it0, int n_it) {
     const InstDesc &D = A.D;
     const Layout &Ly = A.Ly;
@@ -946,7 +1178,7 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
             break;
         }
         const unsigned long long key =
-            evaluate_moves<NW, T, DEC, COUNT>(S, D, Ly, nf, A.L, A.delta, tb, asp, nullptr, &sc.overflow, &sc.work,
+            evaluate_any<NW, T, DEC, G, COUNT>(S, D, Ly, nf, A.L, A.delta, tb, asp, nullptr, &sc.overflow, &sc.work,
                                               !A.full_decode);
         if (tid == 0) {
             const int u = (int)((key >> 16) & 0xffff), v = (int)(key & 0xffff);
@@ -1019,14 +1251,14 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
 }
 
 // One workgroup per search of a plan; iterations [it0, it0 + n_it).
-template <int NW, int T, int DEC, bool COUNT>
+template <int NW, int T, int DEC, int G, bool COUNT>
 __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ StepShared ss;
     Sh S = make_sh(lds, A.D, A.Ly);
     stage_blob<T>(lds, A.D, A.Ly);
     __syncthreads();
-    search_step<NW, T, DEC, COUNT>(A, S, ss, blockIdx.x, A.it0, A.n_it);
+    search_step<NW, T, DEC, G, COUNT>(A, S, ss, blockIdx.x, A.it0, A.n_it);
 }
 
 // eq. 8, read as floor(I_block (4 E[a] + E[b]) / (25 * 2^24)) >= 1 with the
@@ -1191,7 +1423,7 @@ __device__ inline int upper_index(const int *a, int n, int x) {
 static_assert(sizeof(SearchArgs) + sizeof(StepShared) + 4 * sizeof(int) + 64 <= kBatchStaticLds,
               "batch kernel static LDS");
 
-template <int NW, int T, int DEC>
+template <int NW, int T, int DEC, int G>
 __global__ __launch_bounds__(T) void k_batch(BatchClassArgs C) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ SearchArgs A;
@@ -1253,8 +1485,8 @@ __global__ __launch_bounds__(T) void k_batch(BatchClassArgs C) {
         }
         stage_blob<T>(lds, A.D, A.Ly);
         __syncthreads();
-        if (A.NF > 0) search_step<NW, T, DEC, false>(A, S, ss, b, it, A.iters > 0 ? 1 : 0);
-        else search_step<NW, T, DEC, false>(A, S, ss, b, 0, A.iters);
+        if (A.NF > 0) search_step<NW, T, DEC, G, false>(A, S, ss, b, it, A.iters > 0 ? 1 : 0);
+        else search_step<NW, T, DEC, G, false>(A, S, ss, b, 0, A.iters);
         if (tid == 0) {
             const int old = __hip_atomic_fetch_add(&C.done[j], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
             task[0] = old + 1 == (it + 1) * A.B && A.NF > 0 && it < steps - 1;
@@ -1289,7 +1521,7 @@ __global__ void k_fill_zero(int *p, long long n) {
 // pending = 0 means no task can be queued any more: waiting workgroups then
 // leave.  Tasks only ever wait for the queue, never for each other.
 
-template <int NW, int T, int DEC>
+template <int NW, int T, int DEC, int G>
 __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ SearchArgs A;
@@ -1353,7 +1585,7 @@ __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
         } else {
             stage_blob<T>(lds, A.D, A.Ly);
             __syncthreads();
-            search_step<NW, T, DEC, false>(A, S, ss, b, it, 1);
+            search_step<NW, T, DEC, G, false>(A, S, ss, b, it, 1);
             if (tid == 0) {
                 const int old = __hip_atomic_fetch_add(&R->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
                 int fin = -1;
@@ -1438,29 +1670,39 @@ __global__ void k_clock(long long *out) {
 // ---------------------------------------------------------------------------
 // Launchers
 
-#define RCPSP_DISPATCH(NWV, TV, DECV, CALL)                                                 \
-    switch (DECV) {                                                                         \
-    case kEvalCapacity:                                                                     \
-        switch (TV) {                                                                       \
-        case 64: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity; CALL; } break;     \
-        case 128: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity; CALL; } break;   \
-        case 256: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity; CALL; } break;   \
-        default: return hipErrorInvalidValue;                                               \
-        }                                                                                   \
-        break;                                                                              \
-    default:                                                                                \
-        switch ((TV) * 16 + (NWV)) {                                                        \
-        case 64 * 16 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime; CALL; } break;    \
-        case 64 * 16 + 2: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime; CALL; } break;    \
-        case 64 * 16 + 4: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime; CALL; } break;    \
-        case 128 * 16 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime; CALL; } break;  \
-        case 128 * 16 + 2: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime; CALL; } break;  \
-        case 128 * 16 + 4: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime; CALL; } break;  \
-        case 256 * 16 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime; CALL; } break;  \
-        case 256 * 16 + 2: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime; CALL; } break;  \
-        case 256 * 16 + 4: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime; CALL; } break;  \
-        default: return hipErrorInvalidValue;                                               \
-        }                                                                                   \
+#define RCPSP_DISPATCH(NWV, TV, DECV, GV, CALL)                                                                      \
+    switch (DECV) {                                                                                                  \
+    case kEvalCapacity:                                                                                              \
+        if ((GV) != 1) return hipErrorInvalidValue;                                                                  \
+        switch (TV) {                                                                                                \
+        case 64: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;                      \
+        case 128: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;                    \
+        case 256: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;                    \
+        default: return hipErrorInvalidValue;                                                                        \
+        }                                                                                                            \
+        break;                                                                                                       \
+    default:                                                                                                         \
+        switch (((TV) * 16 + (NWV)) * 32 + (GV)) {                                                                   \
+        case (64 * 16 + 1) * 32 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
+        case (64 * 16 + 1) * 32 + 16: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
+        case (64 * 16 + 2) * 32 + 1: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
+        case (64 * 16 + 2) * 32 + 16: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
+        case (64 * 16 + 4) * 32 + 1: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
+        case (64 * 16 + 4) * 32 + 16: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
+        case (128 * 16 + 1) * 32 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (128 * 16 + 1) * 32 + 16: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        case (128 * 16 + 2) * 32 + 1: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (128 * 16 + 2) * 32 + 16: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        case (128 * 16 + 4) * 32 + 1: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (128 * 16 + 4) * 32 + 16: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        case (256 * 16 + 1) * 32 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (256 * 16 + 1) * 32 + 16: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        case (256 * 16 + 2) * 32 + 1: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (256 * 16 + 2) * 32 + 16: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        case (256 * 16 + 4) * 32 + 1: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (256 * 16 + 4) * 32 + 16: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        default: return hipErrorInvalidValue;                                                                        \
+        }                                                                                                            \
     }
 
 template <typename K>
@@ -1469,11 +1711,11 @@ static hipError_t set_lds(K kernel, size_t lds) {
                                (int)lds);
 }
 
-hipError_t launch_eval(const EvalArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
-    RCPSP_DISPATCH(nw, T, dec, {
-        hipError_t e = set_lds(k_eval<NW_, T_, DEC_>, lds);
+hipError_t launch_eval(const EvalArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, G, {
+        hipError_t e = set_lds(k_eval<NW_, T_, DEC_, G_>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_eval<NW_, T_, DEC_>), dim3(1), dim3(T_), lds, st, A);
+        hipLaunchKernelGGL((k_eval<NW_, T_, DEC_, G_>), dim3(1), dim3(T_), lds, st, A);
     });
     return hipGetLastError();
 }
@@ -1487,13 +1729,13 @@ hipError_t launch_reset(const SearchArgs &A, hipStream_t st) {
 size_t round_lds_bytes(int B, int NF) { return sizeof(int) * (6 * (size_t)B + 5 * (size_t)NF); }
 
 // Raise the dynamic LDS limit of the search kernels (outside graph capture).
-hipError_t prepare_search(int T, int nw, int dec, size_t lds, int B, int NF) {
-    RCPSP_DISPATCH(nw, T, dec, {
+hipError_t prepare_search(int T, int nw, int dec, int G, size_t lds, int B, int NF) {
+    RCPSP_DISPATCH(nw, T, dec, G, {
         hipError_t e = set_lds(k_decode_records<NW_, T_, DEC_>, lds);
         if (e != hipSuccess) return e;
-        e = set_lds(k_search<NW_, T_, DEC_, false>, lds);
+        e = set_lds(k_search<NW_, T_, DEC_, G_, false>, lds);
         if (e != hipSuccess) return e;
-        e = set_lds(k_search<NW_, T_, DEC_, true>, lds);
+        e = set_lds(k_search<NW_, T_, DEC_, G_, true>, lds);
         if (e != hipSuccess) return e;
     });
     if (NF > 0) return set_lds(k_round, round_lds_bytes(B, NF));
@@ -1501,44 +1743,45 @@ hipError_t prepare_search(int T, int nw, int dec, size_t lds, int B, int NF) {
 }
 
 hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
-    RCPSP_DISPATCH(nw, T, dec, {
+    RCPSP_DISPATCH(nw, T, dec, 1, {
         hipLaunchKernelGGL((k_decode_records<NW_, T_, DEC_>), dim3(A.NF), dim3(T_), lds, st, A);
     });
     return hipGetLastError();
 }
 
-hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
-    RCPSP_DISPATCH(nw, T, dec, {
+hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, G, {
         if (A.count_work)
-            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, true>), dim3(A.B), dim3(T_), lds, st, A);
+            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, G_, true>), dim3(A.B), dim3(T_), lds, st, A);
         else
-            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, false>), dim3(A.B), dim3(T_), lds, st, A);
+            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, G_, false>), dim3(A.B), dim3(T_), lds, st, A);
     });
     return hipGetLastError();
 }
 
-hipError_t prepare_batch(int T, int nw, int dec, size_t lds) {
-    RCPSP_DISPATCH(nw, T, dec, {
-        hipError_t e = set_lds(k_batch<NW_, T_, DEC_>, lds);
+hipError_t prepare_batch(int T, int nw, int dec, int G, size_t lds) {
+    RCPSP_DISPATCH(nw, T, dec, G, {
+        hipError_t e = set_lds(k_batch<NW_, T_, DEC_, G_>, lds);
         if (e != hipSuccess) return e;
     });
     return hipSuccess;
 }
 
-hipError_t batch_occupancy(int T, int nw, int dec, size_t lds, int *per_cu) {
+hipError_t batch_occupancy(int T, int nw, int dec, int G, size_t lds, int *per_cu) {
     *per_cu = 0;
-    RCPSP_DISPATCH(nw, T, dec, {
-        hipError_t e = set_lds(k_batch<NW_, T_, DEC_>, lds);
+    RCPSP_DISPATCH(nw, T, dec, G, {
+        hipError_t e = set_lds(k_batch<NW_, T_, DEC_, G_>, lds);
         if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<NW_, T_, DEC_>, T_, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<NW_, T_, DEC_, G_>, T_, lds);
         if (e != hipSuccess) return e;
     });
     return hipSuccess;
 }
 
-hipError_t launch_batch(const BatchClassArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st) {
-    RCPSP_DISPATCH(nw, T, dec, {
-        hipLaunchKernelGGL((k_batch<NW_, T_, DEC_>), dim3(grid), dim3(T_), lds, st, C);
+hipError_t launch_batch(const BatchClassArgs &C, int grid, int T, int nw, int dec, int G, size_t lds,
+                        hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, G, {
+        hipLaunchKernelGGL((k_batch<NW_, T_, DEC_, G_>), dim3(grid), dim3(T_), lds, st, C);
     });
     return hipGetLastError();
 }
@@ -1551,20 +1794,20 @@ hipError_t launch_fill_zero(int *p, long long n, hipStream_t st) {
 
 size_t batch_queue_bytes() { return sizeof(BatchQueue); }
 
-hipError_t serve_occupancy(int T, int nw, int dec, size_t lds, int *per_cu) {
+hipError_t serve_occupancy(int T, int nw, int dec, int G, size_t lds, int *per_cu) {
     *per_cu = 0;
-    RCPSP_DISPATCH(nw, T, dec, {
-        hipError_t e = set_lds(k_serve<NW_, T_, DEC_>, lds);
+    RCPSP_DISPATCH(nw, T, dec, G, {
+        hipError_t e = set_lds(k_serve<NW_, T_, DEC_, G_>, lds);
         if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_serve<NW_, T_, DEC_>, T_, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_serve<NW_, T_, DEC_, G_>, T_, lds);
         if (e != hipSuccess) return e;
     });
     return hipSuccess;
 }
 
-hipError_t launch_serve(const ServeArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st) {
-    RCPSP_DISPATCH(nw, T, dec, {
-        hipLaunchKernelGGL((k_serve<NW_, T_, DEC_>), dim3(grid), dim3(T_), lds, st, C);
+hipError_t launch_serve(const ServeArgs &C, int grid, int T, int nw, int dec, int G, size_t lds, hipStream_t st) {
+    RCPSP_DISPATCH(nw, T, dec, G, {
+        hipLaunchKernelGGL((k_serve<NW_, T_, DEC_, G_>), dim3(grid), dim3(T_), lds, st, C);
     });
     return hipGetLastError();
 }

@@ -17,13 +17,13 @@ struct EvalArgs {
     int32_t *best;          // device [4]
 };
 
-hipError_t launch_eval(const EvalArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t launch_eval(const EvalArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
 hipError_t launch_reset(const SearchArgs &A, hipStream_t st);
 hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st);
-hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
 hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t st);
 size_t round_lds_bytes(int B, int NF);
-hipError_t prepare_search(int T, int nw, int dec, size_t lds, int B, int NF);
+hipError_t prepare_search(int T, int nw, int dec, int G, size_t lds, int B, int NF);
 
 struct BatchQueue;
 
@@ -46,9 +46,10 @@ struct BatchClassArgs {
 };
 
 size_t batch_queue_bytes();
-hipError_t prepare_batch(int T, int nw, int dec, size_t lds);
-hipError_t batch_occupancy(int T, int nw, int dec, size_t lds, int *per_cu);
-hipError_t launch_batch(const BatchClassArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t prepare_batch(int T, int nw, int dec, int G, size_t lds);
+hipError_t batch_occupancy(int T, int nw, int dec, int G, size_t lds, int *per_cu);
+hipError_t launch_batch(const BatchClassArgs &C, int grid, int T, int nw, int dec, int G, size_t lds,
+                        hipStream_t st);
 hipError_t launch_fill_zero(int *p, long long n, hipStream_t st);
 
 // Serving: per-request control block in device memory (64 bytes).
@@ -91,8 +92,8 @@ __host__ __device__ inline unsigned long long serve_task(int slot, int kind, int
            (unsigned long long)it;
 }
 
-hipError_t serve_occupancy(int T, int nw, int dec, size_t lds, int *per_cu);
-hipError_t launch_serve(const ServeArgs &C, int grid, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t serve_occupancy(int T, int nw, int dec, int G, size_t lds, int *per_cu);
+hipError_t launch_serve(const ServeArgs &C, int grid, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
 hipError_t launch_serve_begin(ServeQueue *q, unsigned long long *tasks, long long cap, long long n0,
                               hipStream_t st);
 hipError_t launch_clock(long long *out, hipStream_t st);

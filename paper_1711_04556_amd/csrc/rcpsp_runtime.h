@@ -48,6 +48,7 @@ struct rcpsp_search {
     const rcpsp_instance *inst = nullptr;
     rcpsp_search_params p{};
     int T = 64, L = 0, nw = 1, dec = 1, tcw = 1, P = 0;
+    int G = 1;            // lanes per candidate (1, or 16 for the time-indexed group decode)
     int reserve = 256;    // static LDS of the kernel the plan runs in
     rcpsp::Layout Ly{};
     size_t lds = 0;

@@ -125,7 +125,7 @@ struct Req {
 };
 
 struct SClass {
-    int dec = 0, nw = 0, T = 0;
+    int dec = 0, nw = 0, T = 0, G = 1;
     unsigned long long *d_tasks = nullptr;
     ServeQueue *d_q = nullptr;
     unsigned long long *h_tasks = nullptr;   // pinned staging
@@ -187,7 +187,8 @@ void set_failed(rcpsp_server *s, rcpsp_status st, const char *msg) {
 rcpsp_status class_of(rcpsp_server *s, const rcpsp_search *plan, int *out) {
     const int nw = plan->dec == kEvalTime ? plan->nw : 1;
     for (size_t k = 0; k < s->classes.size(); ++k)
-        if (s->classes[k].dec == plan->dec && s->classes[k].nw == nw && s->classes[k].T == plan->T) {
+        if (s->classes[k].dec == plan->dec && s->classes[k].nw == nw && s->classes[k].T == plan->T &&
+            s->classes[k].G == plan->G) {
             *out = (int)k;
             return RCPSP_OK;
         }
@@ -195,6 +196,7 @@ rcpsp_status class_of(rcpsp_server *s, const rcpsp_search *plan, int *out) {
     c.dec = plan->dec;
     c.nw = nw;
     c.T = plan->T;
+    c.G = plan->G;
     HIP_TRY(hipMalloc(&c.d_tasks, sizeof(unsigned long long) * kServeTaskCap));
     HIP_TRY(hipMalloc(&c.d_q, sizeof(ServeQueue)));
     HIP_TRY(hipStreamCreateWithFlags(&c.st, hipStreamNonBlocking));
@@ -314,7 +316,7 @@ rcpsp_status run_slice(rcpsp_server *s, const std::vector<Req *> &fresh) {
         HIP_TRY(hipMemcpyAsync(C.d_tasks, C.h_tasks, sizeof(unsigned long long) * n0, hipMemcpyHostToDevice, C.st));
         HIP_TRY(launch_serve_begin(C.d_q, C.d_tasks, kServeTaskCap, (long long)n0, C.st));
         int per_cu = 0;
-        HIP_TRY(serve_occupancy(C.T, C.nw, C.dec, lds[c], &per_cu));
+        HIP_TRY(serve_occupancy(C.T, C.nw, C.dec, C.G, lds[c], &per_cu));
         if (per_cu < 1) return fail(RCPSP_E_TOO_LARGE, "serving workgroup of %zu B LDS does not fit a CU", lds[c]);
         ServeArgs A{};
         A.items = s->d_items;
@@ -324,7 +326,7 @@ rcpsp_status run_slice(rcpsp_server *s, const std::vector<Req *> &fresh) {
         A.cap = kServeTaskCap;
         A.slice_end = slice_end;
         A.wait_ticks = kServeWaitTicks;
-        HIP_TRY(launch_serve(A, per_cu * s->cus, C.T, C.nw, C.dec, lds[c], C.st));
+        HIP_TRY(launch_serve(A, per_cu * s->cus, C.T, C.nw, C.dec, C.G, lds[c], C.st));
         ++launched;
     }
     for (int c = 0; c < nc; ++c) HIP_TRY(hipStreamSynchronize(s->classes[c].st));
@@ -514,6 +516,8 @@ extern "C" rcpsp_status rcpsp_server_submit(rcpsp_server *s, const rcpsp_instanc
     st = alloc_plan(&probe);
     probe.allocs.clear();
     if (st != RCPSP_OK) return st;
+    if (params->elite > 0 && 6 * params->searches + 5 * params->elite > probe.Ly.cands * probe.Ly.per_lane)
+        return fail(RCPSP_E_TOO_LARGE, "exchange bookkeeping does not fit the workgroup's LDS");
     if (m.total > s->arena.size())
         return fail(RCPSP_E_TOO_LARGE, "request state of %zu B exceeds the arena (%zu B)", m.total, s->arena.size());
     Req *r = new (std::nothrow) Req();

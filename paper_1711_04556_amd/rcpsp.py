@@ -44,12 +44,12 @@ class rcpsp_move(ctypes.Structure):
 class rcpsp_search_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
-        "profile_len", "record_trajectory", "count_work", "full_decode", "eval")] + [("seed", ctypes.c_uint64)]
+        "profile_len", "record_trajectory", "count_work", "full_decode", "eval", "lanes")] + [("seed", ctypes.c_uint64)]
 
 
 class rcpsp_tuning(ctypes.Structure):
     _fields_ = [("eval", ctypes.c_int32), ("threads", ctypes.c_int32), ("profile_len", ctypes.c_int32),
-                ("trials", ctypes.c_int32), ("ns_per_evaluation", ctypes.c_double)]
+                ("trials", ctypes.c_int32), ("lanes", ctypes.c_int32), ("ns_per_evaluation", ctypes.c_double)]
 
 
 class rcpsp_search_result(ctypes.Structure):
@@ -69,7 +69,8 @@ class rcpsp_batch_info(ctypes.Structure):
 
 class rcpsp_batch_tuning(ctypes.Structure):
     _fields_ = [("groups", ctypes.c_int32), ("trials", ctypes.c_int32)] + [
-        (n, ctypes.c_int32 * 8) for n in ("group_n", "group_m", "group_members", "group_eval", "group_threads")] + [
+        (n, ctypes.c_int32 * 8) for n in ("group_n", "group_m", "group_members", "group_eval", "group_threads",
+                                          "group_lanes")] + [
         ("group_evals_per_s", ctypes.c_double * 8)]
 
 
@@ -95,7 +96,7 @@ REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 class rcpsp_search_config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches")]
+        "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches", "lanes")]
 
 
 _lib = None
@@ -269,9 +270,10 @@ class Instance:
 def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                   phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
                   record_trajectory: bool = True, count_work: bool = False, full_decode: bool = False,
-                  eval: int = EVAL_AUTO, seed: int = 1) -> rcpsp_search_params:
+                  eval: int = EVAL_AUTO, seed: int = 1, lanes: int = 0) -> rcpsp_search_params:
     return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
-                               profile_len, int(record_trajectory), int(count_work), int(full_decode), eval, seed)
+                               profile_len, int(record_trajectory), int(count_work), int(full_decode), eval, lanes,
+                               seed)
 
 
 def autotune(instance: "Instance", params: rcpsp_search_params, trial_iterations: int = 10, stream=None):
@@ -381,7 +383,8 @@ def batch_autotune(instances: Sequence["Instance"], params, trial_iterations: in
                                       ctypes.byref(info)))
     g = info.groups
     d = {"groups": g, "trials": info.trials}
-    for k in ("group_n", "group_m", "group_members", "group_eval", "group_threads", "group_evals_per_s"):
+    for k in ("group_n", "group_m", "group_members", "group_eval", "group_threads", "group_lanes",
+              "group_evals_per_s"):
         d[k] = list(getattr(info, k))[:min(g, 8)]
     res = []
     for i in range(n):

@@ -343,3 +343,93 @@ def test_batch_matches_oracle_and_plans(rc):
     for i in range(len(insts)):
         assert np.array_equal(first[i], bt.results(i)["trajectory"])
     bt.close()
+
+
+# ---------------------------------------------------------------------------
+# Group decode: 16 lanes per candidate (time-indexed).  Same results as one
+# candidate per lane and as the oracle.
+
+GROUP_CASES = [
+    ("g30", lambda: synth.single_instance_30(1), 8),
+    ("g60", lambda: synth.generate(60, 4, 10, 0.5, rs=0.3, seed=63), 14),
+    ("wide40", _wide_instance, 12),
+    ("m8", lambda: synth.generate(50, 8, 20, 0.5, rs=None, cap_range=(10, 60), seed=4001), 20),
+    ("serial14", _serial_instance, 5),
+]
+
+
+@pytest.mark.parametrize("name,make,delta", GROUP_CASES, ids=[c[0] for c in GROUP_CASES])
+@pytest.mark.parametrize("threads", [64, 256])
+def test_group_decode_search_parity(rc, name, make, delta, threads):
+    inst = make()
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=delta, tabu_len=30, iterations=25, searches=6, elite=3, phi_max=2, phi_steps=4, seed=8)
+    plan = rc.SearchPlan(gi, rc.search_params(threads=threads, lanes=16, **kw))
+    assert plan.config["lanes"] == 16
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(delta, 30, 25, searches=6, elite=3, phi_max=2, phi_steps=4, decoder=TIME, seed=8)
+    _compare_search(g, o, elite=3)
+
+
+def test_group_decode_overflow_path(rc):
+    """A 16-unit profile per candidate sends most candidates through the
+    group's long-profile decode; results must not change."""
+    inst = synth.single_instance_30(1)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    g = rc.tabu_search(gi, swap_range=8, tabu_len=60, iterations=30, searches=2, profile_len=16, lanes=16, seed=2)
+    o = orc.tabu_search(8, 60, 30, searches=2, decoder=TIME, seed=2)
+    _compare_search(g, o)
+    assert g["overflow_decodes"] > 0
+
+
+def test_group_decode_counts_same_work(rc):
+    """The instrumented group decode counts the same algorithmic operations
+    as the one-lane decode (a property of the method, not of the launch)."""
+    inst = synth.generate(40, 4, 10, 0.5, rs=0.3, seed=24)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True)
+    a = rc.tabu_search(gi, lanes=1, **kw)
+    b = rc.tabu_search(gi, lanes=16, **kw)
+    for k in ("trajectory", "best_makespan", "evaluations"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["total_work"] == b["total_work"] > 0
+
+
+def test_large_instance_time_indexed_group(rc):
+    """300 activities, 8 resources, durations 1..20: the per-lane profile does
+    not fit, so the automatic plan takes 16 lanes per candidate with the
+    time-indexed decoder; neighbourhood and a short cooperative search equal
+    the oracle."""
+    inst = synth.large_batch(1)[0]
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    W = orc.initial_order(3, 0)
+    mk_g, best_g = gi.evaluate_neighbourhood(W, 20)
+    mk_o, best_o = orc.evaluate_neighbourhood(W, 20, TIME)
+    assert np.array_equal(mk_g, mk_o), np.nonzero(mk_g != mk_o)[0][:10]
+    assert [best_g["u"], best_g["v"], best_g["makespan"], best_g["n_feasible"]] == best_o
+    plan = rc.SearchPlan(gi, rc.search_params(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, seed=3))
+    assert plan.config["lanes"] == 16 and plan.config["eval"] == TIME
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, decoder=TIME, seed=3)
+    _compare_search(g, o, elite=4)
+
+
+def test_batch_mixes_lane_and_group_decode(rc):
+    insts = _batch_case()[:4]
+    gis = [rc.Instance(i, eval=TIME) for i in insts]
+    params = [rc.search_params(7, 30, 10, searches=5, elite=3, phi_max=2, phi_steps=4, threads=64,
+                               lanes=(1 if k % 2 else 16), seed=40 + k) for k in range(len(insts))]
+    bt = rc.Batch(gis, params)
+    bt.run()
+    for k, inst in enumerate(insts):
+        o = oracle.Oracle(inst).tabu_search(7, 30, 10, searches=5, elite=3, phi_max=2, phi_steps=4, decoder=TIME,
+                                            seed=40 + k)
+        _compare_search(bt.results(k), o, elite=3)
+    bt.close()
