@@ -24,6 +24,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the serving leg runs one stream per launch class side by side; HIP maps
+# streams onto this many hardware queues, and streams sharing a queue wait
+# for each other's kernels (set before the HIP runtime starts)
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "SSGS neighbour evals/s (batched vs plain) at bit-exact makespan; p50/p99 latency"
 PEAK_INT_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
@@ -37,8 +41,13 @@ BATCH = dict(count=1024, base_seed=3000, searches=32, elite=16, phi_max=3, phi_s
 BATCH_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329)}
 # serving leg: open-loop Poisson arrivals, 50 ms budget from admission
 SERVE = dict(rate=2000.0, warmup_s=2.0, measure_s=10.0, budget_us=50000, searches=16, elite=16, iterations=1000,
-             phi_max=3, phi_steps=20, seed=5, pool=256)
+             phi_max=3, phi_steps=20, seed=5, pool=256, max_active=1024)
 SERVE_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329), 302: (20, 869)}
+# large-instance leg: 256 instances of 300 activities, 8 resources; the
+# workload's 2000 iterations take over an hour at the measured rate, so a
+# few iterations are timed and the rate is reported
+LARGE = dict(count=256, base_seed=4000, searches=16, elite=16, phi_max=3, phi_steps=20, iterations=4,
+             swap_range=20, tabu_len=869)
 
 
 def log(*a):
@@ -167,6 +176,46 @@ def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
     }
 
 
+def large_leg(rcpsp, synth, stream, steps):
+    import torch
+    t0 = time.perf_counter()
+    insts = synth.large_batch(LARGE["count"], LARGE["base_seed"])
+    gis = [rcpsp.Instance(i) for i in insts]
+    base = rcpsp.search_params(LARGE["swap_range"], LARGE["tabu_len"], LARGE["iterations"],
+                               searches=LARGE["searches"], elite=LARGE["elite"], phi_max=LARGE["phi_max"],
+                               phi_steps=LARGE["phi_steps"], record_trajectory=False, seed=LARGE["base_seed"])
+    t1 = time.perf_counter()
+    params, tuning = rcpsp.batch_autotune(gis, base, trial_iterations=1, sample=16, stream=stream)
+    tuning["seconds"] = time.perf_counter() - t1
+    log("large autotune", tuning)
+    bt = rcpsp.Batch(gis, params, stream)
+    info = bt.info
+    bt.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bt.run(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = [bt.results(k, stream, orders=False, trajectory=False) for k in range(len(insts))]
+    evals = sum(r["total_evaluations"] for r in res)
+    bt.close()
+    out = {
+        "workload": f"{len(insts)} instances of 300 activities (8 resources, durations 1..20, capacities 10..60), "
+                    f"{LARGE['searches']} searches and working set {LARGE['elite']} each, swap range 20, tabu list "
+                    f"869, {LARGE['iterations']} iterations timed (the workload's 2000 would take "
+                    f"{dt / steps / LARGE['iterations'] * 2000 / 60:.0f} min at this rate)",
+        "value": evals * steps / dt,
+        "unit": "evals/s",
+        "ms_per_iteration": dt / steps / LARGE["iterations"] * 1e3,
+        "evaluations_per_step": evals,
+        "classes": info,
+        "autotune": tuning,
+    }
+    log("large", out)
+    return out
+
+
 def pct(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
@@ -192,7 +241,7 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
     log("serving set-up", f"{time.perf_counter() - t0:.1f} s")
     arrivals = synth.serving_arrivals(rate, warmup_s + measure_s, SERVE["seed"])
     sizes = synth.SERVING_SIZES
-    srv = rcpsp.Server(max_active=1024, slice_us=1000, arena_bytes=8 << 30)
+    srv = rcpsp.Server(max_active=SERVE["max_active"], slice_us=1000, arena_bytes=8 << 30)
     counters = {n: 0 for n in sizes}
     info_of = {}
     start = srv.now_ns() + 50_000_000
@@ -235,6 +284,9 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
     lat = [(r[3]["seen_ns"] - r[2]) * 1e-6 for r in ok]
     lat_dev = [(r[3]["done_ns"] - r[2]) * 1e-6 for r in ok]
     queue = [(r[3]["admit_ns"] - r[2]) * 1e-6 for r in ok]
+    submit_lag = [(r[3]["submit_ns"] - r[2]) * 1e-6 for r in ok]
+    admit_wait = [(r[3]["admit_ns"] - r[3]["submit_ns"]) * 1e-6 for r in ok]
+    run_time = [(r[3]["done_ns"] - r[3]["admit_ns"]) * 1e-6 for r in ok]
     evals = sum(r[3]["evaluations"] for r in ok)
     per_size = {}
     for n in sizes:
@@ -250,7 +302,7 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
                     f"warm-up), sizes uniform over 30/60/120/300 activities ({SERVE['pool']} distinct instances "
                     f"per size, cycled), {SERVE['searches']} searches and working set {SERVE['elite']} per "
                     f"request, {SERVE['budget_us'] // 1000} ms budget from admission, allowance "
-                    f"{SERVE['iterations']} iterations",
+                    f"{SERVE['iterations']} iterations, at most {SERVE['max_active']} requests resident",
         "requests_measured": len(meas),
         "completed": len(ok),
         "unfinished_at_cutoff": unfinished,
@@ -259,8 +311,14 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
         "p50_ms_device_end": pct(lat_dev, 50),
         "p99_ms_device_end": pct(lat_dev, 99),
         "queueing_p99_ms": pct(queue, 99),
+        "submit_lag_p50_ms": pct(submit_lag, 50),
+        "admission_wait_p50_ms": pct(admit_wait, 50),
+        "admission_wait_p99_ms": pct(admit_wait, 99),
+        "admitted_to_end_p50_ms": pct(run_time, 50),
+        "admitted_to_end_p99_ms": pct(run_time, 99),
         "evals_per_s": evals / measure_s,
         "per_size": per_size,
+        "device_clock_mhz": stats["device_clock_mhz"],
         "slices": stats["slices"],
         "slice_busy_ms_mean": stats["busy_ms"] / max(stats["slices"], 1),
     }
@@ -285,6 +343,7 @@ def main():
                          "then one run of the headline plan")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-instance leg")
     ap.add_argument("--serve-rate", type=float, default=SERVE["rate"])
     ap.add_argument("--serve-seconds", type=float, default=SERVE["measure_s"])
     args = ap.parse_args()
@@ -415,11 +474,14 @@ def main():
         },
         "batched": None,
         "serving": None,
+        "large": None,
         "cpu_baseline": None,
     }
     plan.close()
     if not args.no_batch:
         out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, min(args.warmup, 1))
+    if not args.no_large:
+        out["large"] = large_leg(rcpsp, synth, stream, 1)
     if not args.no_serve:
         out["serving"] = serving_leg(rcpsp, synth, stream, args.serve_rate, SERVE["warmup_s"], args.serve_seconds)
     if not args.no_cpu:

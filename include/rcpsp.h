@@ -271,11 +271,16 @@ rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_param
 
 /* Serving (requests admitted as they arrive).  A server owns a device arena
  * for search state and a host thread that runs the device in time slices:
- * at each slice boundary it admits queued requests in arrival order while
- * the arena has room for their state and fewer than max_active are
- * resident, then launches one persistent kernel per class (decoder, profile
- * width, threads per search) that sets up the new requests and advances
- * every resident request iteration by iteration, each at its own pace.  A
+ * at each slice boundary it admits queued requests while the arena has room
+ * for their state — one queue per launch class (decoder, profile width,
+ * threads per search, lanes per candidate), each in arrival order, each
+ * class holding at most an equal share of max_active resident slots among
+ * the classes with work, so long requests of one class do not block the
+ * others.  Each class runs its own slices: a persistent kernel on the
+ * class's stream (its grid an equal share of the CUs among the classes with
+ * running requests) sets up the new requests and advances every resident
+ * request of the class iteration by iteration, each at its own pace; when a
+ * slice ends the host takes the finished requests and starts the next.  A
  * request ends at the first iteration boundary where its iteration
  * allowance is used up, its time budget (counted from admission) has passed,
  * every search has stopped, the working set reached the critical path, or
@@ -309,6 +314,7 @@ typedef struct {
     int64_t evaluations;      /* of completed requests */
     int32_t resident, queued;
     int64_t arena_used, arena_bytes;
+    double device_clock_mhz;  /* measured rate of the device wall clock the deadlines use */
 } rcpsp_server_stats;
 rcpsp_status rcpsp_server_create(const rcpsp_server_params *params, rcpsp_server **out);
 /* Queue a solve (non-blocking).  params: as for a search plan

@@ -389,10 +389,21 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
         *Ly = make_layout(D, T, tcw, tl, pmax, L, dec, G);
         return Ly->long_len >= I->H && (size_t)Ly->total * 4 <= (size_t)budget;
     };
+    // smallest L' >= L (at most H) whose region holds the long profile
+    // (long_len grows with L, so a binary search finds it)
+    auto cover = [&](int L) {
+        if (L >= H || make_layout(D, T, tcw, tl, pmax, L, dec, G).long_len >= I->H) return std::min(L, H);
+        int lo = L, hi = H;  // long_len(lo) < H; hi satisfies or is H
+        while (hi - lo > 1) {
+            const int mid = lo + (hi - lo) / 2;
+            if (make_layout(D, T, tcw, tl, pmax, mid, dec, G).long_len >= I->H) hi = mid;
+            else lo = mid;
+        }
+        return hi;
+    };
     Layout Ly;
     if (L_req > 0) {
-        int L = std::min(L_req, H);
-        while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec, G).long_len < I->H) ++L;
+        int L = cover(std::min(L_req, H));
         if (!fits(L, &Ly))
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
         *L_out = L;
@@ -400,8 +411,7 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
         return RCPSP_OK;
     }
     int L = std::min(H, ((14 * I->cp + 9) / 10 + 2 * I->dmax + 15) / 16 * 16);
-    L = std::max(L, 1);
-    while (L < H && make_layout(D, T, tcw, tl, pmax, L, dec, G).long_len < I->H) ++L;
+    L = cover(std::max(L, 1));
     // shorter profiles trade LDS for long-profile decodes; below the critical
     // path plus the longest duration nearly every candidate would take that
     // path, so the decoder does not fit
@@ -412,12 +422,22 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
                         T, L);
         L = std::max(Lfloor, L * 3 / 4);
     }
+    // stretch by steps of 4 while it fits and the workgroups per CU stay the
+    // same (both monotone in L: binary search over the number of steps)
     const int k0 = lds_occupancy((size_t)Ly.total * 4, reserve);
     Layout Ln;
-    while (L + 4 <= H && fits(L + 4, &Ln) && lds_occupancy((size_t)Ln.total * 4, reserve) >= k0) {
-        L += 4;
-        Ly = Ln;
+    auto ok = [&](int k) {
+        const int Lk = L + 4 * k;
+        return Lk <= H && fits(Lk, &Ln) && lds_occupancy((size_t)Ln.total * 4, reserve) >= k0;
+    };
+    int klo = 0, khi = (H - L) / 4 + 1;  // ok(klo) holds, ok(khi) does not
+    while (khi - klo > 1) {
+        const int mid = klo + (khi - klo) / 2;
+        if (ok(mid)) klo = mid;
+        else khi = mid;
     }
+    L += 4 * klo;
+    fits(L, &Ly);
     *L_out = L;
     *Ly_out = Ly;
     return RCPSP_OK;

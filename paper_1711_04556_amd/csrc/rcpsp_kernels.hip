@@ -1512,28 +1512,32 @@ __global__ void k_fill_zero(int *p, long long n) {
 // ---------------------------------------------------------------------------
 // Serving: requests arrive over time; each keeps its search state in device
 // memory and advances in time slices.  A slice is one persistent launch per
-// class over a task queue that grows while it runs: the host queues a set-up
-// task for every new request and the tasks of the next iteration of every
-// running one; the task that completes the last search of an iteration ends
-// the request (allowance, deadline, global stop, cancel) or runs its exchange
-// round and, while the slice lasts, queues the next iteration's tasks.  A
-// task is counted in `pending` from being queued until it finishes, so
-// pending = 0 means no task can be queued any more: waiting workgroups then
-// leave.  Tasks only ever wait for the queue, never for each other.
+// class over a task queue that grows while it runs: the host seeds it with
+// the tasks left from the previous slice and a set-up task per new request;
+// the task that completes the last search of an iteration ends the request
+// (allowance, deadline, global stop, cancel) or runs its exchange round and
+// queues the next iteration's tasks.  Workgroups take no task after the
+// slice's end time, and a finished task's slot is marked done, so the host
+// carries every queued task that did not run over to the next slice: a slice
+// ends one task duration after its end time, whatever the backlog.  A task
+// is counted in `pending` from being queued until it finishes, so pending = 0
+// means no task can be queued any more.  Tasks only ever wait for the queue,
+// never for each other.
 
 template <int NW, int T, int DEC, int G>
 __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ SearchArgs A;
     __shared__ StepShared ss;
-    __shared__ long long tk;
+    __shared__ long long tk, hslot;
     __shared__ int flag;
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0) {
             long long task = -1;
-            const unsigned long long h = atomicAdd(&C.q->head, 1ull);
-            if ((long long)h < C.cap) {
+            unsigned long long h = ~0ull;
+            if ((long long)wall_clock64() < C.slice_end) h = atomicAdd(&C.q->head, 1ull);
+            if (h < (unsigned long long)C.cap) {
                 const long long t0 = (long long)wall_clock64();
                 for (;;) {
                     const unsigned long long v =
@@ -1542,8 +1546,12 @@ __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
                         task = (long long)(v - 1ull);
                         break;
                     }
+                    // nothing can arrive any more, or the slice is over (a task
+                    // that lands here later is carried over by the host)
                     if (__hip_atomic_load(&C.q->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
-                    if ((long long)wall_clock64() - t0 > C.wait_ticks ||
+                    const long long now = (long long)wall_clock64();
+                    if (now >= C.slice_end) break;
+                    if (now - t0 > C.wait_ticks ||
                         __hip_atomic_load(&C.q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                         atomicExch(&C.q->abort, 1);
                         break;
@@ -1552,9 +1560,11 @@ __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
                 }
             }
             tk = task;
+            hslot = (long long)h;
         }
         __syncthreads();
         const long long task = tk;
+        const long long my_slot = hslot;
         __syncthreads();
         if (task < 0) break;
         __threadfence();
@@ -1626,23 +1636,20 @@ __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
         }
         if (tid == 0) {
             if (next >= 0) {
-                // queue the next iteration while the slice lasts, else leave it to the next slice
-                bool queued = false;
-                if ((long long)wall_clock64() < C.slice_end) {
-                    const unsigned long long t = atomicAdd(&C.q->tail, (unsigned long long)A.B);
-                    if ((long long)(t + A.B) <= C.cap) {
-                        R->next_iter = -2;
-                        __hip_atomic_fetch_add(&C.q->pending, (long long)A.B, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                        for (int s = 0; s < A.B; ++s)
-                            __hip_atomic_store(&C.tasks[t + s], serve_task(slot, 1, s, next) + 1ull, __ATOMIC_RELEASE,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                        queued = true;
-                    }
+                // queue the next iteration (the host seeds it if the queue is full)
+                const unsigned long long t = atomicAdd(&C.q->tail, (unsigned long long)A.B);
+                if ((long long)(t + A.B) <= C.cap) {
+                    R->next_iter = -2;
+                    __hip_atomic_fetch_add(&C.q->pending, (long long)A.B, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    for (int s = 0; s < A.B; ++s)
+                        __hip_atomic_store(&C.tasks[t + s], serve_task(slot, 1, s, next) + 1ull, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    R->next_iter = next;
                 }
-                if (!queued) R->next_iter = next;
             }
             __threadfence();
+            __hip_atomic_store(&C.tasks[my_slot], kServeTaskDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&C.q->pending, -1ll, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();

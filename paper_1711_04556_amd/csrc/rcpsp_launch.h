@@ -54,7 +54,7 @@ hipError_t launch_fill_zero(int *p, long long n, hipStream_t st);
 
 // Serving: per-request control block in device memory (64 bytes).
 struct ServeReq {
-    int next_iter;       // iteration the next slice starts; -1 set-up, -2 queued on the device
+    int next_iter;       // iteration the host must queue (task queue was full); -1 set-up or none, -2 queued on the device
     int done;            // searches done in the current iteration
     int finished;        // 1 once the request's search has ended
     int replay_iters;    // search steps run per search (iterations of an equal plain run)
@@ -82,9 +82,12 @@ struct ServeArgs {
     unsigned long long *tasks;  // [cap] 0 = empty, else task + 1
     ServeQueue *q;
     long long cap;
-    long long slice_end;        // wall-clock ticks: no new iteration is queued after it
+    long long slice_end;        // wall-clock ticks: no task is taken after it
     long long wait_ticks;       // limit of one wait
 };
+
+// Marks a task slot whose task has run.
+constexpr unsigned long long kServeTaskDone = ~0ull;
 
 // task: slot (20 bits) | kind (1: search step, 0: set-up) | search (16 bits) | iteration (27 bits)
 __host__ __device__ inline unsigned long long serve_task(int slot, int kind, int b, int it) {

@@ -1,6 +1,6 @@
 // Serving runtime behind include/rcpsp.h: a device arena for search state,
-// a request queue with admission by footprint, and a host thread that runs
-// the device in time slices (k_serve).
+// request queues per launch class with admission by footprint, and a host
+// thread that runs the device in time slices (k_serve).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +34,8 @@ namespace {
 constexpr size_t kArenaAlign = 256;
 constexpr long long kServeWaitTicks = 20ll * 100 * 1000 * 1000;  // 20 s at 100 MHz
 constexpr long long kServeTaskCap = 1ll << 20;                    // tasks per class and slice
+constexpr size_t kServeMaxClasses = 32;
+constexpr long long kServeCarryCopy = 1ll << 16;                   // task slots read back with every slice
 
 // First-fit allocator over one device allocation.
 class Arena : public DeviceAllocator {
@@ -119,10 +121,14 @@ struct Req {
     int state = RCPSP_REQ_QUEUED, error = 0, slot = -1, cls = -1;
     rcpsp_search *plan = nullptr;
     int64_t submit_ns = 0, admit_ns = 0, done_ns = 0, seen_ns = 0;
+    long long key = 0;    // launch class (decoder, profile width, threads, lanes) from the footprint probe
     int best = 0, iters = 0, next_iter = -1;
     int64_t evals = 0;
     bool cancel = false, cancel_sent = false, fresh = false;
+    bool seed = false;    // the host must queue iteration next_iter (the device queue was full)
 };
+
+struct Req;
 
 struct SClass {
     int dec = 0, nw = 0, T = 0, G = 1;
@@ -131,6 +137,17 @@ struct SClass {
     unsigned long long *h_tasks = nullptr;   // pinned staging
     size_t h_cap = 0;
     hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;                 // end of the running slice
+    bool running = false;
+    int64_t t_launch = 0;
+    std::vector<Req *> inflight;             // requests of the running slice
+    std::vector<unsigned long long> carry;   // tasks queued but not run in the last slice
+    ServeReq *h_back = nullptr;              // pinned: control blocks read back after the slice
+    ServeQueue *h_q = nullptr;               // pinned: queue header read back after the slice
+    int *h_cancel = nullptr;                 // pinned: cancel flags to upload (per slot)
+    size_t queued = 0;                       // tasks the running slice started with
+    unsigned long long *h_back_tasks = nullptr;  // pinned: the task queue read back after the slice
+    size_t h_back_cap = 0;
 };
 
 }  // namespace
@@ -143,7 +160,9 @@ struct rcpsp_server {
     bool stop = false, failed = false;
     rcpsp_status fail_st = RCPSP_OK;
     std::string fail_msg;
-    std::deque<Req *> queue;
+    std::map<long long, std::deque<Req *>> queues;   // per launch class, arrival order
+    std::map<long long, int> resident_of;            // resident requests per launch class
+    size_t queued = 0;
     std::deque<int64_t> finished;   // tickets not yet taken by the caller
     std::unordered_map<int64_t, Req *> reqs;
     int64_t next_ticket = 1;
@@ -153,15 +172,15 @@ struct rcpsp_server {
     Arena arena;
     SearchArgs *d_items = nullptr, *h_items = nullptr;
     ServeReq *d_req = nullptr, *h_req = nullptr;
-    int *h_one = nullptr;
-    std::vector<SClass> classes;
+    std::vector<SClass> classes;   // reserved up front: references stay valid
     uint32_t *d_decay = nullptr;
     int decay_len = 0;
     int device = 0, cus = 256;
     hipStream_t st = nullptr;
     long long *d_clock = nullptr;
-    long long dev0 = 0;
-    int64_t host0 = 0;
+    long long dev0 = 0, dev_first = 0;   // device wall clock at host0 / host_first
+    int64_t host0 = 0, host_first = 0;
+    int64_t next_sync_ns = 0;
     double ticks_per_ns = 0.1;
     rcpsp_server_stats stats{};
 };
@@ -174,6 +193,34 @@ long long dev_ticks_at(const rcpsp_server *s, int64_t host_ns) {
 
 int64_t host_ns_at(const rcpsp_server *s, long long ticks) {
     return s->host0 + (int64_t)((double)(ticks - s->dev0) / s->ticks_per_ns);
+}
+
+// One reading of the device wall clock against the host clock (the host time
+// is the middle of the launch-to-completion interval).
+rcpsp_status clock_pair(rcpsp_server *s, int64_t *host_ns, long long *ticks) {
+    const int64_t a = rcpsp_server_now_ns();
+    HIP_TRY(launch_clock(s->d_clock, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    const int64_t b = rcpsp_server_now_ns();
+    HIP_TRY(hipMemcpy(ticks, s->d_clock, sizeof(long long), hipMemcpyDeviceToHost));
+    *host_ns = (a + b) / 2;
+    return RCPSP_OK;
+}
+
+// Refresh the host <-> device clock mapping: the rate from the first reading
+// to the newest (measured, not taken from the driver's attribute), the
+// offset from the newest.
+rcpsp_status sync_clocks(rcpsp_server *s) {
+    int64_t h;
+    long long d;
+    rcpsp_status st = clock_pair(s, &h, &d);
+    if (st != RCPSP_OK) return st;
+    if (h - s->host_first > 5 * 1000 * 1000 && d > s->dev_first)
+        s->ticks_per_ns = (double)(d - s->dev_first) / (double)(h - s->host_first);
+    s->host0 = h;
+    s->dev0 = d;
+    s->next_sync_ns = h + 50 * 1000 * 1000;
+    return RCPSP_OK;
 }
 
 void set_failed(rcpsp_server *s, rcpsp_status st, const char *msg) {
@@ -192,159 +239,227 @@ rcpsp_status class_of(rcpsp_server *s, const rcpsp_search *plan, int *out) {
             *out = (int)k;
             return RCPSP_OK;
         }
-    SClass c;
+    if (s->classes.size() >= kServeMaxClasses) return fail(RCPSP_E_TOO_LARGE, "more than %d launch classes", (int)kServeMaxClasses);
+    s->classes.emplace_back();
+    SClass &c = s->classes.back();
     c.dec = plan->dec;
     c.nw = nw;
     c.T = plan->T;
     c.G = plan->G;
+    const size_t slots = s->slot_req.size();
     HIP_TRY(hipMalloc(&c.d_tasks, sizeof(unsigned long long) * kServeTaskCap));
     HIP_TRY(hipMalloc(&c.d_q, sizeof(ServeQueue)));
     HIP_TRY(hipStreamCreateWithFlags(&c.st, hipStreamNonBlocking));
-    s->classes.push_back(c);
+    HIP_TRY(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+    HIP_TRY(hipHostMalloc(&c.h_back, sizeof(ServeReq) * slots, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&c.h_q, sizeof(ServeQueue), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&c.h_cancel, sizeof(int) * slots, hipHostMallocDefault));
     *out = (int)s->classes.size() - 1;
     return RCPSP_OK;
 }
 
-// Admit queued requests in order while a slot and arena room are free.
+// Admit queued requests while slots and arena room are free.  Each launch
+// class has its own queue (arrival order) and at most an equal share of the
+// slots among the classes with work, so long requests of one class do not
+// block the others; classes are visited round-robin.
 void admit(rcpsp_server *s, std::vector<Req *> &fresh) {
     std::unique_lock<std::mutex> g(s->mu);
-    while (!s->queue.empty() && !s->free_slots.empty()) {
-        Req *r = s->queue.front();
-        if (r->cancel) {
-            s->queue.pop_front();
-            r->state = RCPSP_REQ_FAILED;
-            r->error = RCPSP_E_ARG;
-            s->finished.push_back(r->ticket);
-            continue;
+    int classes_with_work = 0;
+    for (auto &kv : s->queues)
+        if (!kv.second.empty() || s->resident_of[kv.first] > 0) ++classes_with_work;
+    const int cap = std::max(1, s->prm.max_active / std::max(classes_with_work, 1));
+    std::map<long long, bool> blocked;
+    for (bool progress = true; progress && !s->free_slots.empty();) {
+        progress = false;
+        for (auto &kv : s->queues) {
+            std::deque<Req *> &qu = kv.second;
+            if (qu.empty() || blocked[kv.first] || s->free_slots.empty()) continue;
+            if (s->resident_of[kv.first] >= cap) continue;
+            Req *r = qu.front();
+            if (r->cancel) {
+                qu.pop_front();
+                --s->queued;
+                r->state = RCPSP_REQ_FAILED;
+                r->error = RCPSP_E_ARG;
+                s->finished.push_back(r->ticket);
+                progress = true;
+                continue;
+            }
+            rcpsp_search *plan = new (std::nothrow) rcpsp_search();
+            if (!plan) return;
+            plan->inst = r->inst;
+            plan->p = r->p;
+            plan->reserve = kBatchStaticLds;
+            plan->allocator = &s->arena;
+            plan->shared_decay = s->d_decay;
+            plan->shared_decay_len = s->decay_len;
+            rcpsp_status st = alloc_plan(plan);
+            if (st == RCPSP_E_NOMEM) {
+                rcpsp_search_destroy(plan);
+                blocked[kv.first] = true;  // the arena frees up as requests are released
+                continue;
+            }
+            qu.pop_front();
+            --s->queued;
+            progress = true;
+            int cls = -1;
+            if (st == RCPSP_OK) st = class_of(s, plan, &cls);
+            if (st != RCPSP_OK) {
+                rcpsp_search_destroy(plan);
+                r->state = RCPSP_REQ_FAILED;
+                r->error = st;
+                s->finished.push_back(r->ticket);
+                continue;
+            }
+            const int slot = s->free_slots.back();
+            s->free_slots.pop_back();
+            s->slot_req[slot] = r;
+            ++s->resident_of[kv.first];
+            r->plan = plan;
+            r->slot = slot;
+            r->cls = cls;
+            r->admit_ns = rcpsp_server_now_ns();
+            r->state = RCPSP_REQ_RUNNING;
+            r->fresh = true;
+            r->next_iter = -1;
+            s->h_items[slot] = plan->a;
+            ServeReq q{};
+            q.next_iter = -1;
+            q.max_iters = plan->p.iterations;
+            q.deadline = r->budget_us > 0 ? dev_ticks_at(s, r->admit_ns + r->budget_us * 1000) : LLONG_MAX;
+            s->h_req[slot] = q;
+            ++s->running;
+            ++s->stats.admitted;
+            fresh.push_back(r);
         }
-        rcpsp_search *plan = new (std::nothrow) rcpsp_search();
-        if (!plan) break;
-        plan->inst = r->inst;
-        plan->p = r->p;
-        plan->p.count_work = r->p.count_work;
-        plan->reserve = kBatchStaticLds;
-        plan->allocator = &s->arena;
-        plan->shared_decay = s->d_decay;
-        plan->shared_decay_len = s->decay_len;
-        rcpsp_status st = alloc_plan(plan);
-        if (st == RCPSP_E_NOMEM) {
-            rcpsp_search_destroy(plan);
-            break;  // the arena frees up as requests are released
-        }
-        s->queue.pop_front();
-        int cls = -1;
-        if (st == RCPSP_OK) st = class_of(s, plan, &cls);
-        if (st != RCPSP_OK) {
-            rcpsp_search_destroy(plan);
-            r->state = RCPSP_REQ_FAILED;
-            r->error = st;
-            s->finished.push_back(r->ticket);
-            continue;
-        }
-        const int slot = s->free_slots.back();
-        s->free_slots.pop_back();
-        s->slot_req[slot] = r;
-        r->plan = plan;
-        r->slot = slot;
-        r->cls = cls;
-        r->admit_ns = rcpsp_server_now_ns();
-        r->state = RCPSP_REQ_RUNNING;
-        r->fresh = true;
-        r->next_iter = -1;
-        s->h_items[slot] = plan->a;
-        ServeReq q{};
-        q.next_iter = -1;
-        q.max_iters = plan->p.iterations;
-        q.deadline = r->budget_us > 0 ? dev_ticks_at(s, r->admit_ns + r->budget_us * 1000) : LLONG_MAX;
-        s->h_req[slot] = q;
-        ++s->running;
-        ++s->stats.admitted;
-        fresh.push_back(r);
     }
 }
 
-// One slice: set-up and iteration tasks per class, launches, read-back.
-rcpsp_status run_slice(rcpsp_server *s, const std::vector<Req *> &fresh) {
-    // new requests' arguments and control blocks
-    for (Req *r : fresh) {
-        HIP_TRY(hipMemcpyAsync(s->d_items + r->slot, s->h_items + r->slot, sizeof(SearchArgs),
-                               hipMemcpyHostToDevice, s->st));
-        HIP_TRY(hipMemcpyAsync(s->d_req + r->slot, s->h_req + r->slot, sizeof(ServeReq), hipMemcpyHostToDevice,
-                               s->st));
-    }
-    std::vector<Req *> active;
+// Classes run independently: each has its own stream, task queue and slice
+// loop, so a class of long iterations never holds back the slices (and so
+// the admissions and completions) of the others.
+
+// Start a slice of class c: new requests' arguments and control blocks, the
+// set-up or next-iteration tasks of its running requests, the launch.
+rcpsp_status launch_class(rcpsp_server *s, int c) {
+    SClass &C = s->classes[c];
+    std::vector<Req *> act;
+    std::vector<char> busy(s->classes.size(), 0);
     {
         std::lock_guard<std::mutex> g(s->mu);
-        for (Req *r : s->slot_req)
-            if (r && r->state == RCPSP_REQ_RUNNING) {
-                active.push_back(r);
-                if (r->cancel && !r->cancel_sent) {
-                    r->cancel_sent = true;
-                    *s->h_one = 1;
-                    HIP_TRY(hipMemcpyAsync(&s->d_req[r->slot].cancel, s->h_one, sizeof(int), hipMemcpyHostToDevice,
-                                           s->st));
-                }
+        for (Req *r : s->slot_req) {
+            if (!r || r->state != RCPSP_REQ_RUNNING) continue;
+            busy[r->cls] = 1;
+            if (r->cls == c) act.push_back(r);
+        }
+        if (act.empty()) return RCPSP_OK;
+        for (Req *r : act)
+            if (r->cancel && !r->cancel_sent && !r->fresh) {
+                r->cancel_sent = true;
+                C.h_cancel[r->slot] = 1;
+                HIP_TRY(hipMemcpyAsync(&s->d_req[r->slot].cancel, C.h_cancel + r->slot, sizeof(int),
+                                       hipMemcpyHostToDevice, C.st));
             }
     }
-    HIP_TRY(hipStreamSynchronize(s->st));
-    const int nc = (int)s->classes.size();
-    std::vector<std::vector<unsigned long long>> tasks(nc);
-    std::vector<size_t> lds(nc, 0);
-    for (Req *r : active) {
-        std::vector<unsigned long long> &t = tasks[r->cls];
-        if (r->fresh) t.push_back(serve_task(r->slot, 0, 0, 0));
-        else
-            for (int b = 0; b < r->p.searches; ++b) t.push_back(serve_task(r->slot, 1, b, r->next_iter));
-        lds[r->cls] = std::max(lds[r->cls], r->plan->lds);
-        r->fresh = false;
-    }
-    const long long slice_end = dev_ticks_at(s, rcpsp_server_now_ns() + (int64_t)s->prm.slice_us * 1000);
-    const int64_t t0 = rcpsp_server_now_ns();
-    int launched = 0;
-    for (int c = 0; c < nc; ++c) {
-        SClass &C = s->classes[c];
-        const size_t n0 = tasks[c].size();
-        if (n0 == 0) continue;
-        if (n0 > (size_t)kServeTaskCap) return fail(RCPSP_E_TOO_LARGE, "slice needs %zu tasks", n0);
-        if (C.h_cap < n0) {
-            if (C.h_tasks) (void)hipHostFree(C.h_tasks);
-            C.h_tasks = nullptr;
-            C.h_cap = std::max<size_t>(n0, 4096);
-            HIP_TRY(hipHostMalloc(&C.h_tasks, sizeof(unsigned long long) * C.h_cap, hipHostMallocDefault));
+    // queued tasks of the last slice first, then seeds and new requests' set-up
+    std::vector<unsigned long long> tasks;
+    tasks.swap(C.carry);
+    size_t lds = 0;
+    for (Req *r : act) {
+        if (r->fresh) {
+            HIP_TRY(hipMemcpyAsync(s->d_items + r->slot, s->h_items + r->slot, sizeof(SearchArgs),
+                                   hipMemcpyHostToDevice, C.st));
+            HIP_TRY(hipMemcpyAsync(s->d_req + r->slot, s->h_req + r->slot, sizeof(ServeReq), hipMemcpyHostToDevice,
+                                   C.st));
+            tasks.push_back(serve_task(r->slot, 0, 0, 0));
+            r->fresh = false;
+        } else if (r->seed) {
+            for (int b = 0; b < r->p.searches; ++b) tasks.push_back(serve_task(r->slot, 1, b, r->next_iter));
+            r->seed = false;
         }
-        for (size_t i = 0; i < n0; ++i) C.h_tasks[i] = tasks[c][i] + 1ull;
-        HIP_TRY(hipMemcpyAsync(C.d_tasks, C.h_tasks, sizeof(unsigned long long) * n0, hipMemcpyHostToDevice, C.st));
-        HIP_TRY(launch_serve_begin(C.d_q, C.d_tasks, kServeTaskCap, (long long)n0, C.st));
-        int per_cu = 0;
-        HIP_TRY(serve_occupancy(C.T, C.nw, C.dec, C.G, lds[c], &per_cu));
-        if (per_cu < 1) return fail(RCPSP_E_TOO_LARGE, "serving workgroup of %zu B LDS does not fit a CU", lds[c]);
-        ServeArgs A{};
-        A.items = s->d_items;
-        A.req = s->d_req;
-        A.tasks = C.d_tasks;
-        A.q = C.d_q;
-        A.cap = kServeTaskCap;
-        A.slice_end = slice_end;
-        A.wait_ticks = kServeWaitTicks;
-        HIP_TRY(launch_serve(A, per_cu * s->cus, C.T, C.nw, C.dec, C.G, lds[c], C.st));
-        ++launched;
+        lds = std::max(lds, r->plan->lds);
     }
-    for (int c = 0; c < nc; ++c) HIP_TRY(hipStreamSynchronize(s->classes[c].st));
+    const size_t n0 = tasks.size();
+    if (n0 == 0) return fail(RCPSP_E_DEVICE, "serving class %d has running requests but no queued task", c);
+    if (n0 > (size_t)kServeTaskCap) return fail(RCPSP_E_TOO_LARGE, "slice needs %zu tasks", n0);
+    if (C.h_cap < n0) {
+        if (C.h_tasks) (void)hipHostFree(C.h_tasks);
+        C.h_tasks = nullptr;
+        C.h_cap = std::max<size_t>(n0, 4096);
+        HIP_TRY(hipHostMalloc(&C.h_tasks, sizeof(unsigned long long) * C.h_cap, hipHostMallocDefault));
+    }
+    for (size_t i = 0; i < n0; ++i) C.h_tasks[i] = tasks[i] + 1ull;
+    HIP_TRY(hipMemcpyAsync(C.d_tasks, C.h_tasks, sizeof(unsigned long long) * n0, hipMemcpyHostToDevice, C.st));
+    HIP_TRY(launch_serve_begin(C.d_q, C.d_tasks, kServeTaskCap, (long long)n0, C.st));
+    int per_cu = 0;
+    HIP_TRY(serve_occupancy(C.T, C.nw, C.dec, C.G, lds, &per_cu));
+    if (per_cu < 1) return fail(RCPSP_E_TOO_LARGE, "serving workgroup of %zu B LDS does not fit a CU", lds);
+    // the classes with running requests share the CUs equally, so that a
+    // class of long tasks cannot hold every CU
+    int nbusy = 0;
+    for (char b : busy) nbusy += b;
+    const int full = per_cu * s->cus;
+    const int share = (full + std::max(nbusy, 1) - 1) / std::max(nbusy, 1);
+    const int grid = std::max(std::min(full, 8), std::min(share, full));
+    ServeArgs A{};
+    A.items = s->d_items;
+    A.req = s->d_req;
+    A.tasks = C.d_tasks;
+    A.q = C.d_q;
+    A.cap = kServeTaskCap;
+    A.slice_end = dev_ticks_at(s, rcpsp_server_now_ns() + (int64_t)s->prm.slice_us * 1000);
+    A.wait_ticks = kServeWaitTicks;
+    C.t_launch = rcpsp_server_now_ns();
+    HIP_TRY(launch_serve(A, grid, C.T, C.nw, C.dec, C.G, lds, C.st));
+    HIP_TRY(hipMemcpyAsync(C.h_back, s->d_req, sizeof(ServeReq) * s->slot_req.size(), hipMemcpyDeviceToHost, C.st));
+    HIP_TRY(hipMemcpyAsync(C.h_q, C.d_q, sizeof(ServeQueue), hipMemcpyDeviceToHost, C.st));
+    // the queue as the slice leaves it (its first kServeCarryCopy slots; the
+    // rest, if any, is read synchronously afterwards)
+    if (C.h_back_cap < (size_t)kServeCarryCopy) {
+        if (C.h_back_tasks) (void)hipHostFree(C.h_back_tasks);
+        C.h_back_tasks = nullptr;
+        C.h_back_cap = (size_t)kServeCarryCopy;
+        HIP_TRY(hipHostMalloc(&C.h_back_tasks, sizeof(unsigned long long) * C.h_back_cap, hipHostMallocDefault));
+    }
+    HIP_TRY(hipMemcpyAsync(C.h_back_tasks, C.d_tasks, sizeof(unsigned long long) * kServeCarryCopy,
+                           hipMemcpyDeviceToHost, C.st));
+    HIP_TRY(hipEventRecord(C.ev, C.st));
+    C.queued = n0;
+    C.inflight = act;
+    C.running = true;
+    return RCPSP_OK;
+}
+
+// End of a slice of class c (its event has completed): results and next
+// iterations of the requests it ran.
+rcpsp_status finish_class(rcpsp_server *s, int c) {
+    SClass &C = s->classes[c];
+    C.running = false;
     const int64_t t1 = rcpsp_server_now_ns();
-    // read back the control blocks and the queues' abort flags
-    HIP_TRY(hipMemcpy(s->h_req, s->d_req, sizeof(ServeReq) * s->slot_req.size(), hipMemcpyDeviceToHost));
-    for (int c = 0; c < nc; ++c) {
-        ServeQueue q{};
-        HIP_TRY(hipMemcpy(&q, s->classes[c].d_q, sizeof(ServeQueue), hipMemcpyDeviceToHost));
-        if (q.abort) return fail(RCPSP_E_DEVICE, "serving class %d: a wait inside the kernel exceeded its limit", c);
+    if (C.h_q->abort) return fail(RCPSP_E_DEVICE, "serving class %d: a wait inside the kernel exceeded its limit", c);
+    // tasks queued in the slice that did not run
+    const size_t nt = (size_t)std::min<unsigned long long>(C.h_q->tail, (unsigned long long)kServeTaskCap);
+    if (nt > (size_t)kServeCarryCopy) {
+        if (C.h_back_cap < nt) {
+            if (C.h_back_tasks) (void)hipHostFree(C.h_back_tasks);
+            C.h_back_tasks = nullptr;
+            C.h_back_cap = nt;
+            HIP_TRY(hipHostMalloc(&C.h_back_tasks, sizeof(unsigned long long) * C.h_back_cap, hipHostMallocDefault));
+        }
+        HIP_TRY(hipMemcpyAsync(C.h_back_tasks, C.d_tasks, sizeof(unsigned long long) * nt, hipMemcpyDeviceToHost,
+                               C.st));
+        HIP_TRY(hipStreamSynchronize(C.st));
+    }
+    C.carry.clear();
+    for (size_t i = 0; i < nt; ++i) {
+        const unsigned long long v = C.h_back_tasks[i];
+        if (v != 0ull && v != kServeTaskDone) C.carry.push_back(v - 1ull);
     }
     std::lock_guard<std::mutex> g(s->mu);
-    if (launched) {
-        ++s->stats.slices;
-        s->stats.busy_ms += (double)(t1 - t0) * 1e-6;
-    }
-    for (Req *r : active) {
-        const ServeReq &q = s->h_req[r->slot];
+    ++s->stats.slices;
+    s->stats.busy_ms += (double)(t1 - C.t_launch) * 1e-6;
+    for (Req *r : C.inflight) {
+        const ServeReq &q = C.h_back[r->slot];
         if (q.finished) {
             r->state = RCPSP_REQ_DONE;
             r->best = q.best;
@@ -358,10 +473,10 @@ rcpsp_status run_slice(rcpsp_server *s, const std::vector<Req *> &fresh) {
             s->finished.push_back(r->ticket);
         } else if (q.next_iter >= 0) {
             r->next_iter = q.next_iter;
-        } else {
-            return fail(RCPSP_E_DEVICE, "request %lld left a slice without a next iteration", (long long)r->ticket);
+            r->seed = true;
         }
     }
+    C.inflight.clear();
     s->cv_idle.notify_all();
     return RCPSP_OK;
 }
@@ -372,32 +487,44 @@ void loop(rcpsp_server *s) {
         set_failed(s, RCPSP_E_DEVICE, "hipSetDevice failed in the server thread");
         return;
     }
+    rcpsp_status st = RCPSP_OK;
     for (;;) {
         {
             std::unique_lock<std::mutex> g(s->mu);
-            s->cv_work.wait(g, [&] { return s->stop || !s->queue.empty() || s->running > 0; });
-            if (s->stop) return;
+            bool any_slice = false;
+            for (const SClass &C : s->classes) any_slice = any_slice || C.running;
+            if (!any_slice)
+                s->cv_work.wait_for(g, std::chrono::milliseconds(1),
+                                    [&] { return s->stop || s->queued > 0 || s->running > 0; });
+            if (s->stop) break;
         }
+        // slices that ended
+        for (int c = 0; st == RCPSP_OK && c < (int)s->classes.size(); ++c) {
+            if (!s->classes[c].running) continue;
+            const hipError_t q = hipEventQuery(s->classes[c].ev);
+            if (q == hipSuccess) st = finish_class(s, c);
+            else if (q != hipErrorNotReady) st = fail(RCPSP_E_DEVICE, "serving slice: %s", hipGetErrorString(q));
+        }
+        if (st != RCPSP_OK) break;
+        // the clock reading waits on the server's own stream, which may share
+        // a hardware queue with a running slice: only refresh while idle
+        bool idle_now = true;
+        for (const SClass &C : s->classes) idle_now = idle_now && !C.running;
+        if (idle_now && rcpsp_server_now_ns() >= s->next_sync_ns && (st = sync_clocks(s)) != RCPSP_OK) break;
         std::vector<Req *> fresh;
         admit(s, fresh);
-        bool any;
-        {
-            std::lock_guard<std::mutex> g(s->mu);
-            any = s->running > 0;
+        // idle classes with running requests start their next slice
+        bool any_slice = false;
+        for (int c = 0; st == RCPSP_OK && c < (int)s->classes.size(); ++c) {
+            if (!s->classes[c].running) st = launch_class(s, c);
+            any_slice = any_slice || s->classes[c].running;
         }
-        if (!any) {
-            // queue blocked by arena room or slots held by unreleased requests
-            std::unique_lock<std::mutex> g(s->mu);
-            s->cv_idle.notify_all();
-            s->cv_work.wait_for(g, std::chrono::milliseconds(1));
-            continue;
-        }
-        rcpsp_status st = run_slice(s, fresh);
-        if (st != RCPSP_OK) {
-            set_failed(s, st, rcpsp_last_error());
-            return;
-        }
+        if (st != RCPSP_OK) break;
+        if (any_slice) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
+    if (st != RCPSP_OK) set_failed(s, st, rcpsp_last_error());
+    for (SClass &C : s->classes)
+        if (C.running) (void)hipStreamSynchronize(C.st);
 }
 
 }  // namespace
@@ -428,17 +555,12 @@ extern "C" rcpsp_status rcpsp_server_create(const rcpsp_server_params *params, r
     } while (0)
     SRV_TRY(hipGetDevice(&s->device));
     SRV_TRY(hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device));
-    int khz = 0;
-    SRV_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
-    if (khz <= 0) return bail(fail(RCPSP_E_DEVICE, "device wall clock rate unknown"));
-    s->ticks_per_ns = (double)khz * 1e-6;
     SRV_TRY(s->arena.init((size_t)s->prm.arena_bytes));
     const size_t slots = (size_t)s->prm.max_active;
     SRV_TRY(hipMalloc(&s->d_items, sizeof(SearchArgs) * slots));
     SRV_TRY(hipMalloc(&s->d_req, sizeof(ServeReq) * slots));
     SRV_TRY(hipHostMalloc(&s->h_items, sizeof(SearchArgs) * slots, hipHostMallocDefault));
     SRV_TRY(hipHostMalloc(&s->h_req, sizeof(ServeReq) * slots, hipHostMallocDefault));
-    SRV_TRY(hipHostMalloc(&s->h_one, sizeof(int), hipHostMallocDefault));
     std::memset(s->h_req, 0, sizeof(ServeReq) * slots);
     SRV_TRY(hipMemcpy(s->d_req, s->h_req, sizeof(ServeReq) * slots, hipMemcpyHostToDevice));
     SRV_TRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
@@ -448,18 +570,20 @@ extern "C" rcpsp_status rcpsp_server_create(const rcpsp_server_params *params, r
         SRV_TRY(hipMemcpy(s->d_decay, E.data(), sizeof(uint32_t) * E.size(), hipMemcpyHostToDevice));
         s->decay_len = (int)E.size();
     }
-    // host <-> device wall-clock mapping
+    // host <-> device wall-clock mapping: two readings 20 ms apart give the
+    // first rate; the server thread refines it every 50 ms
     SRV_TRY(hipMalloc(&s->d_clock, sizeof(long long)));
     {
-        const int64_t a = rcpsp_server_now_ns();
-        SRV_TRY(launch_clock(s->d_clock, s->st));
-        SRV_TRY(hipStreamSynchronize(s->st));
-        const int64_t b = rcpsp_server_now_ns();
-        SRV_TRY(hipMemcpy(&s->dev0, s->d_clock, sizeof(long long), hipMemcpyDeviceToHost));
-        s->host0 = (a + b) / 2;
+        rcpsp_status st = clock_pair(s, &s->host_first, &s->dev_first);
+        if (st != RCPSP_OK) return bail(st);
+        std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        st = sync_clocks(s);
+        if (st != RCPSP_OK) return bail(st);
+        if (!(s->ticks_per_ns > 0.0)) return bail(fail(RCPSP_E_DEVICE, "device wall clock does not advance"));
     }
 #undef SRV_TRY
     s->slot_req.assign(slots, nullptr);
+    s->classes.reserve(kServeMaxClasses);
     for (int i = (int)slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->stats.arena_bytes = (int64_t)s->arena.size();
     s->th = std::thread(loop, s);
@@ -485,13 +609,17 @@ extern "C" void rcpsp_server_destroy(rcpsp_server *s) {
         if (c.d_tasks) (void)hipFree(c.d_tasks);
         if (c.d_q) (void)hipFree(c.d_q);
         if (c.h_tasks) (void)hipHostFree(c.h_tasks);
+        if (c.ev) (void)hipEventDestroy(c.ev);
+        if (c.h_back) (void)hipHostFree(c.h_back);
+        if (c.h_q) (void)hipHostFree(c.h_q);
+        if (c.h_cancel) (void)hipHostFree(c.h_cancel);
+        if (c.h_back_tasks) (void)hipHostFree(c.h_back_tasks);
     }
     if (s->st) (void)hipStreamDestroy(s->st);
     if (s->d_items) (void)hipFree(s->d_items);
     if (s->d_req) (void)hipFree(s->d_req);
     if (s->h_items) (void)hipHostFree(s->h_items);
     if (s->h_req) (void)hipHostFree(s->h_req);
-    if (s->h_one) (void)hipHostFree(s->h_one);
     if (s->d_decay) (void)hipFree(s->d_decay);
     if (s->d_clock) (void)hipFree(s->d_clock);
     delete s;
@@ -520,12 +648,15 @@ extern "C" rcpsp_status rcpsp_server_submit(rcpsp_server *s, const rcpsp_instanc
         return fail(RCPSP_E_TOO_LARGE, "exchange bookkeeping does not fit the workgroup's LDS");
     if (m.total > s->arena.size())
         return fail(RCPSP_E_TOO_LARGE, "request state of %zu B exceeds the arena (%zu B)", m.total, s->arena.size());
+    const long long key = (long long)probe.dec | ((long long)(probe.dec == kEvalTime ? probe.nw : 1) << 4) |
+                          ((long long)probe.T << 8) | ((long long)probe.G << 20);
     Req *r = new (std::nothrow) Req();
     if (!r) return fail(RCPSP_E_NOMEM, "out of host memory");
     r->inst = inst;
     r->p = *params;
     r->budget_us = budget_us;
     r->bytes = m.total;
+    r->key = key;
     r->submit_ns = rcpsp_server_now_ns();
     {
         std::lock_guard<std::mutex> g(s->mu);
@@ -535,7 +666,8 @@ extern "C" rcpsp_status rcpsp_server_submit(rcpsp_server *s, const rcpsp_instanc
         }
         r->ticket = s->next_ticket++;
         s->reqs[r->ticket] = r;
-        s->queue.push_back(r);
+        s->queues[r->key].push_back(r);
+        ++s->queued;
         ++s->stats.submitted;
         *ticket = r->ticket;
     }
@@ -606,6 +738,7 @@ extern "C" rcpsp_status rcpsp_server_release(rcpsp_server *s, int64_t ticket) {
         if (r->slot >= 0) {
             s->slot_req[r->slot] = nullptr;
             s->free_slots.push_back(r->slot);
+            --s->resident_of[r->key];
         }
     }
     if (r->plan) rcpsp_search_destroy(r->plan);
@@ -617,7 +750,7 @@ extern "C" rcpsp_status rcpsp_server_release(rcpsp_server *s, int64_t ticket) {
 extern "C" rcpsp_status rcpsp_server_drain(rcpsp_server *s, int64_t timeout_ms) {
     if (!s) return fail(RCPSP_E_ARG, "null pointer");
     std::unique_lock<std::mutex> g(s->mu);
-    auto idle = [&] { return s->failed || (s->queue.empty() && s->running == 0); };
+    auto idle = [&] { return s->failed || (s->queued == 0 && s->running == 0); };
     if (timeout_ms > 0) {
         if (!s->cv_idle.wait_for(g, std::chrono::milliseconds(timeout_ms), idle))
             return fail(RCPSP_E_ARG, "drain timed out");
@@ -645,8 +778,9 @@ extern "C" rcpsp_status rcpsp_server_get_stats(rcpsp_server *s, rcpsp_server_sta
     std::lock_guard<std::mutex> g(s->mu);
     *out = s->stats;
     out->resident = (int32_t)(s->slot_req.size() - s->free_slots.size());
-    out->queued = (int32_t)s->queue.size();
+    out->queued = (int32_t)s->queued;
     out->arena_used = (int64_t)s->arena.used();
     out->arena_bytes = (int64_t)s->arena.size();
+    out->device_clock_mhz = s->ticks_per_ns * 1000.0;
     return RCPSP_OK;
 }

@@ -88,7 +88,7 @@ class rcpsp_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("slices", ctypes.c_int64), ("busy_ms", ctypes.c_double), ("evaluations", ctypes.c_int64),
                 ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("arena_used", ctypes.c_int64),
-                ("arena_bytes", ctypes.c_int64)]
+                ("arena_bytes", ctypes.c_int64), ("device_clock_mhz", ctypes.c_double)]
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
