@@ -231,14 +231,20 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
     pool = synth.serving_pool(SERVE["pool"])
     gis = {n: [rcpsp.Instance(i) for i in lst] for n, lst in pool.items()}
     params = {}
+    tuning = {}
     for n, lst in gis.items():
         d, tl = SERVE_DELTA_TL[n + 2]
-        # decoder: the library's automatic choice per instance; one wave per search
-        params[n] = rcpsp.search_params(d, tl, SERVE["iterations"], searches=SERVE["searches"],
-                                        elite=SERVE["elite"], phi_max=SERVE["phi_max"],
-                                        phi_steps=SERVE["phi_steps"], threads=64, record_trajectory=False,
-                                        seed=SERVE["seed"])
-    log("serving set-up", f"{time.perf_counter() - t0:.1f} s")
+        base = rcpsp.search_params(d, tl, SERVE["iterations"], searches=SERVE["searches"], elite=SERVE["elite"],
+                                   phi_max=SERVE["phi_max"], phi_steps=SERVE["phi_steps"], threads=64,
+                                   record_trajectory=False, seed=SERVE["seed"])
+        # decoder and lanes per size from the batch autotuner on a sample; one
+        # wave per search for every size, so that sizes share launch classes
+        # (classes split the CUs between them)
+        tuned, info = rcpsp.batch_autotune(lst[:8], base, trial_iterations=1, sample=8, stream=stream)
+        params[n] = tuned[0]
+        tuning[str(n)] = dict(eval=info["group_eval"][0], threads=info["group_threads"][0],
+                              lanes=info["group_lanes"][0])
+    log("serving set-up", f"{time.perf_counter() - t0:.1f} s", tuning)
     arrivals = synth.serving_arrivals(rate, warmup_s + measure_s, SERVE["seed"])
     sizes = synth.SERVING_SIZES
     srv = rcpsp.Server(max_active=SERVE["max_active"], slice_us=1000, arena_bytes=8 << 30)
@@ -318,6 +324,7 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
         "admitted_to_end_p99_ms": pct(run_time, 99),
         "evals_per_s": evals / measure_s,
         "per_size": per_size,
+        "tuning": tuning,
         "device_clock_mhz": stats["device_clock_mhz"],
         "slices": stats["slices"],
         "slice_busy_ms_mean": stats["busy_ms"] / max(stats["slices"], 1),
