@@ -136,7 +136,8 @@ typedef struct {
     int32_t elite;            /* |F|: working-set size; 0 = independent searches */
     int32_t phi_max;          /* diversify when a record was read more than phi_max times */
     int32_t phi_steps;        /* random feasible swaps per diversification */
-    int32_t threads;          /* threads per search: 0 = auto, else 64, 128, 256 */
+    int32_t threads;          /* threads per search: 0 = auto, else 64, 128, 256,
+                                 or 192 (time-indexed, one candidate per lane) */
     int32_t profile_len;      /* time-indexed LDS profile slots per lane, 0 = auto
                                  (about 1.4 x critical path, stretched while the
                                  workgroups per CU stay the same, never below
@@ -210,7 +211,8 @@ rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcpsp_search_pa
 typedef struct {
     int32_t threads, profile_len, lds_bytes, eval;
     int32_t iteration_launches, round_launches;
-    int32_t lanes;
+    int32_t lanes;            /* lanes per candidate */
+    int32_t finish_bits;      /* bits per finish time in the lane states (8 or 16) */
 } rcpsp_search_config;
 rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out);
 

@@ -321,8 +321,10 @@ extern "C" void rcpsp_destroy_instance(rcpsp_instance *inst) {
 // ---------------------------------------------------------------------------
 // LDS layout
 
-// G = 1: one candidate per lane, lane-interleaved state; G > 1 (time-indexed
-// only): one candidate per group of G lanes, contiguous state per candidate.
+// G = 1: one candidate per lane, lane-interleaved state; G = 2 (time-indexed):
+// the same with 8-bit finish times (lane profiles of at most 255 units);
+// G = 16 (time-indexed): one candidate per 16 lanes, contiguous state per
+// candidate.
 static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, int L, int dec, int G = 1) {
     Layout Ly{};
     const int N2h = n2(D.n) / 2;
@@ -345,19 +347,24 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     Ly.predT = o; o += std::max(D.n_arcs, 1);
     o = (o + 1) & ~1;
     Ly.red = o; o += 2 * (T / 64);
-    Ly.scal = o; o += 4;
+    Ly.scal = o; o += std::max(4, 1 + 3 * (T / 64));
     // per candidate: finish times, then the time-indexed profile (L units
     // plus 4 of slack for the 4-wide scan) or the capacity arrays and the
     // copy ring
-    if (dec == kEvalTime && G > 1) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
-    else if (dec == kEvalTime) Ly.per_lane = F0 + (L + 4) * D.nw;
+    // G = 2: one candidate per lane with 8-bit finish times
+    const bool group = dec == kEvalTime && G > 2;
+    const int Fl = (dec == kEvalTime && G == 2) ? (D.n + 3) / 4 : F0;
+    if (group) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
+    else if (dec == kEvalTime) Ly.per_lane = Fl + (L + 4) * D.nw;
     else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
-    Ly.cands = G > 1 ? T / G : T;
+    Ly.cands = group ? T / G : T;
     o = (o + 3) & ~3;
-    Ly.bst = o; o += Ly.per_lane;
+    Ly.bst = o;
+    o += group ? Ly.per_lane : (T / 64) * ((Ly.per_lane + 3) & ~3);   // one base state per wave
     o = (o + 3) & ~3;
     Ly.region = o;
     o += Ly.cands * Ly.per_lane;
+    // the long-profile decode (one thread, 16-bit finish times) uses the whole region
     Ly.long_len = dec == kEvalTime ? (Ly.cands * Ly.per_lane - F0) / D.nw - 4 : 0;
     Ly.total = o;
     return Ly;
@@ -384,7 +391,8 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
         *Ly_out = Ly;
         return RCPSP_OK;
     }
-    const int H = std::max(I->H, 1);
+    // 8-bit finish times (G = 2) hold lane profiles of at most 255 units
+    const int H = G == 2 ? std::min(std::max(I->H, 1), 255) : std::max(I->H, 1);
     auto fits = [&](int L, Layout *Ly) {
         *Ly = make_layout(D, T, tcw, tl, pmax, L, dec, G);
         return Ly->long_len >= I->H && (size_t)Ly->total * 4 <= (size_t)budget;
@@ -454,8 +462,8 @@ static rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, i
     int L = 0;
     Layout Ly;
     rcpsp_status s = RCPSP_E_TOO_LARGE;
-    for (int g : {1, 16}) {
-        if (g > 1 && I->eval != kEvalTime) break;
+    for (int g : {2, 1, 16}) {
+        if (g != 1 && I->eval != kEvalTime) continue;
         for (T = 256; T >= 64; T /= 2) {
             s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly, g);
             if (s != RCPSP_E_TOO_LARGE) break;
@@ -674,7 +682,10 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     s->tcw = (p.swap_range + 31) / 32;
     s->P = potential_moves(N, p.swap_range);
     const int T0 = p.threads ? p.threads : (B >= 256 ? 64 : (B >= 64 ? 128 : 256));
-    if (T0 != 64 && T0 != 128 && T0 != 256) return fail(RCPSP_E_ARG, "threads must be 0, 64, 128 or 256");
+    if (T0 != 64 && T0 != 128 && T0 != 192 && T0 != 256)
+        return fail(RCPSP_E_ARG, "threads must be 0, 64, 128, 192 or 256");
+    if (T0 == 192 && (s->dec != kEvalTime || p.lanes == 16))
+        return fail(RCPSP_E_ARG, "192 threads per search needs the time-indexed decoder with one candidate per lane");
     if (p.lanes != 0 && p.lanes != 1 && p.lanes != 16) return fail(RCPSP_E_ARG, "lanes must be 0, 1 or 16");
     if (p.lanes == 16 && s->dec != kEvalTime) return fail(RCPSP_E_ARG, "16 lanes per candidate needs the time-indexed decoder");
     int T = T0;
@@ -688,10 +699,18 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
         }
         s->G = G;
     };
-    // one candidate per lane unless requested otherwise; when its profile
-    // does not fit, one candidate per 16 lanes (time-indexed)
-    try_shape(p.lanes == 16 ? 16 : 1, p.profile_len);
-    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0 && s->dec == kEvalTime) try_shape(16, p.profile_len);
+    // one candidate per lane unless requested otherwise (time-indexed: 8-bit
+    // finish times when the lane profile stays within 255 units, else
+    // 16-bit); when no per-lane profile fits, one candidate per 16 lanes
+    if (p.lanes == 16) {
+        try_shape(16, p.profile_len);
+    } else if (s->dec == kEvalTime) {
+        try_shape(2, p.profile_len);
+        if (st == RCPSP_E_TOO_LARGE) try_shape(1, p.profile_len);
+    } else {
+        try_shape(1, p.profile_len);
+    }
+    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0 && s->dec == kEvalTime && T0 != 192) try_shape(16, p.profile_len);
     if (st == RCPSP_E_TOO_LARGE && p.eval == RCPSP_EVAL_AUTO && s->dec == kEvalTime) {
         // automatic choice: no time-indexed profile fits, take the capacity-indexed decoder
         s->dec = kEvalCapacity;
@@ -862,7 +881,8 @@ extern "C" rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_sea
     out->eval = s->dec;
     out->iteration_launches = s->iteration_launches;
     out->round_launches = s->round_launches;
-    out->lanes = s->G;
+    out->lanes = s->G > 2 ? s->G : 1;
+    out->finish_bits = s->G == 2 ? 8 : 16;
     return RCPSP_OK;
 }
 
@@ -942,6 +962,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
     else {
         threads.push_back(64);
         threads.push_back(128);
+        threads.push_back(192);
         if (params->searches < 128) threads.push_back(256);
     }
     // profile lengths: the automatic choice, and a shorter one that may fit
@@ -958,6 +979,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
       for (int G : lanes_c) {
         if (G > 1 && ev != kEvalTime) continue;
         for (int T : threads) {
+            if (T == 192 && (ev != kEvalTime || G != 1)) continue;
             std::vector<int> Ls;
             if (ev == kEvalTime && !params->profile_len) {
                 Ls.push_back(0);
@@ -1355,7 +1377,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
             evals.push_back(kEvalCapacity);
         }
         if (p0.threads) threads.push_back(p0.threads);
-        else threads = {64, 128, 256};
+        else threads = {64, 128, 192, 256};
         std::vector<int> lanes_c;
         if (p0.lanes) lanes_c.push_back(p0.lanes);
         else lanes_c = {1, 16};
@@ -1366,6 +1388,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
           for (int G : lanes_c) {
             if (G > 1 && ev != kEvalTime) continue;
             for (int T : threads) {
+                if (T == 192 && (ev != kEvalTime || G != 1)) continue;
                 for (auto &q : sp) {
                     q.eval = ev;
                     q.threads = T;

@@ -94,13 +94,37 @@ struct LaneMem {
     __device__ inline void st16b(uint32_t off, int v) const {
         *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(base) + off) = (uint16_t)v;
     }
+    // finish time of FB bits (8 or 16) at a byte offset
+    template <int FB>
+    __device__ inline int ldf(uint32_t off) const {
+        if (FB == 8) return *(reinterpret_cast<const uint8_t *>(base) + off);
+        return ld16b(off);
+    }
+    template <int FB>
+    __device__ inline void stf(uint32_t off, int v) const {
+        if (FB == 8) *(reinterpret_cast<uint8_t *>(base) + off) = (uint8_t)v;
+        else st16b(off, v);
+    }
 };
+
+// Dwords of finish times (FB bits each) at the start of a candidate's state.
+template <int FB>
+__host__ __device__ inline int f_dwords(int n) {
+    return FB == 8 ? (n + 3) >> 2 : (n + 1) >> 1;
+}
 
 // Byte offset of 16-bit element e of a lane's storage when lanes are
 // interleaved with the given dword stride (stride 1: a single thread).
 template <int STRIDE>
 __device__ inline uint32_t off16(int e) {
     return (uint32_t)(((e >> 1) * STRIDE) << 2) + (uint32_t)((e & 1) << 1);
+}
+
+// Byte offset of finish time e (FB bits) in a lane's storage.
+template <int STRIDE, int FB>
+__device__ inline uint32_t offF(int e) {
+    if (FB == 8) return (uint32_t)(((e >> 2) * STRIDE) << 2) + (uint32_t)(e & 3);
+    return off16<STRIDE>(e);
 }
 
 // ---------------------------------------------------------------------------
@@ -176,30 +200,30 @@ __device__ inline unsigned long long block_min_u64(unsigned long long x, unsigne
 //                     first predecessor index, w_p),
 //   prq[p*NW + w]  = packed requests of w_p (time-indexed profile words),
 //   predT[e]       = byte offset of f[pred[e]] in a lane's storage.
-template <int T>
+template <int T, int FB = 16>
 __device__ inline void build_records(const Sh &S, const InstDesc &D) {
     const int N = D.n, NW = D.nw;
     for (int p = threadIdx.x; p < N; p += T) {
         const int a = S.W[p];
         const int po = S.predoff[a];
         uint4 r;
-        r.x = off16<T>(a);
+        r.x = offF<T, FB>(a);
         r.y = (uint32_t)S.dur[a] | ((uint32_t)(S.predoff[a + 1] - po) << 16);
         r.z = (uint32_t)po;
         r.w = (uint32_t)a;
         reinterpret_cast<uint4 *>(S.prec)[p] = r;
         for (int w = 0; w < NW; ++w) S.prq[p * NW + w] = S.rq[a * NW + w];
     }
-    for (int e = threadIdx.x; e < D.n_arcs; e += T) S.predT[e] = off16<T>(S.pred[e]);
+    for (int e = threadIdx.x; e < D.n_arcs; e += T) S.predT[e] = offF<T, FB>(S.pred[e]);
 }
 
 // Position of the first successor / last predecessor of each w_p, then the
 // feasible swaps in canonical order (u ascending, v ascending).  Returns the
 // number of feasible moves (uniform across the workgroup).
-template <int T>
+template <int T, int FB = 16>
 __device__ int build_moves(const Sh &S, const InstDesc &D, int delta) {
     const int N = D.n, tid = threadIdx.x;
-    build_records<T>(S, D);
+    build_records<T, FB>(S, D);
     for (int p = tid; p < N; p += T) S.pos[S.W[p]] = (uint16_t)p;
     __syncthreads();
     for (int p = tid; p < N; p += T) {
@@ -299,20 +323,20 @@ __device__ inline long long block_sum_i64(long long x, unsigned long long *red) 
 // es_prec: the latest finish time among the predecessors (two reads in
 // flight).  Lane decodes read the precomputed offsets predT, single-thread
 // decodes (stride 1) the predecessor ids.
-template <int STRIDE>
+template <int STRIDE, int FB = 16>
 __device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int po, int np) {
     int es = 0;
     for (int e = 0; e < np; e += 2) {
         const int e1 = (e + 1 < np) ? e + 1 : e;
         uint32_t o0, o1;
         if (STRIDE == 1) {
-            o0 = 2u * S.pred[po + e];
-            o1 = 2u * S.pred[po + e1];
+            o0 = (FB / 8) * (uint32_t)S.pred[po + e];
+            o1 = (FB / 8) * (uint32_t)S.pred[po + e1];
         } else {
             o0 = S.predT[po + e];
             o1 = S.predT[po + e1];
         }
-        es = max(es, max(M.ld16b(o0), M.ld16b(o1)));
+        es = max(es, max(M.template ldf<FB>(o0), M.template ldf<FB>(o1)));
     }
     return es;
 }
@@ -330,11 +354,11 @@ __device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int p
 // activity, one per predecessor read, one per time unit examined by Alg. 5
 // and one per time unit updated by Alg. 6 (d of each for an activity that
 // requests nothing).
-template <int NW, int STRIDE, bool COUNT = false>
+template <int NW, int STRIDE, bool COUNT = false, int FB = 16>
 __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, int L, int u, int v, int p0, int p1,
                          int &front, bool &ovf, long long *wk = nullptr) {
     LaneMem<STRIDE> M{lane_base};
-    const int F0 = (D.n + 1) >> 1;
+    const int F0 = f_dwords<FB>(D.n);
     uint32_t G[NW], FULL[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -356,8 +380,8 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
             any |= rq[w];
         }
         const int d = r.y & 0xffff, np = r.y >> 16;
-        const uint32_t fo = (STRIDE == 1) ? 2u * r.w : r.x;
-        const int es = prec_earliest<STRIDE>(S, M, (int)r.z, np);
+        const uint32_t fo = (STRIDE == 1) ? (FB / 8) * r.w : r.x;
+        const int es = prec_earliest<STRIDE, FB>(S, M, (int)r.z, np);
         if (COUNT) w_ops += 1 + np;
         int s = es;
         if (any != 0 && d > 0) {
@@ -416,11 +440,11 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         } else if (COUNT) {
             w_ops += 2 * d;
         }
-        M.st16b(fo, s + d);
+        M.template stf<FB>(fo, s + d);
     }
     front = fr;
     if (COUNT) *wk += w_ops;
-    return p1 == D.n ? M.ld16(D.n - 1) : 0;
+    return p1 == D.n ? M.template ldf<FB>(STRIDE == 1 ? (FB / 8) * (uint32_t)(D.n - 1) : offF<STRIDE, FB>(D.n - 1)) : 0;
 }
 
 // Capacity-indexed: eq. 7 gives the resource earliest start, Alg. 4 updates
@@ -513,10 +537,10 @@ __device__ inline void init_state(const InstDesc &D, uint32_t *lane_base) {
 
 // Copy a state (finish times + resource state up to `front`) from a
 // stride-1 area into a lane's storage.
-template <int NW, int DEC, int STRIDE>
+template <int NW, int DEC, int STRIDE, int FB = 16>
 __device__ inline void copy_state(const InstDesc &D, const uint32_t *src, uint32_t *lane_base, int front) {
     LaneMem<STRIDE> M{lane_base};
-    const int F0 = (D.n + 1) >> 1;
+    const int F0 = f_dwords<FB>(D.n);
     const int n = F0 + (DEC == kEvalCapacity ? (D.sum_r + 1) >> 1 : front * NW);
     int i = 0;
     for (; i + 4 <= n; i += 4) {
@@ -547,66 +571,72 @@ __device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int
 // Decode every feasible move; return the workgroup's minimum key.
 // out_mk (global, canonical index) receives every makespan when non-null.
 //
-// Lanes take the moves in canonical order, T per round.  Before a round,
-// thread 0 extends the decode of W itself (no swap) in the shared base area
-// up to the round's smallest u; every lane copies that state and decodes its
-// candidate from there.  If W's own schedule passes the lane profile length,
-// lanes decode from scratch instead.  Candidates that overflow the lane
-// profile are decoded afterwards by one thread with the long profile.
-// With COUNT every candidate is decoded from scratch and thread 0 adds the
-// algorithmic operations of all decodes to *work_total (a lane's aborted
-// short-profile decode is not counted).
-template <int NW, int T, int DEC, bool COUNT = false>
+// Each wave takes chunks of 64 moves in canonical order (wave w: chunks w,
+// w + T/64, ...), one candidate per lane, and keeps its own base decode:
+// before a chunk, the wave's lane 0 extends the decode of W itself (no swap)
+// in the wave's base area up to the chunk's smallest u; every lane copies
+// that state and decodes its candidate from there.  Waves never wait for
+// each other inside the loop.  If W's own schedule passes the lane profile
+// length, lanes decode from scratch instead.  Candidates that overflow the
+// lane profile are decoded afterwards by one thread with the long profile.
+// With COUNT every candidate is decoded from scratch and the algorithmic
+// operations of all decodes are added to *work_total (a lane's aborted
+// short-profile decode is not counted).  FB: bits per finish time in the
+// lane and base states (8 when the lane profile is at most 255 units).
+template <int NW, int T, int DEC, bool COUNT = false, int FB = 16>
 __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
                                              int L, int delta, TabuSrc tabu, int asp, int *out_mk,
                                              long long *ovf_total, long long *work_total = nullptr,
                                              bool share = true) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     unsigned long long best = ~0ull;
     long long lw = 0;
-    int *ovf_n = S.scal;          // overflowed candidates
-    int *bstate = S.scal + 1;     // base decode: positions done, front, overflowed
+    int *ovf_n = S.scal;                  // overflowed candidates
+    int *bstate = S.scal + 1 + 3 * wv;    // this wave's base decode: positions done, front, overflowed
+    uint32_t *bst = S.bst + wv * ((Ly.per_lane + 3) & ~3);   // 16-byte aligned per wave
     const bool use_base = share && !COUNT;
-    if (tid == 0) {
-        *ovf_n = 0;
+    if (tid == 0) *ovf_n = 0;
+    if (lane == 0) {
         bstate[0] = 0;
         bstate[1] = 0;
         bstate[2] = 0;
+        if (use_base) init_state<DEC, 1>(D, bst);
     }
-    if (use_base && tid == 0) init_state<DEC, 1>(D, S.bst);
     __syncthreads();
     uint32_t *lane_base = S.region + tid;
-    for (int j0 = 0; j0 < nfeas; j0 += T) {
+    for (int j0 = wv * 64; j0 < nfeas; j0 += T) {
         if (use_base) {
             const int ulo = S.moves[j0] & 0xffff;
-            if (tid == 0 && !bstate[2] && bstate[0] < ulo) {
+            if (lane == 0 && !bstate[2] && bstate[0] < ulo) {
                 bool bovf = false;
                 int bf = bstate[1];
-                if (DEC == kEvalTime) decode_ti<NW, 1>(S, D, S.bst, L, 0, 0, bstate[0], ulo, bf, bovf);
-                else decode_ci<1>(S, D, S.bst, 0, 0, bstate[0], ulo);
+                if (DEC == kEvalTime) decode_ti<NW, 1, false, FB>(S, D, bst, L, 0, 0, bstate[0], ulo, bf, bovf);
+                else decode_ci<1>(S, D, bst, 0, 0, bstate[0], ulo);
                 bstate[0] = ulo;
                 bstate[1] = bf;
                 bstate[2] = bovf ? 1 : 0;
             }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
         }
-        const int j = j0 + tid;
+        const int j = j0 + lane;
         if (j < nfeas) {
             const uint32_t mv = S.moves[j];
-            const int u = mv & 0xffff, v = mv >> 16;
+            const int u = mv & 0xffff, v = (mv >> 16) & 0x7fff;
             int p0 = 0, front = 0;
             if (use_base && !bstate[2]) {
                 p0 = bstate[0];
                 front = bstate[1];
-                copy_state<NW, DEC, T>(D, S.bst, lane_base, front);
+                copy_state<NW, DEC, T, FB>(D, bst, lane_base, front);
             } else {
                 init_state<DEC, T>(D, lane_base);
             }
             bool ovf = false;
             int c;
             long long cw = 0;
-            if (DEC == kEvalTime) c = decode_ti<NW, T, COUNT>(S, D, lane_base, L, u, v, p0, D.n, front, ovf, &cw);
-            else c = decode_ci<T, COUNT>(S, D, lane_base, u, v, p0, D.n, &cw);
+            if (DEC == kEvalTime)
+                c = decode_ti<NW, T, COUNT, FB>(S, D, lane_base, L, u, v, p0, D.n, front, ovf, &cw);
+            else
+                c = decode_ci<T, COUNT>(S, D, lane_base, u, v, p0, D.n, &cw);
             if (COUNT && !ovf) lw += cw;
             if (ovf) {
                 S.moves[j] = mv | 0x80000000u;
@@ -617,7 +647,7 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
                 if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
             }
         }
-        if (use_base) __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     if (DEC == kEvalTime) {
@@ -865,19 +895,26 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
 }
 
 // Lane-per-candidate (G = 1) or group decode (G > 1, time-indexed only).
+// Layout codes: G = 1 one candidate per lane with 16-bit finish times,
+// G = 2 one candidate per lane with 8-bit finish times (lane profiles of at
+// most 255 units), G = 16 one candidate per 16 lanes (time-indexed).
 template <int NW, int T, int DEC, int G, bool COUNT = false>
 __device__ inline unsigned long long evaluate_any(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas, int L,
                                                   int delta, TabuSrc tabu, int asp, int *out_mk, long long *ovf_total,
                                                   long long *work_total = nullptr, bool share = true) {
-    if constexpr (G > 1) {
+    if constexpr (G > 2) {
         static_assert(DEC == kEvalTime, "group decode is time-indexed");
         return evaluate_moves_g<NW, T, G, COUNT>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk, ovf_total, work_total,
                                                  share);
     } else {
-        return evaluate_moves<NW, T, DEC, COUNT>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk, ovf_total,
-                                                 work_total, share);
+        return evaluate_moves<NW, T, DEC, COUNT, G == 2 ? 8 : 16>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk,
+                                                                 ovf_total, work_total, share);
     }
 }
+
+// Finish-time bits of the lane records for a layout code.
+template <int G>
+constexpr int records_fb() { return G == 2 ? 8 : 16; }
 
 // ---------------------------------------------------------------------------
 // rcpsp_evaluate_neighbourhood
@@ -925,7 +962,7 @@ __global__ __launch_bounds__(T) void k_eval(EvalArgs A) {
         if (tid == 0) A.best[3] = -5;  // RCPSP_E_ORDER
         return;
     }
-    const int nf = build_moves<T>(S, D, A.delta);
+    const int nf = build_moves<T, records_fb<G>()>(S, D, A.delta);
     if (A.makespan) {
         for (int i = tid; i < A.P; i += T) A.makespan[i] = -1;
     }
@@ -1111,7 +1148,7 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
         if (flags0 & kFlagDiversify) {
             // Section 6.1: phi_steps random feasible swaps, tabu list untouched
             for (int step = 0; step < A.phi_steps; ++step) {
-                const int nf = build_moves<T>(S, D, A.delta);
+                const int nf = build_moves<T, records_fb<G>()>(S, D, A.delta);
                 if (nf == 0) break;
                 if (tid == 0) {
                     const int j = (int)rng_below(A.seed, kStreamDiversify + (uint64_t)b, sc.rng_ctr++, (uint32_t)nf);
@@ -1172,7 +1209,7 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
             if (tid == 0 && sc.it_done < A.iters) sc.stopped = 1;
             break;
         }
-        const int nf = build_moves<T>(S, D, A.delta);
+        const int nf = build_moves<T, records_fb<G>()>(S, D, A.delta);
         if (nf == 0) {
             if (tid == 0) sc.stopped = 1;
             break;
@@ -1691,22 +1728,37 @@ __global__ void k_clock(long long *out) {
     default:                                                                                                         \
         switch (((TV) * 16 + (NWV)) * 32 + (GV)) {                                                                   \
         case (64 * 16 + 1) * 32 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
+        case (64 * 16 + 1) * 32 + 2: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;      \
         case (64 * 16 + 1) * 32 + 16: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
         case (64 * 16 + 2) * 32 + 1: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
+        case (64 * 16 + 2) * 32 + 2: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;      \
         case (64 * 16 + 2) * 32 + 16: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
         case (64 * 16 + 4) * 32 + 1: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
+        case (64 * 16 + 4) * 32 + 2: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;      \
         case (64 * 16 + 4) * 32 + 16: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
         case (128 * 16 + 1) * 32 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (128 * 16 + 1) * 32 + 2: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
         case (128 * 16 + 1) * 32 + 16: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
         case (128 * 16 + 2) * 32 + 1: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (128 * 16 + 2) * 32 + 2: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
         case (128 * 16 + 2) * 32 + 16: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
         case (128 * 16 + 4) * 32 + 1: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (128 * 16 + 4) * 32 + 2: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
         case (128 * 16 + 4) * 32 + 16: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        case (192 * 16 + 1) * 32 + 1: { constexpr int T_ = 192, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (192 * 16 + 1) * 32 + 2: { constexpr int T_ = 192, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
+        case (192 * 16 + 2) * 32 + 1: { constexpr int T_ = 192, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (192 * 16 + 2) * 32 + 2: { constexpr int T_ = 192, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
+        case (192 * 16 + 4) * 32 + 1: { constexpr int T_ = 192, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (192 * 16 + 4) * 32 + 2: { constexpr int T_ = 192, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
         case (256 * 16 + 1) * 32 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (256 * 16 + 1) * 32 + 2: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
         case (256 * 16 + 1) * 32 + 16: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
         case (256 * 16 + 2) * 32 + 1: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (256 * 16 + 2) * 32 + 2: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
         case (256 * 16 + 2) * 32 + 16: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
         case (256 * 16 + 4) * 32 + 1: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
+        case (256 * 16 + 4) * 32 + 2: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
         case (256 * 16 + 4) * 32 + 16: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
         default: return hipErrorInvalidValue;                                                                        \
         }                                                                                                            \

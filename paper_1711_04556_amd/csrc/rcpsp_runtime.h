@@ -48,7 +48,8 @@ struct rcpsp_search {
     const rcpsp_instance *inst = nullptr;
     rcpsp_search_params p{};
     int T = 64, L = 0, nw = 1, dec = 1, tcw = 1, P = 0;
-    int G = 1;            // lanes per candidate (1, or 16 for the time-indexed group decode)
+    int G = 1;            // layout: 1 one candidate per lane, 2 the same with 8-bit finish
+                          // times, 16 one candidate per 16 lanes (time-indexed)
     int reserve = 256;    // static LDS of the kernel the plan runs in
     rcpsp::Layout Ly{};
     size_t lds = 0;

@@ -96,7 +96,8 @@ REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 class rcpsp_search_config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches", "lanes")]
+        "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches", "lanes",
+        "finish_bits")]
 
 
 _lib = None
