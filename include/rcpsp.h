@@ -141,7 +141,7 @@ typedef struct {
     int32_t profile_len;      /* time-indexed LDS profile slots per lane, 0 = auto
                                  (about 1.4 x critical path, stretched while the
                                  workgroups per CU stay the same, never below
-                                 critical path + longest duration) */
+                                 1.25 x critical path + longest duration) */
     int32_t record_trajectory;/* 1 = keep (u, v, C_after, C_best) per iteration on the device */
     int32_t count_work;       /* 1 = also count the decodes' algorithmic operations
                                  (instrumented kernels; for measurement runs) */
@@ -151,8 +151,8 @@ typedef struct {
     int32_t eval;             /* decoder for this search: 0 = the instance's,
                                  or capacity-indexed when the instance's is
                                  time-indexed and its LDS profile (at least
-                                 critical path + longest duration slots) does
-                                 not fit; 1 time-indexed, 2 capacity-indexed.
+                                 1.25 x critical path + longest duration
+                                 slots) does not fit; 1 time-indexed, 2 capacity-indexed.
                                  The resolved decoder is reported by
                                  rcpsp_search_get_config and decides results. */
     int32_t lanes;            /* lanes per candidate decode: 0 = auto (1, or 16
@@ -228,7 +228,8 @@ rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config 
  * iteration runs.  The groups' launches run side by side in one captured
  * graph.
  *   inst    [count] instances (must outlive the batch)
- *   params  [count] search parameters (threads 0 = 64)
+ *   params  [count] search parameters (threads 0 = 64; a member whose
+ *           workgroup does not fit with the given threads takes fewer)
  * Errors: RCPSP_E_TOO_LARGE when an instance's workgroup does not fit a CU;
  * RCPSP_E_DEVICE from run_timed or results when a run ended early because
  * one wait inside the kernel exceeded its limit (20 s), which leaves the

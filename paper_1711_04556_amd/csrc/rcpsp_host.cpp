@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -411,6 +412,7 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
     };
     Layout Ly;
     if (L_req > 0) {
+        if (G == 2 && L_req > 255) return fail(RCPSP_E_TOO_LARGE, "8-bit finish times need a profile of at most 255");
         int L = cover(std::min(L_req, H));
         if (!fits(L, &Ly))
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget, T, L);
@@ -420,10 +422,11 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
     }
     int L = std::min(H, ((14 * I->cp + 9) / 10 + 2 * I->dmax + 15) / 16 * 16);
     L = cover(std::max(L, 1));
-    // shorter profiles trade LDS for long-profile decodes; below the critical
-    // path plus the longest duration nearly every candidate would take that
-    // path, so the decoder does not fit
-    const int Lfloor = std::max(16, std::min(H, I->cp + I->dmax));
+    // shorter profiles trade LDS for long-profile decodes; below 1.25 x the
+    // critical path plus the longest duration most candidates of a search
+    // take that path (schedules of tight instances run well past the critical
+    // path), so the decoder does not fit
+    const int Lfloor = std::max(16, std::min(H, (5 * I->cp + 3) / 4 + I->dmax));
     while (!fits(L, &Ly)) {
         if (L <= Lfloor)
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, profile %d)", Ly.total * 4, budget,
@@ -691,7 +694,8 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     int T = T0;
     rcpsp_status st = RCPSP_E_TOO_LARGE;
     auto try_shape = [&](int G, int Lreq) {
-        T = T0;
+        // 192 threads exist for the one-candidate-per-lane time-indexed layouts only
+        T = (T0 == 192 && (s->dec != kEvalTime || G > 2)) ? 128 : T0;
         st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, Lreq, s->reserve, &s->L, &s->Ly, G);
         while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
             T /= 2;
@@ -710,7 +714,7 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     } else {
         try_shape(1, p.profile_len);
     }
-    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0 && s->dec == kEvalTime && T0 != 192) try_shape(16, p.profile_len);
+    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0 && s->dec == kEvalTime) try_shape(16, p.profile_len);
     if (st == RCPSP_E_TOO_LARGE && p.eval == RCPSP_EVAL_AUTO && s->dec == kEvalTime) {
         // automatic choice: no time-indexed profile fits, take the capacity-indexed decoder
         s->dec = kEvalCapacity;
@@ -1042,6 +1046,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
 struct rcpsp_batch {
     struct Class {
         int dec = 0, nw = 0, T = 0, G = 1, per_cu = 0, grid = 0, count = 0;
+        long long first_tasks = 0;   // search tasks of the first iteration
         size_t lds = 0;
         BatchClassArgs args{};
     };
@@ -1089,13 +1094,24 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         if (st != RCPSP_OK) return st;
         if (p.threads == 0) p.threads = 64;
         p.count_work = 0;
-        rcpsp_search *s = new (std::nothrow) rcpsp_search();
-        if (!s) return fail(RCPSP_E_NOMEM, "out of host memory");
-        s->inst = inst[i];
-        s->p = p;
-        s->reserve = kBatchStaticLds;
+        // the threads per search (chosen per group by the autotuner) are a
+        // preference: a member whose workgroup does not fit takes fewer
+        rcpsp_search *s = nullptr;
+        for (;;) {
+            s = new (std::nothrow) rcpsp_search();
+            if (!s) return fail(RCPSP_E_NOMEM, "out of host memory");
+            s->inst = inst[i];
+            s->p = p;
+            s->reserve = kBatchStaticLds;
+            st = alloc_plan(s);
+            if (st == RCPSP_E_TOO_LARGE && p.threads > 64) {
+                rcpsp_search_destroy(s);
+                p.threads = p.threads == 192 ? 128 : p.threads / 2;
+                continue;
+            }
+            break;
+        }
         bt->items.push_back(s);
-        st = alloc_plan(s);
         if (st != RCPSP_OK) return st;
         const int need = 6 * p.searches + 5 * p.elite;
         if (p.elite > 0 && need > s->Ly.cands * s->Ly.per_lane)
@@ -1167,6 +1183,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         for (int j = 0; j < cl.count; ++j) cumB[j + 1] = cumB[j] + bt->items[m[j]]->p.searches;
         for (int j = 0; j < cl.count; ++j)
             for (int it = 0; it < steps_of(m[j]); ++it) act[it] = j + 1;
+        cl.first_tasks = max_steps > 0 ? cumB[act[0]] : 0;
         std::vector<long long> off(max_steps + 1);
         off[0] = cl.count;
         for (int it = 0; it < max_steps; ++it) off[it + 1] = off[it] + cumB[act[it]];
@@ -1203,7 +1220,10 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         A.done = bt->d_state + cursor + cl.count;
         cursor += 2ll * cl.count;
         HIP_TRY(prepare_batch(cl.T, cl.nw, cl.dec, cl.G, cl.lds));
-        cl.grid = (int)std::min<long long>(A.total, (long long)cl.per_cu * cus);
+    }
+    for (int c = 0; c < nc; ++c) {
+        rcpsp_batch::Class &cl = bt->classes[c];
+        cl.grid = (int)std::min<long long>(cl.args.total, (long long)cl.per_cu * cus);
     }
     // one graph: clear the counters, then every class's persistent launch on
     // its own branch so that the classes run side by side

@@ -568,6 +568,10 @@ __device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int
     return decode_ci<1, COUNT>(S, D, S.region, u, v, 0, D.n, wk);
 }
 
+template <int NW, int G, bool COUNT>
+__device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, int u, int v, int p0, int p1,
+                         int &front, bool &ovf, long long *wk);
+
 // Decode every feasible move; return the workgroup's minimum key.
 // out_mk (global, canonical index) receives every makespan when non-null.
 //
@@ -578,7 +582,7 @@ __device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int
 // that state and decodes its candidate from there.  Waves never wait for
 // each other inside the loop.  If W's own schedule passes the lane profile
 // length, lanes decode from scratch instead.  Candidates that overflow the
-// lane profile are decoded afterwards by one thread with the long profile.
+// lane profile are decoded afterwards with a profile of the full horizon.
 // With COUNT every candidate is decoded from scratch and the algorithmic
 // operations of all decodes are added to *work_total (a lane's aborted
 // short-profile decode is not counted).  FB: bits per finish time in the
@@ -650,10 +654,51 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    if (DEC == kEvalTime) {
+    if constexpr (DEC == kEvalTime) {
         const int novf = *ovf_n;
         if (novf > 0) {
-            if (tid == 0) {
+            // Candidates whose schedule passed the lane profile: groups of
+            // 16 lanes decode them side by side (the group decode below),
+            // each group in its own slice of the candidate region when a
+            // slice holds a profile of the whole horizon (no schedule is
+            // longer than the sum of durations); else one thread in the
+            // whole region.
+            constexpr int GG = 16, NGR = T / GG;
+            const int grp = tid / GG, g = tid & (GG - 1), gbase = tid & 63 & ~(GG - 1);
+            const int F016 = (D.n + 1) >> 1;
+            const int chunk = ((Ly.cands * Ly.per_lane) / NGR) & ~3;
+            const int glen = (chunk - F016) / NW;
+            if (glen >= D.horizon) {
+                uint32_t *cb = S.region + grp * chunk;
+                int rank = 0;
+                for (int j0 = 0; j0 < nfeas; j0 += GG) {
+                    const int jj = j0 + g;
+                    const bool flagged = jj < nfeas && (S.moves[jj] & 0x80000000u) != 0u;
+                    unsigned long long m = (__ballot(flagged) >> gbase) & 0xffffull;
+                    while (m != 0ull) {
+                        const int bit = __ffsll(m) - 1;
+                        m &= m - 1ull;
+                        if (rank++ % NGR != grp) continue;
+                        const int j = j0 + bit;
+                        const uint32_t mv = S.moves[j];
+                        const int u = mv & 0xffff, v = (mv >> 16) & 0x7fff;
+                        bool ovf = false;
+                        int front = 0;
+                        long long cw = 0;
+                        const int c = decode_tg<NW, GG, COUNT>(S, D, cb, glen, u, v, 0, D.n, front, ovf, &cw);
+                        if (g == 0) {
+                            if (COUNT) lw += cw;
+                            const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
+                            best = k < best ? k : best;
+                            if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                __syncthreads();
+                for (int j = tid; j < nfeas; j += T) S.moves[j] &= 0x7fffffffu;
+                if (tid == 0 && ovf_total) *ovf_total += novf;
+            } else if (tid == 0) {
                 for (int j = 0; j < nfeas; ++j) {
                     const uint32_t mv = S.moves[j];
                     if (mv & 0x80000000u) {
@@ -700,9 +745,9 @@ __device__ inline int group_max(int x) {
     return x;
 }
 
-template <int NW, int G, bool COUNT = false>
+template <int NW, int G, bool COUNT>
 __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, int u, int v, int p0, int p1,
-                         int &front, bool &ovf, long long *wk = nullptr) {
+                         int &front, bool &ovf, long long *wk) {
     static_assert(G == 4 || G == 8 || G == 16, "lanes per candidate");
     const int g = threadIdx.x & (G - 1);
     const int gbase = threadIdx.x & 63 & ~(G - 1);
@@ -821,7 +866,7 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
             if (grp == 0 && !bstate[2] && bstate[0] < ulo) {
                 bool bovf = false;
                 int bf = bstate[1];
-                decode_tg<NW, G>(S, D, S.bst, L, 0, 0, bstate[0], ulo, bf, bovf);
+                decode_tg<NW, G, false>(S, D, S.bst, L, 0, 0, bstate[0], ulo, bf, bovf, nullptr);
                 if (g == 0) {
                     bstate[0] = ulo;
                     bstate[1] = bf;

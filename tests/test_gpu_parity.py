@@ -152,7 +152,7 @@ def test_single_search_trajectory_30(rc, dec):
     _compare_search(g, o)
 
 
-@pytest.mark.parametrize("threads", [64, 128, 256])
+@pytest.mark.parametrize("threads", [64, 128, 192, 256])
 def test_independent_searches_any_launch_shape(rc, threads):
     inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=63)
     orc = oracle.Oracle(inst)
@@ -162,16 +162,32 @@ def test_independent_searches_any_launch_shape(rc, threads):
     _compare_search(g, o)
 
 
-def test_short_profile_overflow_path(rc):
-    """A 16-slot lane profile forces most candidates through the long-profile
-    decode; results must not change."""
+@pytest.mark.parametrize("threads", [64, 192, 256])
+def test_short_profile_overflow_path(rc, threads):
+    """A 16-slot lane profile forces most candidates through the full-horizon
+    re-decode (16-lane groups side by side); results must not change."""
     inst = synth.single_instance_30(1)
     orc = oracle.Oracle(inst)
     gi = rc.Instance(inst, eval=TIME)
-    g = rc.tabu_search(gi, swap_range=8, tabu_len=60, iterations=30, searches=2, profile_len=16, seed=2)
+    g = rc.tabu_search(gi, swap_range=8, tabu_len=60, iterations=30, searches=2, profile_len=16, threads=threads,
+                       seed=2)
     o = orc.tabu_search(8, 60, 30, searches=2, decoder=TIME, seed=2)
     _compare_search(g, o)
     assert g["overflow_decodes"] > 0
+
+
+def test_overflow_redecode_counts_same_work(rc):
+    """Candidates re-decoded after a lane-profile overflow count the same
+    algorithmic operations as when the lane profile holds them."""
+    inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=25)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=10, tabu_len=60, iterations=10, searches=4, seed=7, count_work=True, threads=192)
+    a = rc.tabu_search(gi, **kw)
+    b = rc.tabu_search(gi, profile_len=16, **kw)
+    for k in ("trajectory", "best_makespan", "evaluations"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["overflow_decodes"] == 0 and b["overflow_decodes"] > 0
+    assert a["total_work"] == b["total_work"] > 0
 
 
 @pytest.mark.parametrize("dec", [TIME, CAP])
@@ -433,3 +449,22 @@ def test_batch_mixes_lane_and_group_decode(rc):
                                             seed=40 + k)
         _compare_search(bt.results(k), o, elite=3)
     bt.close()
+
+
+@pytest.mark.parametrize("threads,profile_len,bits", [(192, 0, 8), (64, 300, 16), (128, 0, 8)])
+def test_finish_time_width_and_three_waves(rc, threads, profile_len, bits):
+    """Lane states hold 8-bit finish times while the lane profile is at most
+    255 units and 16-bit beyond; 192 threads run three waves, each with its
+    own base decode.  Same search as the oracle either way."""
+    inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=64)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=12, tabu_len=60, iterations=30, searches=9, elite=4, phi_max=2, phi_steps=5, seed=12)
+    plan = rc.SearchPlan(gi, rc.search_params(threads=threads, profile_len=profile_len, eval=TIME, **kw))
+    cfg = plan.config
+    assert cfg["threads"] == threads and cfg["finish_bits"] == bits and cfg["lanes"] == 1
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(12, 60, 30, searches=9, elite=4, phi_max=2, phi_steps=5, decoder=TIME, seed=12)
+    _compare_search(g, o, elite=4)
