@@ -346,6 +346,15 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     Ly.prec = o; o += 4 * D.n;
     Ly.prq = o; o += D.n * std::max(D.nw, 1);
     Ly.predT = o; o += std::max(D.n_arcs, 1);
+    // one candidate per lane, time-indexed: the lane offsets of the first
+    // four predecessors' finish times per position (16-byte entries)
+    const bool group = dec == kEvalTime && G > 2;
+    o = (o + 3) & ~3;
+    Ly.pin = 0;
+    if (dec == kEvalTime && !group) {
+        Ly.pin = o;
+        o += 4 * D.n;
+    }
     o = (o + 1) & ~1;
     Ly.red = o; o += 2 * (T / 64);
     Ly.scal = o; o += std::max(4, 1 + 3 * (T / 64));
@@ -353,7 +362,6 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     // plus 4 of slack for the 4-wide scan) or the capacity arrays and the
     // copy ring
     // G = 2: one candidate per lane with 8-bit finish times
-    const bool group = dec == kEvalTime && G > 2;
     const int Fl = (dec == kEvalTime && G == 2) ? (D.n + 3) / 4 : F0;
     if (group) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
     else if (dec == kEvalTime) Ly.per_lane = Fl + (L + 4) * D.nw;

@@ -37,7 +37,7 @@ struct InstDesc {
 
 // Dword offsets of the workgroup's LDS areas.
 struct Layout {
-    int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, prec, prq, predT, bst, red, scal, region;
+    int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, prec, prq, predT, pin, bst, red, scal, region;
     int per_lane;    // dwords of private decode state per candidate slot
     int cands;       // candidate slots per round (threads, or threads / lanes per candidate)
     int long_len;    // time slots available to the single-thread long-profile decode

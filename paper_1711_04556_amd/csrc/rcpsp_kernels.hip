@@ -32,7 +32,7 @@ struct Sh {
     const uint32_t *rq, *res;
     uint16_t *W, *Wimp, *pos, *fs, *lp;
     int *cnt;
-    uint32_t *tc, *ring, *moves, *prec, *prq, *predT, *bst;
+    uint32_t *tc, *ring, *moves, *prec, *prq, *predT, *pin, *bst;
     unsigned long long *red;
     int *scal;
     uint32_t *region;
@@ -63,6 +63,7 @@ __device__ inline Sh make_sh(uint32_t *lds, const InstDesc &D, const Layout &Ly)
     s.prec = lds + Ly.prec;
     s.prq = lds + Ly.prq;
     s.predT = lds + Ly.predT;
+    s.pin = Ly.pin ? lds + Ly.pin : nullptr;
     s.bst = lds + Ly.bst;
     s.red = reinterpret_cast<unsigned long long *>(lds + Ly.red);
     s.scal = reinterpret_cast<int *>(lds + Ly.scal);
@@ -199,7 +200,10 @@ __device__ inline unsigned long long block_min_u64(unsigned long long x, unsigne
 //   prec[4p..4p+3] = (byte offset of f[w_p] in a lane's storage, d | npred << 16,
 //                     first predecessor index, w_p),
 //   prq[p*NW + w]  = packed requests of w_p (time-indexed profile words),
-//   predT[e]       = byte offset of f[pred[e]] in a lane's storage.
+//   predT[e]       = byte offset of f[pred[e]] in a lane's storage,
+//   pin[4p..4p+3]  = the same offsets for the first four predecessors of w_p
+//                    (one 16-byte load; present for one-candidate-per-lane
+//                    time-indexed layouts only).
 template <int T, int FB = 16>
 __device__ inline void build_records(const Sh &S, const InstDesc &D) {
     const int N = D.n, NW = D.nw;
@@ -215,6 +219,16 @@ __device__ inline void build_records(const Sh &S, const InstDesc &D) {
         for (int w = 0; w < NW; ++w) S.prq[p * NW + w] = S.rq[a * NW + w];
     }
     for (int e = threadIdx.x; e < D.n_arcs; e += T) S.predT[e] = offF<T, FB>(S.pred[e]);
+    if (S.pin) {
+        for (int p = threadIdx.x; p < N; p += T) {
+            const int a = S.W[p];
+            const int po = S.predoff[a], np = S.predoff[a + 1] - po;
+            uint32_t o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] = k < np ? offF<T, FB>(S.pred[po + k]) : 0u;
+            reinterpret_cast<uint4 *>(S.pin)[p] = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+    }
 }
 
 // Position of the first successor / last predecessor of each w_p, then the
@@ -348,12 +362,21 @@ __device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int p
 // whose schedule would pass L reports overflow and is decoded again with a
 // longer profile.  Time units at or beyond `front` have never been written and
 // hold the full capacity, so a scan that reaches `front` ends there.  Each
-// scan step tests four units with selects only, so their loads are in flight
-// together.
+// scan step tests four units with selects only, so their loads are in
+// flight together.  Alg. 6 is a fill of never-written units up to s + d with
+// the full capacity, then LDS atomic subtractions: neither waits for a
+// returned value.  The record of the next position is loaded while the
+// current one is placed, and one-candidate-per-lane layouts read the first
+// four predecessor offsets in one load; the work done stays that of Alg. 5
+// and 6.
 // With COUNT, *wk receives the decode's algorithmic operations: one per
 // activity, one per predecessor read, one per time unit examined by Alg. 5
 // and one per time unit updated by Alg. 6 (d of each for an activity that
 // requests nothing).
+__device__ inline void lds_sub(uint32_t *p, uint32_t x) {
+    __hip_atomic_fetch_sub(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int NW, int STRIDE, bool COUNT = false, int FB = 16>
 __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, int L, int u, int v, int p0, int p1,
                          int &front, bool &ovf, long long *wk = nullptr) {
@@ -365,13 +388,23 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         G[w] = D.guard[w];
         FULL[w] = D.full[w];
     }
+    constexpr bool kPin = STRIDE > 1;
     const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
+    const uint4 *pin = reinterpret_cast<const uint4 *>(S.pin);
     uint32_t *prof = lane_base + F0 * STRIDE;   // time unit t, word w at prof[(t*NW + w)*STRIDE]
     long long w_ops = 0;
     int fr = front;
+    // the record and predecessor offsets of a position (clamped to the last
+    // one, so the load one position ahead stays in range)
+    auto qof = [&](int p) {
+        p = min(p, D.n - 1);
+        return (p == u) ? v : ((p == v) ? u : p);
+    };
+    int q = qof(p0);
+    uint4 r = rec[q];
+    uint4 pi = kPin ? pin[q] : make_uint4(0u, 0u, 0u, 0u);
     for (int p = p0; p < p1; ++p) {
-        const int q = (p == u) ? v : ((p == v) ? u : p);
-        const uint4 r = rec[q];
+        // requests: loaded with the predecessors' finish times (no wait of their own)
         uint32_t rq[NW];
         uint32_t any = 0;
 #pragma unroll
@@ -381,11 +414,23 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         }
         const int d = r.y & 0xffff, np = r.y >> 16;
         const uint32_t fo = (STRIDE == 1) ? (FB / 8) * r.w : r.x;
-        const int es = prec_earliest<STRIDE, FB>(S, M, (int)r.z, np);
+        int es;
+        if constexpr (kPin) {
+            const int f0 = M.template ldf<FB>(pi.x), f1 = M.template ldf<FB>(pi.y);
+            const int f2 = M.template ldf<FB>(pi.z), f3 = M.template ldf<FB>(pi.w);
+            es = max(max(np > 0 ? f0 : 0, np > 1 ? f1 : 0), max(np > 2 ? f2 : 0, np > 3 ? f3 : 0));
+            for (int e = 4; e < np; ++e) es = max(es, M.template ldf<FB>(S.predT[r.z + e]));
+        } else {
+            es = prec_earliest<STRIDE, FB>(S, M, (int)r.z, np);
+        }
+        // next position's record, loaded while this activity is placed
+        const int qn = qof(p + 1);
+        const uint4 rn = rec[qn];
+        const uint4 pn = kPin ? pin[qn] : make_uint4(0u, 0u, 0u, 0u);
         if (COUNT) w_ops += 1 + np;
         int s = es;
         if (any != 0 && d > 0) {
-            int t = es, run = 0;
+            int t = es, run = 0;   // run: free units just before t
             s = -1;
             while (s < 0 && t < fr) {
                 const uint32_t *P = prof + t * NW * STRIDE;
@@ -413,34 +458,28 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 t += 4;
             }
             if (s < 0) s = t - run;  // reached the frontier: all later units are free
-            if (s + d > L) {
+            const int e = s + d;
+            if (e > L) {
                 ovf = true;
                 return -1;
             }
-            if (COUNT) w_ops += (s + d - es) + d;
-            for (int x = fr; x < s; ++x) {
+            if (COUNT) w_ops += (e - es) + d;
+            for (int x = fr; x < e; ++x) {
 #pragma unroll
                 for (int w = 0; w < NW; ++w) prof[(x * NW + w) * STRIDE] = FULL[w];
             }
-            for (int x = s; x < s + d; x += 2) {
-                uint32_t *P = prof + x * NW * STRIDE;
-                uint32_t A0[NW], A1[NW];
+            for (int x = s; x < e; ++x) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    A0[w] = P[w * STRIDE];
-                    A1[w] = P[(NW + w) * STRIDE];
-                }
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    P[w * STRIDE] = ((x < fr) ? A0[w] : FULL[w]) - rq[w];
-                    if (x + 1 < s + d) P[(NW + w) * STRIDE] = ((x + 1 < fr) ? A1[w] : FULL[w]) - rq[w];
-                }
+                for (int w = 0; w < NW; ++w) lds_sub(prof + (x * NW + w) * STRIDE, rq[w]);
             }
-            fr = max(fr, s + d);
+            fr = max(fr, e);
         } else if (COUNT) {
             w_ops += 2 * d;
         }
         M.template stf<FB>(fo, s + d);
+        q = qn;
+        r = rn;
+        pi = pn;
     }
     front = fr;
     if (COUNT) *wk += w_ops;
@@ -568,7 +607,7 @@ __device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int
     return decode_ci<1, COUNT>(S, D, S.region, u, v, 0, D.n, wk);
 }
 
-template <int NW, int G, bool COUNT>
+template <int NW, int G, bool COUNT, int FB = 16>
 __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, int u, int v, int p0, int p1,
                          int &front, bool &ovf, long long *wk);
 
@@ -577,9 +616,10 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
 //
 // Each wave takes chunks of 64 moves in canonical order (wave w: chunks w,
 // w + T/64, ...), one candidate per lane, and keeps its own base decode:
-// before a chunk, the wave's lane 0 extends the decode of W itself (no swap)
-// in the wave's base area up to the chunk's smallest u; every lane copies
-// that state and decodes its candidate from there.  Waves never wait for
+// before a chunk, the wave extends the decode of W itself (no swap) in its
+// base area up to the chunk's smallest u (time-indexed: lanes 0-15 with the
+// group decode; capacity-indexed: lane 0); every lane copies that state and
+// decodes its candidate from there.  Waves never wait for
 // each other inside the loop.  If W's own schedule passes the lane profile
 // length, lanes decode from scratch instead.  Candidates that overflow the
 // lane profile are decoded afterwards with a profile of the full horizon.
@@ -611,14 +651,24 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
     for (int j0 = wv * 64; j0 < nfeas; j0 += T) {
         if (use_base) {
             const int ulo = S.moves[j0] & 0xffff;
-            if (lane == 0 && !bstate[2] && bstate[0] < ulo) {
-                bool bovf = false;
-                int bf = bstate[1];
-                if (DEC == kEvalTime) decode_ti<NW, 1, false, FB>(S, D, bst, L, 0, 0, bstate[0], ulo, bf, bovf);
-                else decode_ci<1>(S, D, bst, 0, 0, bstate[0], ulo);
-                bstate[0] = ulo;
-                bstate[1] = bf;
-                bstate[2] = bovf ? 1 : 0;
+            if constexpr (DEC == kEvalTime) {
+                // lanes 0-15 of the wave extend it together (group decode)
+                if (lane < 16 && !bstate[2] && bstate[0] < ulo) {
+                    bool bovf = false;
+                    int bf = bstate[1];
+                    decode_tg<NW, 16, false, FB>(S, D, bst, L, 0, 0, bstate[0], ulo, bf, bovf, nullptr);
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane == 0) {
+                        bstate[0] = ulo;
+                        bstate[1] = bf;
+                        bstate[2] = bovf ? 1 : 0;
+                    }
+                }
+            } else {
+                if (lane == 0 && !bstate[2] && bstate[0] < ulo) {
+                    decode_ci<1>(S, D, bst, 0, 0, bstate[0], ulo);
+                    bstate[0] = ulo;
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -745,15 +795,24 @@ __device__ inline int group_max(int x) {
     return x;
 }
 
-template <int NW, int G, bool COUNT>
+template <int NW, int G, bool COUNT, int FB>
 __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, int u, int v, int p0, int p1,
                          int &front, bool &ovf, long long *wk) {
     static_assert(G == 4 || G == 8 || G == 16, "lanes per candidate");
     const int g = threadIdx.x & (G - 1);
     const int gbase = threadIdx.x & 63 & ~(G - 1);
     constexpr unsigned long long gm = (1ull << G) - 1ull;
-    uint16_t *F = reinterpret_cast<uint16_t *>(cb);
-    uint32_t *prof = cb + ((D.n + 1) >> 1);
+    // finish times of FB bits (8: states shared with one-candidate-per-lane
+    // layouts of at most 255 units)
+    auto fget = [&](int a) -> int {
+        if (FB == 8) return reinterpret_cast<const uint8_t *>(cb)[a];
+        return reinterpret_cast<const uint16_t *>(cb)[a];
+    };
+    auto fset = [&](int a, int x) {
+        if (FB == 8) reinterpret_cast<uint8_t *>(cb)[a] = (uint8_t)x;
+        else reinterpret_cast<uint16_t *>(cb)[a] = (uint16_t)x;
+    };
+    uint32_t *prof = cb + f_dwords<FB>(D.n);
     uint32_t Gd[NW], FULL[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -770,7 +829,7 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
         int es = 0;
         for (int e0 = 0; e0 < np; e0 += G) {
             const int e = e0 + g;
-            if (e < np) es = max(es, (int)F[S.pred[r.z + e]]);
+            if (e < np) es = max(es, fget(S.pred[r.z + e]));
         }
         es = group_max<G>(es);
         uint32_t rq[NW];
@@ -827,12 +886,12 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
             w_ops += 2 * d;
         }
         if (COUNT && g == 0) w_ops += 1 + np;
-        if (g == 0) F[a] = (uint16_t)(s + d);
+        if (g == 0) fset(a, s + d);
         __builtin_amdgcn_wave_barrier();
     }
     front = fr;
     if (COUNT && g == 0) *wk += w_ops;
-    return p1 == D.n ? (int)F[D.n - 1] : 0;
+    return p1 == D.n ? fget(D.n - 1) : 0;
 }
 
 // Group version of evaluate_moves: T/G candidates per round, one per group
@@ -1101,6 +1160,25 @@ __global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
     reset_unit<64>(A, blockIdx.x, w);
 }
 
+// Makespan of the order in S.W decoded from scratch over the whole decode
+// region (at least the horizon): time-indexed by lanes 0-15 together (group
+// decode), capacity-indexed by thread 0.  Every thread of the workgroup calls
+// it; the value is that of thread 0.
+template <int NW, int DEC>
+__device__ inline int decode_order(const Sh &S, const InstDesc &D, const Layout &Ly) {
+    if constexpr (DEC == kEvalTime) {
+        int c = 0;
+        if (threadIdx.x < 16) {
+            bool ovf = false;
+            int front = 0;
+            c = decode_tg<NW, 16, false, 16>(S, D, S.region, Ly.long_len, 0, 0, 0, D.n, front, ovf, nullptr);
+        }
+        return c;
+    } else {
+        return threadIdx.x == 0 ? decode_long<NW, DEC>(S, D, Ly, 0, 0) : 0;
+    }
+}
+
 // Makespan of initial working-set record k (buffer 0); the blob is staged.
 template <int NW, int T, int DEC>
 __device__ void decode_record(const SearchArgs &A, const Sh &S, int k) {
@@ -1111,7 +1189,8 @@ __device__ void decode_record(const SearchArgs &A, const Sh &S, int k) {
     __syncthreads();
     build_records<T>(S, D);
     __syncthreads();
-    if (threadIdx.x == 0) A.Fmeta[k].C = decode_long<NW, DEC>(S, D, A.Ly, 0, 0);
+    const int c = decode_order<NW, DEC>(S, D, A.Ly);
+    if (threadIdx.x == 0) A.Fmeta[k].C = c;
     __threadfence();
     __syncthreads();
 }
@@ -1207,7 +1286,8 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
             }
             build_records<T>(S, D);
             __syncthreads();
-            if (tid == 0) sc.C_cur = decode_long<NW, DEC>(S, D, Ly, 0, 0);
+            const int c = decode_order<NW, DEC>(S, D, Ly);
+            if (tid == 0) sc.C_cur = c;
         }
         __syncthreads();
         copy_dw<T>(reinterpret_cast<uint32_t *>(S.Wimp), Wd, N2 / 2);
@@ -1230,8 +1310,9 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
         if (flags0 & kFlagInitDecode) {
             build_records<T>(S, D);
             __syncthreads();
+            const int c = decode_order<NW, DEC>(S, D, Ly);
             if (tid == 0) {
-                sc.C_cur = decode_long<NW, DEC>(S, D, Ly, 0, 0);
+                sc.C_cur = c;
                 sc.C_best = sc.C_cur;
                 ss.dirty_best = 1;
                 sc.flags &= ~kFlagInitDecode;
