@@ -234,21 +234,74 @@ __device__ inline void build_records(const Sh &S, const InstDesc &D) {
 // Position of the first successor / last predecessor of each w_p, then the
 // feasible swaps in canonical order (u ascending, v ascending).  Returns the
 // number of feasible moves (uniform across the workgroup).
-template <int T, int FB = 16>
-__device__ int build_moves(const Sh &S, const InstDesc &D, int delta) {
+// Positions of W, then for each position the first successor and the last
+// predecessor position (stored +1; 0 = none).
+template <int T>
+__device__ inline void order_bounds(const Sh &S, const InstDesc &D) {
     const int N = D.n, tid = threadIdx.x;
-    build_records<T, FB>(S, D);
     for (int p = tid; p < N; p += T) S.pos[S.W[p]] = (uint16_t)p;
     __syncthreads();
     for (int p = tid; p < N; p += T) {
         const int a = S.W[p];
-        int fsv = N, lpv = 0;  // lp stored +1; 0 = no predecessor
+        int fsv = N, lpv = 0;
         for (int e = S.succoff[a]; e < S.succoff[a + 1]; ++e) fsv = min(fsv, (int)S.pos[S.succ[e]]);
         for (int e = S.predoff[a]; e < S.predoff[a + 1]; ++e) lpv = max(lpv, (int)S.pos[S.pred[e]] + 1);
         S.fs[p] = (uint16_t)fsv;
         S.lp[p] = (uint16_t)lpv;
     }
     __syncthreads();
+}
+
+// One random feasible swap of W (the diversification of Section 6.1): the
+// move of index j in canonical order, j drawn uniformly below the number of
+// feasible moves, exactly as build_moves lists them; only the thread whose
+// range of u holds j enumerates its moves again.  Returns the number of
+// feasible moves (0: W is left as it is).
+template <int T>
+__device__ int random_swap(const Sh &S, const InstDesc &D, int delta, uint64_t seed, uint64_t stream,
+                           unsigned long long *ctr) {
+    const int N = D.n, tid = threadIdx.x;
+    order_bounds<T>(S, D);
+    const int nu = N - 2;
+    const int ch = (nu + T - 1) / T;
+    const int u0 = 1 + tid * ch, u1 = min(u0 + ch, N - 1);
+    int c = 0;
+    for (int u = u0; u < u1; ++u) {
+        const int vmax = min(min(u + delta, N - 2), (int)S.fs[u] - 1);
+        for (int v = u + 1; v <= vmax; ++v) c += (S.lp[v] <= u);
+    }
+    int total;
+    const int off = block_excl_scan<T>(c, &total, S.cnt);
+    if (total == 0) return 0;
+    int *shj = S.cnt + T / 64 + 1;
+    if (tid == 0) *shj = (int)rng_below(seed, stream, (*ctr)++, (uint32_t)total);
+    __syncthreads();
+    const int j = *shj;
+    if (j >= off && j < off + c) {
+        int k = off;
+        for (int u = u0; u < u1; ++u) {
+            const int vmax = min(min(u + delta, N - 2), (int)S.fs[u] - 1);
+            for (int v = u + 1; v <= vmax; ++v) {
+                if (S.lp[v] <= u) {
+                    if (k == j) {
+                        const uint16_t t = S.W[u];
+                        S.W[u] = S.W[v];
+                        S.W[v] = t;
+                    }
+                    ++k;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+template <int T, int FB = 16>
+__device__ int build_moves(const Sh &S, const InstDesc &D, int delta) {
+    const int N = D.n, tid = threadIdx.x;
+    build_records<T, FB>(S, D);
+    order_bounds<T>(S, D);
     const int nu = N - 2;
     const int ch = (nu + T - 1) / T;
     const int u0 = 1 + tid * ch, u1 = min(u0 + ch, N - 1);
@@ -1272,17 +1325,8 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
         if (flags0 & kFlagDiversify) {
             // Section 6.1: phi_steps random feasible swaps, tabu list untouched
             for (int step = 0; step < A.phi_steps; ++step) {
-                const int nf = build_moves<T, records_fb<G>()>(S, D, A.delta);
+                const int nf = random_swap<T>(S, D, A.delta, A.seed, kStreamDiversify + (uint64_t)b, &sc.rng_ctr);
                 if (nf == 0) break;
-                if (tid == 0) {
-                    const int j = (int)rng_below(A.seed, kStreamDiversify + (uint64_t)b, sc.rng_ctr++, (uint32_t)nf);
-                    const uint32_t mv = S.moves[j];
-                    const int u = mv & 0xffff, v = mv >> 16;
-                    const uint16_t t = S.W[u];
-                    S.W[u] = S.W[v];
-                    S.W[v] = t;
-                }
-                __syncthreads();
             }
             build_records<T>(S, D);
             __syncthreads();
