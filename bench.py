@@ -83,7 +83,7 @@ def measured_traffic(cfg):
         return None
 
 
-def cpu_baseline(inst, decoder, iters=2):
+def cpu_baseline(inst, decoder, iters=5):
     """The oracle (single thread, as it stands) on a bounded sample of the
     same workload: all 480 searches, the first `iters` iterations."""
     import oracle
