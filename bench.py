@@ -48,6 +48,9 @@ SERVE_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329), 302: (20, 869)}
 # few iterations are timed and the rate is reported
 LARGE = dict(count=256, base_seed=4000, searches=16, elite=16, phi_max=3, phi_steps=20, iterations=4,
              swap_range=20, tabu_len=869)
+# heterogeneous-model leg: independent searches of the plain workload's
+# instance and move parameters, host-driven vs in-kernel
+HOSTED = dict(searches=8, iterations=50)
 
 
 def log(*a):
@@ -176,6 +179,43 @@ def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
         "classes": info,
         "autotune": tuning,
     }
+
+
+def hosted_leg(rcpsp, gi, dec, stream):
+    """The same independent searches in the homogeneous model (the whole loop
+    in one captured graph) and in the heterogeneous model (the host runs the
+    loop, one device neighbourhood evaluation and read-back per iteration);
+    wall time of each, results compared."""
+    import numpy as np
+    import torch
+    kw = dict(WORKLOAD, searches=HOSTED["searches"], iterations=HOSTED["iterations"], elite=0, eval=dec)
+    plan = rcpsp.SearchPlan(gi, rcpsp.search_params(record_trajectory=True, **kw), stream)
+    plan.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(stream)
+    torch.cuda.synchronize()
+    t_hom = time.perf_counter() - t0
+    g = plan.results(stream)
+    plan.close()
+    rcpsp.tabu_search_hosted(gi, stream, **dict(kw, iterations=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = rcpsp.tabu_search_hosted(gi, stream, **kw)
+    torch.cuda.synchronize()
+    t_het = time.perf_counter() - t0
+    equal = all(np.array_equal(g[k], h[k]) for k in ("trajectory", "best_makespan", "iterations_done",
+                                                     "evaluations", "best_order"))
+    its = int(np.asarray(h["iterations_done"]).sum())
+    out = dict(workload=f"{HOSTED['searches']} independent searches x {HOSTED['iterations']} iterations on the "
+                        "plain workload's instance (swap range 20, tabu list 329)",
+               homogeneous_ms=1e3 * t_hom, hosted_ms=1e3 * t_het, search_iterations=its,
+               hosted_us_per_iteration=1e6 * t_het / max(its, 1),
+               homogeneous_evals_per_s=h["total_evaluations"] / t_hom,
+               hosted_evals_per_s=h["total_evaluations"] / t_het,
+               homogeneous_speedup=t_het / t_hom, results_equal=bool(equal))
+    log("hosted", out)
+    return out
 
 
 def large_leg(rcpsp, synth, stream, steps):
@@ -353,6 +393,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-large", action="store_true", help="skip the large-instance leg")
+    ap.add_argument("--no-hosted", action="store_true", help="skip the heterogeneous-model leg")
     ap.add_argument("--serve-rate", type=float, default=SERVE["rate"])
     ap.add_argument("--serve-seconds", type=float, default=SERVE["measure_s"])
     args = ap.parse_args()
@@ -482,11 +523,14 @@ def main():
             "launches_per_step": n_launch,
         },
         "batched": None,
+        "hosted": None,
         "serving": None,
         "large": None,
         "cpu_baseline": None,
     }
     plan.close()
+    if not args.no_hosted:
+        out["hosted"] = hosted_leg(rcpsp, gi, gi.info["eval"], stream)
     if not args.no_batch:
         out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, min(args.warmup, 1))
     if not args.no_large:

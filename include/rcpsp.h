@@ -206,6 +206,24 @@ void rcpsp_search_destroy(rcpsp_search *s);
 rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcpsp_search_params *params,
                                rcpsp_search_result *res, void *hip_stream);
 
+/* The same independent searches in the heterogeneous model (the CPU-driven
+ * alternative the paper compares its homogeneous model with, Section 1): the
+ * host runs each search's loop (move application, Alg. 3 tabu list, best and
+ * stop updates) and every iteration's neighbourhood is evaluated on the
+ * device by rcpsp_evaluate_neighbourhood_device, one launch and one
+ * read-back per iteration, searches one after another.  Initial orders come
+ * from the reset kernel, so the results equal those of rcpsp_tabu_search
+ * with the same parameters.  Synchronous on hip_stream.
+ *   params  elite must be 0 (independent searches), count_work 0, eval 0 or
+ *           the instance's decoder; threads, profile_len and lanes are
+ *           ignored (the evaluation entry point chooses its own shape)
+ *   res     as for rcpsp_search_results (elite outputs untouched,
+ *           overflow_decodes and total_work 0)
+ * Errors: RCPSP_E_ARG for the parameters above; errors of the evaluation
+ * entry point. */
+rcpsp_status rcpsp_tabu_search_hosted(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                      rcpsp_search_result *res, void *hip_stream);
+
 /* Kernel names and per-launch statistics of the last run of a search plan:
  * launches of the iteration kernel and the number of candidate decodes. */
 typedef struct {

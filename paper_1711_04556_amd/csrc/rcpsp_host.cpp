@@ -958,6 +958,120 @@ extern "C" rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcps
     return st;
 }
 
+// Heterogeneous model (the CPU-driven alternative the paper sets against its
+// homogeneous one, Section 1): the host runs every search's loop and the GPU
+// only evaluates each iteration's neighbourhood (the device entry point of
+// rcpsp_evaluate_neighbourhood, one launch and one read-back per
+// iteration).  Initial orders and their makespans come from the reset and
+// decode kernels of a plan of the same searches run for no iteration, so a
+// host-driven search follows exactly the trajectory of the homogeneous one.
+extern "C" rcpsp_status rcpsp_tabu_search_hosted(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                                 rcpsp_search_result *res, void *hip_stream) {
+    if (!inst || !params || !res) return fail(RCPSP_E_ARG, "null pointer");
+    const rcpsp_search_params &p = *params;
+    rcpsp_status st = validate_params(p);
+    if (st != RCPSP_OK) return st;
+    if (p.elite != 0) return fail(RCPSP_E_ARG, "host-driven searches are independent (elite must be 0)");
+    if (p.count_work) return fail(RCPSP_E_ARG, "count_work is not available for host-driven searches");
+    if (p.eval != 0 && p.eval != inst->eval)
+        return fail(RCPSP_E_ARG, "host-driven searches decode with the instance's decoder");
+    hipStream_t hs = (hipStream_t)hip_stream;
+    const int N = inst->n, B = p.searches, iters = p.iterations, tl = p.tabu_len;
+    // initial orders and makespans
+    rcpsp_search_params p0 = p;
+    p0.iterations = 0;
+    p0.record_trajectory = 0;
+    p0.eval = inst->eval;
+    rcpsp_search *s0 = nullptr;
+    st = rcpsp_search_create(inst, &p0, hip_stream, &s0);
+    if (st != RCPSP_OK) return st;
+    std::vector<int32_t> W0((size_t)B * N), C0(B);
+    st = rcpsp_search_run(s0, hip_stream);
+    if (st == RCPSP_OK) {
+        rcpsp_search_result r0{};
+        r0.best_order = W0.data();
+        r0.best_makespan = C0.data();
+        st = rcpsp_search_results(s0, &r0, hip_stream);
+    }
+    rcpsp_search_destroy(s0);
+    if (st != RCPSP_OK) return st;
+    struct Bufs {
+        int32_t *order = nullptr;
+        uint8_t *tabu = nullptr;
+        rcpsp_move *best = nullptr;
+        ~Bufs() {
+            if (order) (void)hipFree(order);
+            if (tabu) (void)hipFree(tabu);
+            if (best) (void)hipFree(best);
+        }
+    } d;
+    HIP_TRY(hipMalloc(&d.order, sizeof(int32_t) * N));
+    HIP_TRY(hipMalloc(&d.tabu, (size_t)N * N));
+    HIP_TRY(hipMalloc(&d.best, sizeof(rcpsp_move)));
+    std::vector<uint8_t> tabu((size_t)N * N);
+    std::vector<uint32_t> ring(tl);
+    int gbest = INT_MAX;
+    long long tot = 0;
+    for (int b = 0; b < B; ++b) {
+        std::vector<int32_t> W(W0.begin() + (size_t)b * N, W0.begin() + (size_t)(b + 1) * N), Wb = W;
+        int Cbest = C0[b], it = 0, widx = 0;
+        long long ev = 0;
+        std::fill(tabu.begin(), tabu.end(), 0);
+        std::fill(ring.begin(), ring.end(), 0u);
+        HIP_TRY(hipMemcpyAsync(d.tabu, tabu.data(), tabu.size(), hipMemcpyHostToDevice, hs));
+        int32_t *traj = (res->trajectory && p.record_trajectory) ? res->trajectory + (size_t)b * iters * 4 : nullptr;
+        if (traj) std::fill(traj, traj + (size_t)iters * 4, -1);
+        for (; it < iters; ++it) {
+            if (Cbest == inst->cp) break;   // independent searches stop at the critical path
+            HIP_TRY(hipMemcpyAsync(d.order, W.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, hs));
+            st = eval_device(inst, d.order, p.swap_range, d.tabu, Cbest, nullptr, d.best, hs);
+            if (st != RCPSP_OK) return st;
+            rcpsp_move mv{};
+            HIP_TRY(hipMemcpyAsync(&mv, d.best, sizeof(rcpsp_move), hipMemcpyDeviceToHost, hs));
+            HIP_TRY(hipStreamSynchronize(hs));
+            if (mv.n_feasible < 0) return fail(RCPSP_E_DEVICE, "neighbourhood evaluation rejected the order");
+            if (mv.n_feasible == 0) break;   // no feasible move: the search stops
+            const int u = mv.u, v = mv.v, c = mv.makespan;
+            std::swap(W[u], W[v]);
+            // Alg. 3: evict the oldest entry, insert (u, v), advance the write index
+            const uint32_t old = ring[widx];
+            if (old != 0u) {
+                const size_t e = (size_t)(old & 0xffff) * N + (old >> 16);
+                tabu[e] = 0;
+                HIP_TRY(hipMemcpyAsync(d.tabu + e, &tabu[e], 1, hipMemcpyHostToDevice, hs));
+            }
+            ring[widx] = (uint32_t)u | ((uint32_t)v << 16);
+            const size_t e = (size_t)u * N + v;
+            tabu[e] = 1;
+            HIP_TRY(hipMemcpyAsync(d.tabu + e, &tabu[e], 1, hipMemcpyHostToDevice, hs));
+            widx = (widx + 1) % tl;
+            ev += mv.n_feasible;
+            if (c < Cbest) {
+                Cbest = c;
+                Wb = W;
+            }
+            if (traj) {
+                traj[(size_t)it * 4] = u;
+                traj[(size_t)it * 4 + 1] = v;
+                traj[(size_t)it * 4 + 2] = c;
+                traj[(size_t)it * 4 + 3] = Cbest;
+            }
+        }
+        HIP_TRY(hipStreamSynchronize(hs));
+        gbest = std::min(gbest, Cbest);
+        tot += ev;
+        if (res->best_makespan) res->best_makespan[b] = Cbest;
+        if (res->iterations_done) res->iterations_done[b] = it;
+        if (res->evaluations) res->evaluations[b] = ev;
+        if (res->best_order) std::copy(Wb.begin(), Wb.end(), res->best_order + (size_t)b * N);
+    }
+    res->global_best = gbest;
+    res->total_evaluations = tot;
+    res->overflow_decodes = 0;
+    res->total_work = 0;
+    return RCPSP_OK;
+}
+
 extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_params *params,
                                       int32_t trial_iterations, void *hip_stream, rcpsp_search_params *out,
                                       rcpsp_tuning *info) {

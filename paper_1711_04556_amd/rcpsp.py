@@ -141,6 +141,9 @@ def lib():
     L.rcpsp_search_get_config.restype = ctypes.c_int
     L.rcpsp_tabu_search.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), ctypes.POINTER(rcpsp_search_result), vp]
     L.rcpsp_tabu_search.restype = ctypes.c_int
+    L.rcpsp_tabu_search_hosted.argtypes = [vp, ctypes.POINTER(rcpsp_search_params),
+                                           ctypes.POINTER(rcpsp_search_result), vp]
+    L.rcpsp_tabu_search_hosted.restype = ctypes.c_int
     L.rcpsp_autotune.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), i32, vp, ctypes.POINTER(rcpsp_search_params),
                                  ctypes.POINTER(rcpsp_tuning)]
     L.rcpsp_autotune.restype = ctypes.c_int
@@ -511,6 +514,13 @@ def tabu_search(instance: Instance, stream=None, **kw) -> dict:
         return plan.results(stream)
     finally:
         plan.close()
+
+
+def tabu_search_hosted(instance: Instance, stream=None, **kw) -> dict:
+    """rcpsp_tabu_search_hosted: the same independent searches driven by the
+    host, one device neighbourhood evaluation per iteration."""
+    p = search_params(**kw)
+    return _results(lib().rcpsp_tabu_search_hosted, (instance.h, ctypes.byref(p)), p, instance.n, stream)
 
 
 def version() -> str:

@@ -468,3 +468,29 @@ def test_finish_time_width_and_three_waves(rc, threads, profile_len, bits):
     plan.close()
     o = orc.tabu_search(12, 60, 30, searches=9, elite=4, phi_max=2, phi_steps=5, decoder=TIME, seed=12)
     _compare_search(g, o, elite=4)
+
+
+@pytest.mark.parametrize("dec", [TIME, CAP])
+def test_host_driven_search_matches_homogeneous(rc, dec):
+    """Heterogeneous model: the host runs the loop and the device evaluates
+    each neighbourhood; trajectories equal the in-kernel search's and the
+    oracle's, including a search that stops at the critical path."""
+    for n, rs, seed, iters in ((40, 0.3, 66, 25), (20, 0.9, 67, 30)):
+        inst = synth.generate(n, 4, 10, 0.5, rs=rs, seed=seed)
+        gi = rc.Instance(inst, eval=dec)
+        kw = dict(swap_range=10, tabu_len=40, iterations=iters, searches=3, seed=8)
+        h = rc.tabu_search_hosted(gi, **kw)
+        g = rc.tabu_search(gi, **kw)
+        o = oracle.Oracle(inst).tabu_search(10, 40, iters, searches=3, decoder=dec, seed=8)
+        _compare_search(h, o)
+        _compare_search(g, o)
+        assert h["global_best"] == g["global_best"] and h["total_evaluations"] == g["total_evaluations"]
+
+
+def test_host_driven_search_arguments(rc):
+    inst = synth.generate(20, 4, 10, 0.5, rs=0.3, seed=68)
+    gi = rc.Instance(inst, eval=TIME)
+    for bad in (dict(elite=2), dict(count_work=True), dict(eval=CAP)):
+        with pytest.raises(rc.RcpspError) as e:
+            rc.tabu_search_hosted(gi, **dict(dict(swap_range=6, tabu_len=20, iterations=5, searches=2, seed=1), **bad))
+        assert e.value.status == -1
