@@ -218,6 +218,39 @@ def hosted_leg(rcpsp, gi, dec, stream):
     return out
 
 
+def convergence_leg(rcpsp, gi, dec, stream, seeds, searches=(1, 4, 16, 64, 256, 480)):
+    """Best makespan against iterations for different numbers of cooperating
+    searches (working set 16) on the plain workload's instance, each point the
+    mean over `seeds` seeded runs of 1000 iterations; 480 independent
+    searches (no working set) as the reference without cooperation.  The
+    best at iteration i is the minimum over the searches of their best after
+    i + 1 iterations."""
+    import numpy as np
+    checkpoints = (0, 9, 49, 99, 249, 499, 999)
+    rows = []
+    t0 = time.perf_counter()
+    for B, elite in [(b, 16) for b in searches] + [(480, 0)]:
+        curves = []
+        for k in range(seeds):
+            kw = dict(WORKLOAD, searches=B, elite=elite, eval=dec, seed=1000 + k)
+            plan = rcpsp.SearchPlan(gi, rcpsp.search_params(record_trajectory=True, **kw), stream)
+            plan.run(stream)
+            r = plan.results(stream, orders=False)
+            plan.close()
+            traj = np.asarray(r["trajectory"])[:, :, 3].astype(np.int64)   # best per search per iteration
+            # iterations not run (a search stopped early) keep the last best
+            best = np.where(traj < 0, np.iinfo(np.int32).max, traj)
+            best = np.minimum.accumulate(best, axis=1).min(axis=0)
+            curves.append(best)
+        c = np.mean(np.asarray(curves, dtype=np.float64), axis=0)
+        rows.append(dict(searches=B, working_set=elite,
+                         mean_best={str(i + 1): round(float(c[i]), 2) for i in checkpoints}))
+        log("convergence", rows[-1], f"{time.perf_counter() - t0:.0f} s")
+    return dict(workload="plain workload's instance, 1000 iterations, cooperative searches with working set 16 "
+                         f"and 480 independent searches; mean over {seeds} seeds (1000..{999 + seeds})",
+                rows=rows)
+
+
 def large_leg(rcpsp, synth, stream, steps):
     import torch
     t0 = time.perf_counter()
@@ -394,6 +427,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-large", action="store_true", help="skip the large-instance leg")
     ap.add_argument("--no-hosted", action="store_true", help="skip the heterogeneous-model leg")
+    ap.add_argument("--convergence", type=int, default=0, metavar="SEEDS",
+                    help="also run the convergence study with this many seeds per point (off by default)")
     ap.add_argument("--serve-rate", type=float, default=SERVE["rate"])
     ap.add_argument("--serve-seconds", type=float, default=SERVE["measure_s"])
     args = ap.parse_args()
@@ -531,6 +566,8 @@ def main():
     plan.close()
     if not args.no_hosted:
         out["hosted"] = hosted_leg(rcpsp, gi, gi.info["eval"], stream)
+    if args.convergence > 0:
+        out["convergence"] = convergence_leg(rcpsp, gi, gi.info["eval"], stream, args.convergence)
     if not args.no_batch:
         out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, min(args.warmup, 1))
     if not args.no_large:
