@@ -70,6 +70,8 @@ def lib():
         L.orc_decay_table.argtypes = [u32p, ctypes.c_int]
         L.orc_iterations_assigned.argtypes = [ctypes.c_int] * 4
         L.orc_tabu_search.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_fbi.argtypes = [ctypes.c_void_p, ctypes.c_int, i32p]
+        L.orc_fbi.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -86,7 +88,7 @@ class OrcParams(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_int), ("tabu_len", ctypes.c_int), ("iterations", ctypes.c_int),
                 ("searches", ctypes.c_int), ("elite", ctypes.c_int), ("phi_max", ctypes.c_int),
                 ("phi_steps", ctypes.c_int), ("decoder", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("i_block", ctypes.c_int)]
+                ("i_block", ctypes.c_int), ("fbi", ctypes.c_int)]
 
 
 class OrcResults(ctypes.Structure):
@@ -168,6 +170,12 @@ class Oracle:
                                          aspiration, _p(mk), _p(best))
         return mk[:P], best.tolist()
 
+    def fbi(self, order: Sequence[int], decoder: int = TIME):
+        """Forward-backward improvement of an activity list: (improved list, makespan)."""
+        o = _i32(order).copy()
+        c = lib().orc_fbi(self.h, decoder, _p(o))
+        return o.tolist(), c
+
     def initial_order(self, seed: int, stream: int) -> List[int]:
         out = np.zeros(self.n, dtype=np.int32)
         lib().orc_initial_order(self.h, seed, stream, _p(out))
@@ -175,16 +183,18 @@ class Oracle:
 
     def tabu_search(self, delta: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                     phi_max: int = 3, phi_steps: int = 20, decoder: int = TIME, seed: int = 1,
-                    trajectory: bool = True, i_block: int = 0) -> dict:
+                    trajectory: bool = True, i_block: int = 0, fbi: bool = False) -> dict:
         """i_block: eq. 8's iteration allowance when it differs from the
-        iterations run (a search cut short by a time budget); 0 = iterations."""
+        iterations run (a search cut short by a time budget); 0 = iterations.
+        fbi: forward-backward improvement of every second initial solution."""
         B, N = searches, self.n
         out = dict(best_makespan=np.zeros(B, np.int32), best_order=np.zeros((B, N), np.int32),
                    iterations_done=np.zeros(B, np.int32), evaluations=np.zeros(B, np.int64),
                    trajectory=np.zeros((B, iterations, 4), np.int32) if trajectory else None,
                    elite_makespan=np.zeros(max(elite, 1), np.int32),
                    elite_order=np.zeros((max(elite, 1), N), np.int32))
-        prm = OrcParams(delta, tabu_len, iterations, searches, elite, phi_max, phi_steps, decoder, seed, i_block)
+        prm = OrcParams(delta, tabu_len, iterations, searches, elite, phi_max, phi_steps, decoder, seed, i_block,
+                        int(fbi))
         res = OrcResults(*[out[k].ctypes.data if out[k] is not None else None for k in
                            ("best_makespan", "best_order", "iterations_done", "evaluations", "trajectory",
                             "elite_makespan", "elite_order")])

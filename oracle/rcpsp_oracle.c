@@ -434,6 +434,74 @@ typedef struct {
     int IC, reads;
 } record_t;
 
+/* Forward-backward improvement (the improvement the paper applies to every
+ * second initial solution, defined there only by citation of Li and Willis;
+ * also known as double justification).  Reading taken:
+ *   - backward pass: the serial SGS on the instance with every arc reversed,
+ *     over the activities in decreasing order of their finish times (ties:
+ *     the later list position first, which keeps successors first); its
+ *     finish times g are times measured back from the end, so the activities
+ *     sorted by decreasing g (ties: the later backward-list position first)
+ *     are in increasing order of their right-justified start times;
+ *   - forward pass: the serial SGS over that list;
+ *   - repeat while the forward makespan strictly decreases; the last list
+ *     that decreased it is the result;
+ *   - both passes use the search's decoder.
+ * Returns the makespan of the resulting order (written to `order`). */
+static orc_inst *reversed_instance(const orc_inst *I) {
+    int n = I->n, ne = I->succ_off[n];
+    int *off = (int *)calloc(n + 1, sizeof(int));
+    int *lst = (int *)malloc(sizeof(int) * (ne > 0 ? ne : 1));
+    for (int j = 0; j < n; j++) {
+        off[j + 1] = off[j];
+        for (int e = I->pred_off[j]; e < I->pred_off[j + 1]; e++) lst[off[j + 1]++] = I->pred[e];
+    }
+    orc_inst *R = orc_create(n, I->m, I->d, I->R, I->r, off, lst);
+    free(off); free(lst);
+    return R;
+}
+
+static _Thread_local const int *g_sort_key, *g_sort_pos;
+static int by_key_desc(const void *x, const void *y) {
+    int a = *(const int *)x, b = *(const int *)y;
+    if (g_sort_key[a] != g_sort_key[b]) return g_sort_key[a] > g_sort_key[b] ? -1 : 1;
+    return g_sort_pos[a] > g_sort_pos[b] ? -1 : 1;
+}
+
+/* the activities by decreasing key, ties by decreasing position in `order` */
+static void sort_desc(int n, const int *key, const int *order, int *out) {
+    int *pos = (int *)malloc(sizeof(int) * n);
+    for (int p = 0; p < n; p++) pos[order[p]] = p;
+    for (int a = 0; a < n; a++) out[a] = a;
+    g_sort_key = key; g_sort_pos = pos;
+    qsort(out, n, sizeof(int), by_key_desc);
+    free(pos);
+}
+
+int orc_fbi(const orc_inst *I, int decoder, int *order) {
+    int n = I->n;
+    orc_inst *R = reversed_instance(I);
+    int *s = (int *)malloc(sizeof(int) * n), *f = (int *)malloc(sizeof(int) * n);
+    int *g = (int *)malloc(sizeof(int) * n), *B = (int *)malloc(sizeof(int) * n);
+    int *Wn = (int *)malloc(sizeof(int) * n);
+    int C = orc_decode(I, decoder, order, s);
+    for (int a = 0; a < n; a++) f[a] = s[a] + I->d[a];
+    for (;;) {
+        sort_desc(n, f, order, B);
+        orc_decode(R, decoder, B, s);
+        for (int a = 0; a < n; a++) g[a] = s[a] + I->d[a];
+        sort_desc(n, g, B, Wn);
+        int C2 = orc_decode(I, decoder, Wn, s);
+        if (C2 >= C) break;
+        C = C2;
+        memcpy(order, Wn, sizeof(int) * n);
+        for (int a = 0; a < n; a++) f[a] = s[a] + I->d[a];
+    }
+    free(s); free(f); free(g); free(B); free(Wn);
+    orc_free(R);
+    return C;
+}
+
 #define STREAM_INIT 0ULL
 #define STREAM_DIVERSIFY (1ULL << 32)
 
@@ -536,6 +604,7 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
         F[k].ring_v = (int *)calloc(TL, sizeof(int));
         F[k].tc = (uint8_t *)calloc((size_t)n * n, 1);
         orc_initial_order(I, p->seed, STREAM_INIT + (uint64_t)k, F[k].W);
+        if (p->fbi && (k & 1)) orc_fbi(I, p->decoder, F[k].W);
         F[k].C = orc_decode(I, p->decoder, F[k].W, NULL);
     }
     if (res->trajectory)
@@ -544,6 +613,7 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
     if (NF == 0) {
         for (int b = 0; b < B; b++) {
             orc_initial_order(I, p->seed, STREAM_INIT + (uint64_t)b, S[b].W_cur);
+            if (p->fbi && (b & 1)) orc_fbi(I, p->decoder, S[b].W_cur);
             S[b].C_cur = orc_decode(I, p->decoder, S[b].W_cur, NULL);
             S[b].C_best = S[b].C_cur;
             memcpy(S[b].W_best, S[b].W_cur, sizeof(int) * n);

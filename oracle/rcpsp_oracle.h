@@ -104,6 +104,8 @@ typedef struct {
     uint64_t seed;
     int i_block;      /* I_block of eq. 8 when the search is cut short (a time
                          budget) before its iteration allowance; 0 = iterations */
+    int fbi;          /* 1 = forward-backward improvement of every second
+                         initial solution (odd stream index) */
 } orc_params;
 
 typedef struct {
@@ -115,6 +117,10 @@ typedef struct {
     int *elite_makespan;     /* [elite] or NULL */
     int *elite_order;        /* [elite*N] or NULL */
 } orc_results;
+
+/* Forward-backward improvement of an activity list with the given decoder
+ * (in place); returns the makespan of the result.  Reading in the source. */
+int orc_fbi(const orc_inst *inst, int decoder, int *order);
 
 /* Tabu search (Sections 3, 4, 6; working set of Section 6.1).  Returns 0. */
 int orc_tabu_search(const orc_inst *inst, const orc_params *p, orc_results *res);
