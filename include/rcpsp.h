@@ -160,6 +160,16 @@ typedef struct {
                                  fit), 1, or 16 (time-indexed only: 16 lanes
                                  test 16 time units per step); same results */
     uint64_t seed;            /* seeds the initial orders and diversification */
+    int32_t fbi;              /* 1 = forward-backward improvement of every second
+                                 initial solution (odd search index, or odd
+                                 working-set record index): backward serial
+                                 SGS on the reversed project over activities by
+                                 decreasing finish time, forward serial SGS by
+                                 decreasing backward finish (ties: later list
+                                 position first), repeated while the makespan
+                                 strictly decreases, with the search's decoder.
+                                 Search plans only (batches and servers reject
+                                 it).  0 = off */
 } rcpsp_search_params;
 
 /* Results; every pointer may be NULL (not copied).  Sizes in parentheses. */

@@ -656,6 +656,7 @@ static hipError_t enqueue_run(rcpsp_search *s, hipStream_t st, RunTimer *tm) {
     };
     int nit = 0, nrd = 0;
     if ((e = launch_reset(a, st)) != hipSuccess) return e;
+    if (p.fbi && (e = launch_fbi(a, T, s->nw, s->dec, s->lds, st)) != hipSuccess) return e;
     if (NF > 0) {
         if ((e = launch_decode_records(a, T, s->nw, s->dec, s->lds, st)) != hipSuccess) return e;
         if ((e = round(0, 1)) != hipSuccess) return e;
@@ -1200,6 +1201,7 @@ rcpsp_status rcpsp::validate_params(const rcpsp_search_params &p) {
     if (p.elite < 0) return fail(RCPSP_E_ARG, "elite must be >= 0");
     if (p.phi_max < 0 || p.phi_steps < 0) return fail(RCPSP_E_ARG, "phi_max and phi_steps must be >= 0");
     if (p.eval < 0 || p.eval > 2) return fail(RCPSP_E_ARG, "unknown decoder %d", p.eval);
+    if (p.fbi != 0 && p.fbi != 1) return fail(RCPSP_E_ARG, "fbi must be 0 or 1");
     return RCPSP_OK;
 }
 
@@ -1214,6 +1216,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         rcpsp_search_params p = params[i];
         rcpsp_status st = validate_params(p);
         if (st != RCPSP_OK) return st;
+        if (p.fbi) return fail(RCPSP_E_ARG, "batch member %d: forward-backward improvement is for search plans only", i);
         if (p.threads == 0) p.threads = 64;
         p.count_work = 0;
         // the threads per search (chosen per group by the autotuner) are a

@@ -1232,6 +1232,102 @@ __device__ inline int decode_order(const Sh &S, const InstDesc &D, const Layout 
     }
 }
 
+// Activities in decreasing order of key (16-bit, by activity), ties by
+// decreasing position in S.W, written to out[]: each thread ranks its
+// activities by counting those ordered before them (keys and positions make
+// the order strict).
+template <int T>
+__device__ inline void sort_desc(const Sh &S, const InstDesc &D, const uint16_t *key, uint16_t *out) {
+    const int N = D.n;
+    for (int p = threadIdx.x; p < N; p += T) S.pos[S.W[p]] = (uint16_t)p;
+    __syncthreads();
+    for (int a = threadIdx.x; a < N; a += T) {
+        const int ka = key[a], pa = S.pos[a];
+        int rank = 0;
+        for (int b = 0; b < N; ++b) {
+            const int kb = key[b], pb = S.pos[b];
+            rank += (kb > ka) || (kb == ka && pb > pa);
+        }
+        out[rank] = (uint16_t)a;
+    }
+    __syncthreads();
+}
+
+// Forward-backward improvement of the activity list in S.W (in place): the
+// backward pass is the serial SGS on the project with every arc reversed
+// (successor lists taken as predecessor lists) over the activities by
+// decreasing finish time; its finish times are measured back from the end,
+// so the activities by decreasing backward finish are in increasing order of
+// their right-justified starts, and the forward pass is the serial SGS over
+// that list.  Ties: the later list position first (which keeps every list
+// precedence-feasible for its pass).  Repeated while the forward makespan
+// strictly decreases; the last list that decreased it stays.  Both passes use
+// the search's decoder, decoding whole lists over the decode region (finish
+// times as 16-bit values at its start).
+template <int NW, int T, int DEC>
+__device__ void fbi_order(const Sh &S, const InstDesc &D, const Layout &Ly, int *shc) {
+    Sh R = S;
+    R.pred = S.succ;
+    R.predoff = S.succoff;
+    const int N = D.n, N2h = n2(N) / 2;
+    const uint16_t *fin = reinterpret_cast<const uint16_t *>(S.region);
+    uint32_t *Wd = reinterpret_cast<uint32_t *>(S.W);
+    uint32_t *Wk = reinterpret_cast<uint32_t *>(S.Wimp);   // the best list so far
+    build_records<T>(S, D);
+    __syncthreads();
+    int c = decode_order<NW, DEC>(S, D, Ly);
+    if (threadIdx.x == 0) shc[0] = c;
+    __syncthreads();
+    int C = shc[0];
+    for (int i = threadIdx.x; i < N2h; i += T) Wk[i] = Wd[i];
+    for (;;) {
+        __syncthreads();
+        // backward list: by decreasing finish time of the current schedule
+        sort_desc<T>(S, D, fin, S.fs);
+        for (int p = threadIdx.x; p < N; p += T) S.W[p] = S.fs[p];
+        __syncthreads();
+        build_records<T>(R, D);
+        __syncthreads();
+        decode_order<NW, DEC>(R, D, Ly);
+        __syncthreads();
+        // forward list: by decreasing backward finish time
+        sort_desc<T>(S, D, fin, S.fs);
+        for (int p = threadIdx.x; p < N; p += T) S.W[p] = S.fs[p];
+        __syncthreads();
+        build_records<T>(S, D);
+        __syncthreads();
+        c = decode_order<NW, DEC>(S, D, Ly);
+        if (threadIdx.x == 0) shc[0] = c;
+        __syncthreads();
+        const int c2 = shc[0];
+        if (c2 >= C) break;
+        C = c2;
+        for (int i = threadIdx.x; i < N2h; i += T) Wk[i] = Wd[i];
+    }
+    for (int i = threadIdx.x; i < N2h; i += T) Wd[i] = Wk[i];
+    __syncthreads();
+}
+
+// Forward-backward improvement of every second initial solution: workgroup
+// g takes unit 2g + 1 (a search's order without a working set, else a
+// working-set record), right after the reset kernel wrote it.
+template <int NW, int T, int DEC>
+__global__ __launch_bounds__(T) void k_fbi(SearchArgs A) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ int shc[1];
+    const InstDesc &D = A.D;
+    Sh S = make_sh(lds, D, A.Ly);
+    stage_blob<T>(lds, D, A.Ly);
+    const int i = 2 * blockIdx.x + 1, N2h = n2(D.n) / 2;
+    uint32_t *g = reinterpret_cast<uint32_t *>((A.NF > 0 ? A.Fw : A.Wcur) + (size_t)i * n2(D.n));
+    uint32_t *Wd = reinterpret_cast<uint32_t *>(S.W);
+    for (int x = threadIdx.x; x < N2h; x += T) Wd[x] = g[x];
+    __syncthreads();
+    fbi_order<NW, T, DEC>(S, D, A.Ly, shc);
+    for (int x = threadIdx.x; x < N2h; x += T) g[x] = Wd[x];
+    __threadfence();
+}
+
 // Makespan of initial working-set record k (buffer 0); the blob is staged.
 template <int NW, int T, int DEC>
 __device__ void decode_record(const SearchArgs &A, const Sh &S, int k) {
@@ -1962,6 +2058,8 @@ hipError_t prepare_search(int T, int nw, int dec, int G, size_t lds, int B, int 
     RCPSP_DISPATCH(nw, T, dec, G, {
         hipError_t e = set_lds(k_decode_records<NW_, T_, DEC_>, lds);
         if (e != hipSuccess) return e;
+        e = set_lds(k_fbi<NW_, T_, DEC_>, lds);
+        if (e != hipSuccess) return e;
         e = set_lds(k_search<NW_, T_, DEC_, G_, false>, lds);
         if (e != hipSuccess) return e;
         e = set_lds(k_search<NW_, T_, DEC_, G_, true>, lds);
@@ -1969,6 +2067,15 @@ hipError_t prepare_search(int T, int nw, int dec, int G, size_t lds, int B, int 
     });
     if (NF > 0) return set_lds(k_round, round_lds_bytes(B, NF));
     return hipSuccess;
+}
+
+hipError_t launch_fbi(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
+    const int units = A.NF > 0 ? A.NF : A.B;
+    if (units < 2) return hipSuccess;
+    RCPSP_DISPATCH(nw, T, dec, 1, {
+        hipLaunchKernelGGL((k_fbi<NW_, T_, DEC_>), dim3(units / 2), dim3(T_), lds, st, A);
+    });
+    return hipGetLastError();
 }
 
 hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {

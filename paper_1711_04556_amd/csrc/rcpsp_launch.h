@@ -20,6 +20,7 @@ struct EvalArgs {
 hipError_t launch_eval(const EvalArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
 hipError_t launch_reset(const SearchArgs &A, hipStream_t st);
 hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t launch_fbi(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st);
 hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
 hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t st);
 size_t round_lds_bytes(int B, int NF);

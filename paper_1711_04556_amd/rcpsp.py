@@ -44,7 +44,8 @@ class rcpsp_move(ctypes.Structure):
 class rcpsp_search_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
-        "profile_len", "record_trajectory", "count_work", "full_decode", "eval", "lanes")] + [("seed", ctypes.c_uint64)]
+        "profile_len", "record_trajectory", "count_work", "full_decode", "eval", "lanes")] + [("seed", ctypes.c_uint64),
+                                                                                              ("fbi", ctypes.c_int32)]
 
 
 class rcpsp_tuning(ctypes.Structure):
@@ -274,10 +275,10 @@ class Instance:
 def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                   phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
                   record_trajectory: bool = True, count_work: bool = False, full_decode: bool = False,
-                  eval: int = EVAL_AUTO, seed: int = 1, lanes: int = 0) -> rcpsp_search_params:
+                  eval: int = EVAL_AUTO, seed: int = 1, lanes: int = 0, fbi: bool = False) -> rcpsp_search_params:
     return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
                                profile_len, int(record_trajectory), int(count_work), int(full_decode), eval, lanes,
-                               seed)
+                               seed, int(fbi))
 
 
 def autotune(instance: "Instance", params: rcpsp_search_params, trial_iterations: int = 10, stream=None):

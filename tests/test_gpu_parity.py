@@ -494,3 +494,24 @@ def test_host_driven_search_arguments(rc):
         with pytest.raises(rc.RcpspError) as e:
             rc.tabu_search_hosted(gi, **dict(dict(swap_range=6, tabu_len=20, iterations=5, searches=2, seed=1), **bad))
         assert e.value.status == -1
+
+
+@pytest.mark.parametrize("dec", [TIME, CAP])
+def test_forward_backward_improvement_of_initial_solutions(rc, dec):
+    """Every second initial solution improved forward-backward before the
+    search starts: independent searches and working-set records, against the
+    oracle; the host-driven search takes the same initial orders."""
+    inst = synth.generate(40, 4, 10, 0.5, rs=0.25, seed=69)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=dec)
+    kw = dict(swap_range=10, tabu_len=40, iterations=12, seed=4)
+    g = rc.tabu_search(gi, searches=4, fbi=True, **kw)
+    o = orc.tabu_search(10, 40, 12, searches=4, decoder=dec, seed=4, fbi=True)
+    _compare_search(g, o)
+    h = rc.tabu_search_hosted(gi, searches=4, fbi=True, **kw)
+    _compare_search(h, o)
+    g = rc.tabu_search(gi, searches=6, elite=4, phi_max=2, phi_steps=4, fbi=True, **kw)
+    o = orc.tabu_search(10, 40, 12, searches=6, elite=4, phi_max=2, phi_steps=4, decoder=dec, seed=4, fbi=True)
+    _compare_search(g, o, elite=4)
+    # the improvement shortens at least one of these initial solutions
+    assert any(orc.fbi(orc.initial_order(4, b), dec)[1] < orc.decode(orc.initial_order(4, b), dec) for b in (1, 3))
