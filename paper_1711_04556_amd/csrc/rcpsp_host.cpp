@@ -801,6 +801,14 @@ static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     rcpsp_status st0 = alloc_plan(s);
     if (st0 != RCPSP_OK) return st0;
     HIP_TRY(prepare_search(s->T, s->nw, s->dec, s->G, s->lds, s->p.searches, s->p.elite));
+    {
+        // iteration-kernel workgroups: those that fit the GPU at once, at most one per search
+        int per_cu = 0, cus = 0, dev = 0;
+        HIP_TRY(search_occupancy(s->T, s->nw, s->dec, s->G, s->lds, &per_cu));
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        s->a.grid = per_cu > 0 ? std::min(s->p.searches, per_cu * cus) : s->p.searches;
+    }
     // capture the whole run as one graph
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

@@ -70,7 +70,8 @@ struct SlotMeta {
 struct Global {
     int Cstar;
     int gstop;
-    int pad[2];
+    int queue;     // next search of the current iteration launch (plain plans)
+    int pad;
 };
 
 constexpr uint64_t kStreamInit = 0ull;
@@ -82,6 +83,7 @@ struct SearchArgs {
     Layout Ly;
     int delta, tl, iters, B, NF, phi_max, phi_steps, tcw, L, record, count_work, full_decode;
     int it0, n_it;
+    int grid;      // iteration-kernel workgroups (each takes searches from A.g->queue)
     int decay_len;
     unsigned long long seed;
     SearchScalars *sc;

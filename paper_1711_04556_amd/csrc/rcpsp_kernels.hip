@@ -1203,6 +1203,7 @@ __device__ void reset_unit(const SearchArgs &A, int i, uint16_t *w) {
     if (i == 0 && tid == 0) {
         A.g->Cstar = 0x7fffffff;
         A.g->gstop = 0;
+        A.g->queue = 0;
     }
     __threadfence();
     __syncthreads();
@@ -1553,15 +1554,27 @@ __device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, in
     __syncthreads();
 }
 
-// One workgroup per search of a plan; iterations [it0, it0 + n_it).
+// Iterations [it0, it0 + n_it) of every search of a plan: as many
+// workgroups as fit the GPU at once, each taking searches from a queue
+// (A.g->queue, zeroed by the reset kernel and after every exchange round), so
+// no CU idles while searches remain and the slowest search of a fixed group
+// no longer sets the pace.  Each search's step reads and writes only its own
+// state, so results do not depend on which workgroup runs it.
 template <int NW, int T, int DEC, int G, bool COUNT>
 __global__ __launch_bounds__(T) void k_search(SearchArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ StepShared ss;
+    __shared__ int next;
     Sh S = make_sh(lds, A.D, A.Ly);
     stage_blob<T>(lds, A.D, A.Ly);
-    __syncthreads();
-    search_step<NW, T, DEC, G, COUNT>(A, S, ss, blockIdx.x, A.it0, A.n_it);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) next = atomicAdd(&A.g->queue, 1);
+        __syncthreads();
+        const int b = next;
+        if (b >= A.B) break;
+        search_step<NW, T, DEC, G, COUNT>(A, S, ss, b, A.it0, A.n_it);
+    }
 }
 
 // eq. 8, read as floor(I_block (4 E[a] + E[b]) / (25 * 2^24)) >= 1 with the
@@ -1679,6 +1692,7 @@ __device__ void exchange_round(const SearchArgs &A, int parity, int init, int *r
 __global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int init) {
     extern __shared__ int rs[];
     exchange_round<256>(A, parity, init, rs);
+    if (threadIdx.x == 0) A.g->queue = 0;   // the next iteration launch starts from search 0
 }
 
 // ---------------------------------------------------------------------------
@@ -2087,10 +2101,11 @@ hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, si
 
 hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st) {
     RCPSP_DISPATCH(nw, T, dec, G, {
+        const int grid = A.grid > 0 ? A.grid : A.B;
         if (A.count_work)
-            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, G_, true>), dim3(A.B), dim3(T_), lds, st, A);
+            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, G_, true>), dim3(grid), dim3(T_), lds, st, A);
         else
-            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, G_, false>), dim3(A.B), dim3(T_), lds, st, A);
+            hipLaunchKernelGGL((k_search<NW_, T_, DEC_, G_, false>), dim3(grid), dim3(T_), lds, st, A);
     });
     return hipGetLastError();
 }
@@ -2098,6 +2113,15 @@ hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, siz
 hipError_t prepare_batch(int T, int nw, int dec, int G, size_t lds) {
     RCPSP_DISPATCH(nw, T, dec, G, {
         hipError_t e = set_lds(k_batch<NW_, T_, DEC_, G_>, lds);
+        if (e != hipSuccess) return e;
+    });
+    return hipSuccess;
+}
+
+hipError_t search_occupancy(int T, int nw, int dec, int G, size_t lds, int *per_cu) {
+    *per_cu = 0;
+    RCPSP_DISPATCH(nw, T, dec, G, {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_search<NW_, T_, DEC_, G_, false>, T_, lds);
         if (e != hipSuccess) return e;
     });
     return hipSuccess;

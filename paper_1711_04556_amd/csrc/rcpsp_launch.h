@@ -21,6 +21,7 @@ hipError_t launch_eval(const EvalArgs &A, int T, int nw, int dec, int G, size_t 
 hipError_t launch_reset(const SearchArgs &A, hipStream_t st);
 hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st);
 hipError_t launch_fbi(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st);
+hipError_t search_occupancy(int T, int nw, int dec, int G, size_t lds, int *per_cu);
 hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
 hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t st);
 size_t round_lds_bytes(int B, int NF);
