@@ -875,17 +875,16 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
     const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
     long long w_ops = 0;
     int fr = front;
-    // a position's record and its first G predecessors (one per lane),
-    // loaded one position ahead (clamped to the last position)
-    auto qof = [&](int p) {
-        p = min(p, D.n - 1);
-        return (p == u) ? v : ((p == v) ? u : p);
-    };
-    int q = qof(p0);
-    uint4 r = rec[q];
-    int pid = (g < (int)(r.y >> 16)) ? (int)S.pred[r.z + g] : 0;
     for (int p = p0; p < p1; ++p) {
+        const int q = (p == u) ? v : ((p == v) ? u : p);
+        const uint4 r = rec[q];
         const int d = r.y & 0xffff, np = r.y >> 16, a = (int)r.w;
+        int es = 0;
+        for (int e0 = 0; e0 < np; e0 += G) {
+            const int e = e0 + g;
+            if (e < np) es = max(es, fget(S.pred[r.z + e]));
+        }
+        es = group_max<G>(es);
         uint32_t rq[NW];
         uint32_t any = 0;
 #pragma unroll
@@ -893,15 +892,6 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
             rq[w] = S.prq[q * NW + w];
             any |= rq[w];
         }
-        int es = g < np ? fget(pid) : 0;
-        for (int e0 = G; e0 < np; e0 += G) {
-            const int e = e0 + g;
-            if (e < np) es = max(es, fget(S.pred[r.z + e]));
-        }
-        es = group_max<G>(es);
-        const int qn = qof(p + 1);
-        const uint4 rn = rec[qn];
-        const int pidn = (g < (int)(rn.y >> 16)) ? (int)S.pred[rn.z + g] : 0;
         int s = es;
         if (any != 0 && d > 0) {
             int t = es, c = 0;  // c: free units just before t
@@ -932,22 +922,15 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
                 return -1;
             }
             if (COUNT && g == 0) w_ops += (s + d - es) + d;
-            // Alg. 6 (and the full capacity for never-written units below s):
-            // stores and atomic subtractions, no value to wait for
             const int lo = min(s, fr), hi = s + d;
             for (int x0 = lo; x0 < hi; x0 += G) {
                 const int x = x0 + g;
                 if (x < hi) {
                     uint32_t *P = prof + x * NW;
-                    if (x < s) {
 #pragma unroll
-                        for (int w = 0; w < NW; ++w) P[w] = FULL[w];
-                    } else if (x < fr) {
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) lds_sub(P + w, rq[w]);
-                    } else {
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) P[w] = FULL[w] - rq[w];
+                    for (int w = 0; w < NW; ++w) {
+                        const uint32_t A = (x < fr) ? P[w] : FULL[w];
+                        P[w] = (x < s) ? FULL[w] : A - rq[w];
                     }
                 }
             }
@@ -958,9 +941,6 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
         if (COUNT && g == 0) w_ops += 1 + np;
         if (g == 0) fset(a, s + d);
         __builtin_amdgcn_wave_barrier();
-        q = qn;
-        r = rn;
-        pid = pidn;
     }
     front = fr;
     if (COUNT && g == 0) *wk += w_ops;
