@@ -88,7 +88,8 @@ class OrcParams(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_int), ("tabu_len", ctypes.c_int), ("iterations", ctypes.c_int),
                 ("searches", ctypes.c_int), ("elite", ctypes.c_int), ("phi_max", ctypes.c_int),
                 ("phi_steps", ctypes.c_int), ("decoder", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("i_block", ctypes.c_int), ("fbi", ctypes.c_int)]
+                ("i_block", ctypes.c_int), ("fbi", ctypes.c_int),
+                ("decoder_of_iteration", ctypes.POINTER(ctypes.c_int32))]
 
 
 class OrcResults(ctypes.Structure):
@@ -183,18 +184,25 @@ class Oracle:
 
     def tabu_search(self, delta: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                     phi_max: int = 3, phi_steps: int = 20, decoder: int = TIME, seed: int = 1,
-                    trajectory: bool = True, i_block: int = 0, fbi: bool = False) -> dict:
+                    trajectory: bool = True, i_block: int = 0, fbi: bool = False,
+                    decoder_of_iteration: Optional[Sequence[int]] = None) -> dict:
         """i_block: eq. 8's iteration allowance when it differs from the
         iterations run (a search cut short by a time budget); 0 = iterations.
-        fbi: forward-backward improvement of every second initial solution."""
+        fbi: forward-backward improvement of every second initial solution.
+        decoder_of_iteration: per iteration, the decoder of its decodes
+        (periodic re-selection); set-up decodes keep `decoder`."""
         B, N = searches, self.n
         out = dict(best_makespan=np.zeros(B, np.int32), best_order=np.zeros((B, N), np.int32),
                    iterations_done=np.zeros(B, np.int32), evaluations=np.zeros(B, np.int64),
                    trajectory=np.zeros((B, iterations, 4), np.int32) if trajectory else None,
                    elite_makespan=np.zeros(max(elite, 1), np.int32),
                    elite_order=np.zeros((max(elite, 1), N), np.int32))
+        sched = None
+        if decoder_of_iteration is not None:
+            sched = _i32(list(decoder_of_iteration)).copy()
+            assert len(sched) == iterations and set(sched.tolist()) <= {TIME, CAPACITY}
         prm = OrcParams(delta, tabu_len, iterations, searches, elite, phi_max, phi_steps, decoder, seed, i_block,
-                        int(fbi))
+                        int(fbi), _p(sched) if sched is not None else None)
         res = OrcResults(*[out[k].ctypes.data if out[k] is not None else None for k in
                            ("best_makespan", "best_order", "iterations_done", "evaluations", "trajectory",
                             "elite_makespan", "elite_order")])

@@ -540,7 +540,8 @@ static int elite_min(const record_t *F, int nf) {
 }
 
 /* Read record k into search b (Section 6.1). */
-static void read_record(const orc_inst *I, const orc_params *p, int b, search_t *S, record_t *F, int k) {
+static void read_record(const orc_inst *I, const orc_params *p, int dec, int b, search_t *S, record_t *F,
+                        int k) {
     int n = I->n;
     record_t *R = &F[k];
     R->reads += 1;
@@ -550,7 +551,7 @@ static void read_record(const orc_inst *I, const orc_params *p, int b, search_t 
     S->C_read = R->C;
     if (R->reads > p->phi_max) {
         diversify(I, p, b, S);
-        S->C_cur = orc_decode(I, p->decoder, S->W_cur, NULL);
+        S->C_cur = orc_decode(I, dec, S->W_cur, NULL);
     }
     memcpy(S->W_imp, S->W_cur, sizeof(int) * n);
     S->C_imp = S->C_cur;
@@ -563,8 +564,8 @@ static void read_record(const orc_inst *I, const orc_params *p, int b, search_t 
 
 /* One exchange round: fired searches in ascending id write (if they improved
  * the record they read and beat its current content) then read the next
- * record. */
-static void exchange_round(const orc_inst *I, const orc_params *p, search_t *S, record_t *F) {
+ * record; a diversified read is decoded with `dec`. */
+static void exchange_round(const orc_inst *I, const orc_params *p, int dec, search_t *S, record_t *F) {
     int n = I->n;
     for (int b = 0; b < p->searches; b++) {
         search_t *s = &S[b];
@@ -580,7 +581,7 @@ static void exchange_round(const orc_inst *I, const orc_params *p, search_t *S, 
             R->IC = 0;
             R->reads = 0;
         }
-        read_record(I, p, b, s, F, (k + 1) % p->elite);
+        read_record(I, p, dec, b, s, F, (k + 1) % p->elite);
     }
 }
 
@@ -626,7 +627,7 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
             S[b].it_read = 0;
             S[b].C_imp = S[b].C_read = INT_MAX;
         }
-        exchange_round(I, p, S, F);
+        exchange_round(I, p, p->decoder, S, F);
     }
 
     int cp = I->cp;
@@ -634,6 +635,7 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
     int *mk = (int *)malloc(sizeof(int) * (P > 0 ? P : 1));
     int *w = (int *)malloc(sizeof(int) * n);
     for (int it = 0; it < IT && !gstop; it++) {
+        const int dec = p->decoder_of_iteration ? p->decoder_of_iteration[it] : p->decoder;
         int c_star = NF > 0 ? elite_min(F, NF) : INT_MAX;
         for (int b = 0; b < B; b++) {
             search_t *s = &S[b];
@@ -647,7 +649,7 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
                     if (!orc_move_feasible(I, s->W_cur, u, v)) continue;
                     memcpy(w, s->W_cur, sizeof(int) * n);
                     w[u] = s->W_cur[v]; w[v] = s->W_cur[u];
-                    int c = orc_decode(I, p->decoder, w, NULL);
+                    int c = orc_decode(I, dec, w, NULL);
                     nfeas++;
                     int adm = !orc_stl_check(s->tc, n, u, v) || c < asp;
                     if (adm && lex_less(c, u, v, bc, bu, bv)) { bc = c; bu = u; bv = v; }
@@ -674,7 +676,8 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
             }
         }
         if (NF > 0 && it < IT - 1) {
-            exchange_round(I, p, S, F);
+            /* the reads of this round are completed by iteration it + 1 */
+            exchange_round(I, p, p->decoder_of_iteration ? p->decoder_of_iteration[it + 1] : p->decoder, S, F);
             if (elite_min(F, NF) == cp) gstop = 1;
         }
     }

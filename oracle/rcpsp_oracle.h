@@ -106,6 +106,13 @@ typedef struct {
                          budget) before its iteration allowance; 0 = iterations */
     int fbi;          /* 1 = forward-backward improvement of every second
                          initial solution (odd stream index) */
+    const int *decoder_of_iteration;  /* [iterations] or NULL: the decoder of
+                         every decode of iteration it (its neighbourhood, and
+                         the diversification of a read that an exchange round
+                         gave it), the periodic re-selection of the
+                         experimental set-up (Section 7); set-up decodes
+                         (initial orders, records, the first reads) keep
+                         `decoder` */
 } orc_params;
 
 typedef struct {
