@@ -251,6 +251,42 @@ def convergence_leg(rcpsp, gi, dec, stream, seeds, searches=(1, 4, 16, 64, 256, 
                 rows=rows)
 
 
+def reselect_leg(rcpsp, gi, stream, period, probe, threads, profile_len, periods=2):
+    """Periodic decoder re-selection on the plain workload (480 searches,
+    working set 16), `periods` periods of `period` iterations, each starting
+    with `probe` timed iterations of both decoders: wall time against the
+    same iterations with each decoder fixed, and the segment log.  threads
+    and profile_len shape the time-indexed decoder (the capacity-indexed one
+    takes its automatic shape)."""
+    import torch
+    iters = period * periods
+    kw = dict(WORKLOAD, iterations=iters, record_trajectory=False, threads=threads, profile_len=profile_len)
+    t = {}
+    for name, dec in (("time", 1), ("capacity", 2)):
+        shape = {} if dec == 1 else dict(threads=0, profile_len=0)
+        plan = rcpsp.SearchPlan(gi, rcpsp.search_params(**dict(kw, eval=dec, **shape)), stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(stream)
+        torch.cuda.synchronize()
+        t[name] = time.perf_counter() - t0
+        r = plan.results(stream, orders=False)
+        t[name + "_best"] = r["global_best"]
+        plan.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, segs = rcpsp.tabu_search_reselect(gi, period, probe, stream, **kw)
+    torch.cuda.synchronize()
+    t_rs = time.perf_counter() - t0
+    out = dict(workload=f"plain workload, {iters} iterations, period {period}, probe {probe}",
+               reselect_ms=1e3 * t_rs, time_fixed_ms=1e3 * t["time"], capacity_fixed_ms=1e3 * t["capacity"],
+               best=dict(reselect=r["global_best"], time=t["time_best"], capacity=t["capacity_best"]),
+               segments=[dict(first=s["first_iteration"], n=s["iterations"], eval=s["eval"], probe=s["probe"],
+                              ms_per_iteration=round(s["ms_per_iteration"], 4)) for s in segs])
+    log("reselect", out)
+    return out
+
+
 def large_leg(rcpsp, synth, stream, steps):
     import torch
     t0 = time.perf_counter()
@@ -429,6 +465,8 @@ def main():
     ap.add_argument("--no-hosted", action="store_true", help="skip the heterogeneous-model leg")
     ap.add_argument("--convergence", type=int, default=0, metavar="SEEDS",
                     help="also run the convergence study with this many seeds per point (off by default)")
+    ap.add_argument("--reselect", type=int, default=0, metavar="PERIOD",
+                    help="also run periodic decoder re-selection with this period (two periods)")
     ap.add_argument("--serve-rate", type=float, default=SERVE["rate"])
     ap.add_argument("--serve-seconds", type=float, default=SERVE["measure_s"])
     args = ap.parse_args()
@@ -568,6 +606,10 @@ def main():
         out["hosted"] = hosted_leg(rcpsp, gi, gi.info["eval"], stream)
     if args.convergence > 0:
         out["convergence"] = convergence_leg(rcpsp, gi, gi.info["eval"], stream, args.convergence)
+    if args.reselect > 0:
+        ti = kw["eval"] == rcpsp.EVAL_TIME
+        out["reselect"] = reselect_leg(rcpsp, gi, stream, args.reselect, max(1, args.reselect // 100),
+                                       kw["threads"] if ti else 0, kw["profile_len"] if ti else 0)
     if not args.no_batch:
         out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, min(args.warmup, 1))
     if not args.no_large:

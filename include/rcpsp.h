@@ -234,6 +234,50 @@ rcpsp_status rcpsp_tabu_search(const rcpsp_instance *inst, const rcpsp_search_pa
 rcpsp_status rcpsp_tabu_search_hosted(const rcpsp_instance *inst, const rcpsp_search_params *params,
                                       rcpsp_search_result *res, void *hip_stream);
 
+/* Periodic decoder re-selection: the paper's sequential CPU version picks
+ * the faster decoder by timing both every 1000 iterations instead of the
+ * Section 5.4 rules (Section 7, experimental set-up).  The searches run on
+ * the device as for rcpsp_tabu_search; at the start of every period of
+ * `period` iterations each decoder whose lane layout fits runs `probe`
+ * iterations (time-indexed first), timed with HIP events around its
+ * iteration-kernel launches, and the faster one per iteration runs the rest
+ * of the period.  When only one decoder fits, it runs every period without
+ * probes.  The two decoders are different serial schedules (the
+ * time-indexed one back-fills), so the choice changes the search: every
+ * decode of iteration it (its neighbourhood, and with a working set the
+ * diversification of a read given by the exchange round before it) uses the
+ * decoder of the logged segment holding it; set-up decodes (initial orders,
+ * working-set records, forward-backward improvement, the first reads) use
+ * the instance's decoder.  With the log, the run is reproducible exactly
+ * (a search with that per-iteration decoder schedule).  Synchronous on
+ * hip_stream.
+ *   params   as for rcpsp_search_create, eval must be 0; threads and lanes
+ *            apply to the time-indexed decoder (the capacity-indexed one
+ *            takes its automatic shape where they name 192 threads or 16
+ *            lanes)
+ *   period   iterations per period, >= 2 * probe
+ *   probe    iterations each decoder runs at the start of a period, >= 1
+ *   res      as for rcpsp_search_results
+ *   log      [log_cap] segments in run order: first iteration, iterations,
+ *            decoder, probe (1) or chosen run (0), measured milliseconds per
+ *            iteration launch (per iteration with a working set, per launch
+ *            of all the segment's iterations without one, divided by its
+ *            iterations); may be NULL when log_cap is 0
+ *   n_log    out: segments run (also when more than log_cap)
+ * Errors: RCPSP_E_ARG for the parameters above; RCPSP_E_BUFFER when the
+ * log is too short (res and n_log are complete); errors of
+ * rcpsp_search_create. */
+typedef struct {
+    int32_t first_iteration, iterations;
+    int32_t eval;               /* RCPSP_EVAL_TIME or RCPSP_EVAL_CAPACITY */
+    int32_t probe;              /* 1 timing probe, 0 chosen decoder */
+    float ms_per_iteration;
+} rcpsp_decoder_segment;
+rcpsp_status rcpsp_tabu_search_reselect(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                        int32_t period, int32_t probe, rcpsp_search_result *res,
+                                        rcpsp_decoder_segment *log, int32_t log_cap, int32_t *n_log,
+                                        void *hip_stream);
+
 /* Kernel names and per-launch statistics of the last run of a search plan:
  * launches of the iteration kernel and the number of candidate decodes. */
 typedef struct {

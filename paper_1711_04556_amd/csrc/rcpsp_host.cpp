@@ -682,11 +682,11 @@ static hipError_t enqueue_run(rcpsp_search *s, hipStream_t st, RunTimer *tm) {
     return hipSuccess;
 }
 
-// Layout and device state of a plan (no launches).
-rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
+// Decoder, threads, lane layout and LDS of a plan (no allocation).
+static rcpsp_status shape_plan(rcpsp_search *s) {
     const rcpsp_instance *I = s->inst;
     const rcpsp_search_params &p = s->p;
-    const int N = I->n, N2 = n2(N), B = p.searches, NF = p.elite;
+    const int N = I->n, B = p.searches, NF = p.elite;
     s->dec = p.eval ? p.eval : I->eval;
     s->nw = I->desc.nw;
     if (s->dec == kEvalTime && s->nw == 0)
@@ -734,6 +734,28 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     s->lds = (size_t)s->Ly.total * 4;
     if (NF > 0 && round_lds_bytes(B, NF) > (size_t)kMaxLds)
         return fail(RCPSP_E_TOO_LARGE, "%d searches with a working set exceed the exchange kernel's LDS", B);
+    return RCPSP_OK;
+}
+
+// Iteration-kernel workgroups of a shaped plan: those that fit the GPU at
+// once, at most one per search.
+static rcpsp_status plan_grid(const rcpsp_search *s, int *grid) {
+    int per_cu = 0, cus = 0, dev = 0;
+    HIP_TRY(prepare_search(s->T, s->nw, s->dec, s->G, s->lds, s->p.searches, s->p.elite));
+    HIP_TRY(search_occupancy(s->T, s->nw, s->dec, s->G, s->lds, &per_cu));
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    *grid = per_cu > 0 ? std::min(s->p.searches, per_cu * cus) : s->p.searches;
+    return RCPSP_OK;
+}
+
+// Layout and device state of a plan (no launches).
+rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
+    const rcpsp_instance *I = s->inst;
+    const rcpsp_search_params &p = s->p;
+    const int N = I->n, N2 = n2(N), B = p.searches, NF = p.elite;
+    rcpsp_status st = shape_plan(s);
+    if (st != RCPSP_OK) return st;
 
     SearchArgs &a = s->a;
     a = SearchArgs{};
@@ -799,16 +821,8 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
 
 static rcpsp_status build_plan(rcpsp_search *s, hipStream_t user_stream) {
     rcpsp_status st0 = alloc_plan(s);
+    if (st0 == RCPSP_OK) st0 = plan_grid(s, &s->a.grid);
     if (st0 != RCPSP_OK) return st0;
-    HIP_TRY(prepare_search(s->T, s->nw, s->dec, s->G, s->lds, s->p.searches, s->p.elite));
-    {
-        // iteration-kernel workgroups: those that fit the GPU at once, at most one per search
-        int per_cu = 0, cus = 0, dev = 0;
-        HIP_TRY(search_occupancy(s->T, s->nw, s->dec, s->G, s->lds, &per_cu));
-        HIP_TRY(hipGetDevice(&dev));
-        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        s->a.grid = per_cu > 0 ? std::min(s->p.searches, per_cu * cus) : s->p.searches;
-    }
     // capture the whole run as one graph
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -838,14 +852,8 @@ extern "C" rcpsp_status rcpsp_search_create(const rcpsp_instance *inst, const rc
     if (!inst || !params || !out) return fail(RCPSP_E_ARG, "null pointer");
     *out = nullptr;
     const rcpsp_search_params &p = *params;
-    if (p.swap_range < 1 || p.swap_range > kMaxDelta)
-        return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", p.swap_range, kMaxDelta);
-    if (p.tabu_len < 1) return fail(RCPSP_E_ARG, "tabu_len must be >= 1");
-    if (p.iterations < 0) return fail(RCPSP_E_ARG, "iterations must be >= 0");
-    if (p.searches < 1) return fail(RCPSP_E_ARG, "searches must be >= 1");
-    if (p.elite < 0) return fail(RCPSP_E_ARG, "elite must be >= 0");
-    if (p.phi_max < 0 || p.phi_steps < 0) return fail(RCPSP_E_ARG, "phi_max and phi_steps must be >= 0");
-    if (p.eval < 0 || p.eval > 2) return fail(RCPSP_E_ARG, "unknown decoder %d", p.eval);
+    rcpsp_status st0 = validate_params(p);
+    if (st0 != RCPSP_OK) return st0;
     if ((long long)p.searches * std::max(p.iterations, 1) * 4 > (1ll << 40))
         return fail(RCPSP_E_TOO_LARGE, "trajectory too large");
     rcpsp_search *s = new (std::nothrow) rcpsp_search();
@@ -1079,6 +1087,184 @@ extern "C" rcpsp_status rcpsp_tabu_search_hosted(const rcpsp_instance *inst, con
     res->overflow_decodes = 0;
     res->total_work = 0;
     return RCPSP_OK;
+}
+
+// Periodic decoder re-selection (what the paper's sequential CPU version
+// does instead of the Section 5.4 rules, Section 7): the searches of one plan
+// run on the device as usual, and at the start of every period each decoder
+// that fits runs a few iterations, timed with HIP events around its
+// iteration launches; the faster one runs the rest of the period.  The two
+// decoders are different functions (the time-indexed serial schedule
+// back-fills, the capacity-indexed one does not), so the choice changes the
+// search: every decode of iteration it (its neighbourhood, a diversified
+// read that the preceding exchange round gave it) uses the decoder of the
+// segment holding it, and the log of segments is what a replay needs.  The
+// plan's device state is shared: each decoder has its own lane layout,
+// threads and grid over the same buffers in HBM.
+namespace {
+struct ReselectShape {
+    int dec, T, nw, G;
+    size_t lds;
+    SearchArgs a;
+};
+struct PlanGuard {
+    rcpsp_search *s = nullptr;
+    ~PlanGuard() { rcpsp_search_destroy(s); }
+};
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
+extern "C" rcpsp_status rcpsp_tabu_search_reselect(const rcpsp_instance *inst, const rcpsp_search_params *params,
+                                                   int32_t period, int32_t probe, rcpsp_search_result *res,
+                                                   rcpsp_decoder_segment *log, int32_t log_cap, int32_t *n_log,
+                                                   void *hip_stream) {
+    if (!inst || !params || !res || !n_log || (log_cap > 0 && !log)) return fail(RCPSP_E_ARG, "null pointer");
+    if (log_cap < 0) return fail(RCPSP_E_ARG, "log_cap must be >= 0");
+    if (probe < 1 || period < 2 * probe) return fail(RCPSP_E_ARG, "need probe >= 1 and period >= 2 * probe");
+    *n_log = 0;
+    const rcpsp_search_params &p = *params;
+    rcpsp_status st = validate_params(p);
+    if (st != RCPSP_OK) return st;
+    if (p.eval != 0) return fail(RCPSP_E_ARG, "the decoder is chosen by timing (eval must be 0)");
+    if ((long long)p.searches * std::max(p.iterations, 1) * 4 > (1ll << 40))
+        return fail(RCPSP_E_TOO_LARGE, "trajectory too large");
+    hipStream_t hs = (hipStream_t)hip_stream;
+    // the plan (state in HBM, set-up with the instance's decoder) ...
+    PlanGuard g;
+    g.s = new (std::nothrow) rcpsp_search();
+    if (!g.s) return fail(RCPSP_E_NOMEM, "out of host memory");
+    rcpsp_search *s = g.s;
+    s->inst = inst;
+    s->p = p;
+    if ((st = alloc_plan(s)) != RCPSP_OK || (st = plan_grid(s, &s->a.grid)) != RCPSP_OK) return st;
+    // ... and one shape per decoder over it; a decoder whose layout does not
+    // fit, or that the instance cannot use, takes no part
+    std::vector<ReselectShape> shapes;
+    for (int dec : {kEvalTime, kEvalCapacity}) {
+        ReselectShape sh{};
+        if (dec == s->dec) {
+            sh = ReselectShape{s->dec, s->T, s->nw, s->G, s->lds, s->a};
+        } else {
+            rcpsp_search alt;
+            alt.inst = inst;
+            alt.p = p;
+            alt.p.eval = dec;
+            // threads and lanes the other decoder does not support fall back to its automatic shape
+            if (dec == kEvalCapacity && (alt.p.threads == 192 || alt.p.lanes == 16)) {
+                alt.p.threads = 0;
+                alt.p.lanes = 0;
+            }
+            rcpsp_status sst = shape_plan(&alt);
+            if (sst == RCPSP_E_TOO_LARGE) continue;
+            if (sst != RCPSP_OK) return sst;
+            sh = ReselectShape{alt.dec, alt.T, alt.nw, alt.G, alt.lds, s->a};
+            sh.a.Ly = alt.Ly;
+            sh.a.L = alt.L;
+            if ((sst = plan_grid(&alt, &sh.a.grid)) != RCPSP_OK) return sst;
+        }
+        shapes.push_back(sh);
+    }
+    const ReselectShape *cur = nullptr;
+    for (const ReselectShape &sh : shapes)
+        if (sh.dec == s->dec) cur = &sh;
+    const int iters = p.iterations, NF = p.elite;
+    const SearchArgs &a0 = s->a;
+    EventPool pool;
+    size_t n_ev = 0;
+    auto mark = [&](hipStream_t stq) -> hipError_t {
+        if (n_ev == pool.ev.size()) {
+            hipEvent_t ev;
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return e;
+            pool.ev.push_back(ev);
+        }
+        return hipEventRecord(pool.ev[n_ev++], stq);
+    };
+    // iterations [it0, it0 + n) with one shape; returns the summed
+    // iteration-launch milliseconds
+    auto run = [&](const ReselectShape &sh, int it0, int n, double *ms) -> rcpsp_status {
+        n_ev = 0;
+        auto search = [&](int i0, int k) -> hipError_t {
+            SearchArgs ai = sh.a;
+            ai.it0 = i0;
+            ai.n_it = k;
+            // the queue of searches starts from zero (an exchange round
+            // clears it too, but not every launch follows one)
+            hipError_t e = launch_fill_zero(&a0.g->queue, 1, hs);
+            if (e != hipSuccess) return e;
+            if ((e = mark(hs)) != hipSuccess) return e;
+            if ((e = launch_search(ai, sh.T, sh.nw, sh.dec, sh.G, sh.lds, hs)) != hipSuccess) return e;
+            return mark(hs);
+        };
+        if (n == 0) {
+            // no iteration: the launch only decodes the initial orders
+            HIP_TRY(search(it0, 0));
+        } else if (NF > 0) {
+            for (int it = it0; it < it0 + n; ++it) {
+                HIP_TRY(search(it, 1));
+                if (it < iters - 1) HIP_TRY(launch_round(a0, it & 1, 0, hs));
+            }
+        } else {
+            HIP_TRY(search(it0, n));
+        }
+        HIP_TRY(hipStreamSynchronize(hs));
+        double t = 0.0;
+        for (size_t i = 0; i + 1 < n_ev; i += 2) {
+            float f = 0.f;
+            HIP_TRY(hipEventElapsedTime(&f, pool.ev[i], pool.ev[i + 1]));
+            t += f;
+        }
+        *ms = t;
+        return RCPSP_OK;
+    };
+    int32_t nl = 0;
+    auto note = [&](int first, int n, int dec, int is_probe, double ms) {
+        if (nl < log_cap) log[nl] = rcpsp_decoder_segment{first, n, dec, is_probe, (float)(ms / n)};
+        ++nl;
+    };
+    HIP_TRY(launch_reset(a0, hs));
+    if (p.fbi) HIP_TRY(launch_fbi(a0, cur->T, cur->nw, cur->dec, cur->lds, hs));
+    if (NF > 0) {
+        HIP_TRY(launch_decode_records(a0, cur->T, cur->nw, cur->dec, cur->lds, hs));
+        HIP_TRY(launch_round(a0, 0, 1, hs));
+    }
+    // a launch of no iteration decodes the initial orders (and completes the
+    // first reads) with the instance's decoder
+    double ms = 0.0;
+    if ((st = run(*cur, 0, 0, &ms)) != RCPSP_OK) return st;
+    for (int it = 0; it < iters;) {
+        const int end = std::min(iters, it + period);
+        if (shapes.size() > 1) {
+            double best = 0.0;
+            for (const ReselectShape &sh : shapes) {
+                const int n = std::min(probe, end - it);
+                if (n <= 0) break;
+                if ((st = run(sh, it, n, &ms)) != RCPSP_OK) return st;
+                note(it, n, sh.dec, 1, ms);
+                if (&sh == &shapes[0] || ms / n < best) {
+                    best = ms / n;
+                    cur = &sh;
+                }
+                it += n;
+            }
+        }
+        if (end > it) {
+            if ((st = run(*cur, it, end - it, &ms)) != RCPSP_OK) return st;
+            note(it, end - it, cur->dec, 0, ms);
+            it = end;
+        }
+    }
+    *n_log = nl;
+    s->iteration_launches = 0;
+    st = rcpsp_search_results(s, res, hip_stream);
+    if (st == RCPSP_OK && nl > log_cap)
+        return fail(RCPSP_E_BUFFER, "%d segments, log holds %d (results are complete)", nl, log_cap);
+    return st;
 }
 
 extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_params *params,

@@ -95,6 +95,11 @@ class rcpsp_server_stats(ctypes.Structure):
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
+class rcpsp_decoder_segment(ctypes.Structure):
+    _fields_ = [("first_iteration", ctypes.c_int32), ("iterations", ctypes.c_int32), ("eval", ctypes.c_int32),
+                ("probe", ctypes.c_int32), ("ms_per_iteration", ctypes.c_float)]
+
+
 class rcpsp_search_config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches", "lanes",
@@ -145,6 +150,10 @@ def lib():
     L.rcpsp_tabu_search_hosted.argtypes = [vp, ctypes.POINTER(rcpsp_search_params),
                                            ctypes.POINTER(rcpsp_search_result), vp]
     L.rcpsp_tabu_search_hosted.restype = ctypes.c_int
+    L.rcpsp_tabu_search_reselect.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), i32, i32,
+                                             ctypes.POINTER(rcpsp_search_result),
+                                             ctypes.POINTER(rcpsp_decoder_segment), i32, i32p, vp]
+    L.rcpsp_tabu_search_reselect.restype = ctypes.c_int
     L.rcpsp_autotune.argtypes = [vp, ctypes.POINTER(rcpsp_search_params), i32, vp, ctypes.POINTER(rcpsp_search_params),
                                  ctypes.POINTER(rcpsp_tuning)]
     L.rcpsp_autotune.restype = ctypes.c_int
@@ -522,6 +531,21 @@ def tabu_search_hosted(instance: Instance, stream=None, **kw) -> dict:
     host, one device neighbourhood evaluation per iteration."""
     p = search_params(**kw)
     return _results(lib().rcpsp_tabu_search_hosted, (instance.h, ctypes.byref(p)), p, instance.n, stream)
+
+
+def tabu_search_reselect(instance: Instance, period: int, probe: int, stream=None, **kw):
+    """rcpsp_tabu_search_reselect: the searches of rcpsp_tabu_search with the
+    decoder re-chosen by timing at the start of every period.  Returns
+    (results, segments), segments a list of dicts in run order."""
+    p = search_params(**kw)
+    cap = 3 * (p.iterations // max(period, 1) + 1)   # two probes and a chosen run per period
+    log = (rcpsp_decoder_segment * cap)()
+    n = ctypes.c_int32(0)
+    fn = lambda res: lib().rcpsp_tabu_search_reselect(instance.h, ctypes.byref(p), period, probe, res, log, cap,
+                                                      ctypes.byref(n), _stream_ptr(stream))
+    out = _results(fn, (), p, instance.n, stream, sync=False)
+    segs = [{k: getattr(log[i], k) for k, _ in rcpsp_decoder_segment._fields_} for i in range(n.value)]
+    return out, segs
 
 
 def version() -> str:
