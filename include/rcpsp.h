@@ -155,10 +155,13 @@ typedef struct {
                                  slots) does not fit; 1 time-indexed, 2 capacity-indexed.
                                  The resolved decoder is reported by
                                  rcpsp_search_get_config and decides results. */
-    int32_t lanes;            /* lanes per candidate decode: 0 = auto (1, or 16
-                                 when a per-lane time-indexed profile does not
-                                 fit), 1, or 16 (time-indexed only: 16 lanes
-                                 test 16 time units per step); same results */
+    int32_t lanes;            /* lanes per candidate decode: 0 = auto (1, or
+                                 16 time-indexed / 8 capacity-indexed when a
+                                 per-lane state does not fit), 1, 16
+                                 (time-indexed only: 16 lanes test 16 time
+                                 units per step) or 8 (capacity-indexed only:
+                                 a lane per resource, eq. 7 and Alg. 4 of the
+                                 resources side by side); same results */
     uint64_t seed;            /* seeds the initial orders and diversification */
     int32_t fbi;              /* 1 = forward-backward improvement of every second
                                  initial solution (odd search index, or odd

@@ -324,8 +324,8 @@ extern "C" void rcpsp_destroy_instance(rcpsp_instance *inst) {
 
 // G = 1: one candidate per lane, lane-interleaved state; G = 2 (time-indexed):
 // the same with 8-bit finish times (lane profiles of at most 255 units);
-// G = 16 (time-indexed): one candidate per 16 lanes, contiguous state per
-// candidate.
+// G = 16 (time-indexed) and G = 8 (capacity-indexed, a lane per resource):
+// one candidate per G lanes, contiguous state per candidate.
 static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, int L, int dec, int G = 1) {
     Layout Ly{};
     const int N2h = n2(D.n) / 2;
@@ -348,7 +348,7 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     Ly.predT = o; o += std::max(D.n_arcs, 1);
     // one candidate per lane, time-indexed: the lane offsets of the first
     // four predecessors' finish times per position (16-byte entries)
-    const bool group = dec == kEvalTime && G > 2;
+    const bool group = G > 2;
     o = (o + 3) & ~3;
     Ly.pin = 0;
     if (dec == kEvalTime && !group) {
@@ -363,7 +363,8 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     // copy ring
     // G = 2: one candidate per lane with 8-bit finish times
     const int Fl = (dec == kEvalTime && G == 2) ? (D.n + 3) / 4 : F0;
-    if (group) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
+    if (group && dec == kEvalTime) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
+    else if (group) Ly.per_lane = (F0 + (D.sum_r + 1) / 2 + (G * D.copy_p + 1) / 2 + 3) & ~3;   // a copy ring per lane
     else if (dec == kEvalTime) Ly.per_lane = Fl + (L + 4) * D.nw;
     else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
     Ly.cands = group ? T / G : T;
@@ -393,7 +394,7 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
     const InstDesc &D = I->desc;
     const int budget = kMaxLds - 1024;  // static shared variables
     if (dec == kEvalCapacity) {
-        Layout Ly = make_layout(D, T, tcw, tl, pmax, 0, dec, 1);
+        Layout Ly = make_layout(D, T, tcw, tl, pmax, 0, dec, G);
         if ((size_t)Ly.total * 4 > (size_t)budget)
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d)", Ly.total * 4, budget, T);
         *L_out = 0;
@@ -696,10 +697,13 @@ static rcpsp_status shape_plan(rcpsp_search *s) {
     const int T0 = p.threads ? p.threads : (B >= 256 ? 64 : (B >= 64 ? 128 : 256));
     if (T0 != 64 && T0 != 128 && T0 != 192 && T0 != 256)
         return fail(RCPSP_E_ARG, "threads must be 0, 64, 128, 192 or 256");
-    if (T0 == 192 && (s->dec != kEvalTime || p.lanes == 16))
+    if (T0 == 192 && (s->dec != kEvalTime || p.lanes > 1))
         return fail(RCPSP_E_ARG, "192 threads per search needs the time-indexed decoder with one candidate per lane");
-    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 16) return fail(RCPSP_E_ARG, "lanes must be 0, 1 or 16");
+    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 8 && p.lanes != 16)
+        return fail(RCPSP_E_ARG, "lanes must be 0, 1, 8 or 16");
     if (p.lanes == 16 && s->dec != kEvalTime) return fail(RCPSP_E_ARG, "16 lanes per candidate needs the time-indexed decoder");
+    if (p.lanes == 8 && s->dec != kEvalCapacity)
+        return fail(RCPSP_E_ARG, "8 lanes per candidate needs the capacity-indexed decoder");
     int T = T0;
     rcpsp_status st = RCPSP_E_TOO_LARGE;
     auto try_shape = [&](int G, int Lreq) {
@@ -714,20 +718,22 @@ static rcpsp_status shape_plan(rcpsp_search *s) {
     };
     // one candidate per lane unless requested otherwise (time-indexed: 8-bit
     // finish times when the lane profile stays within 255 units, else
-    // 16-bit); when no per-lane profile fits, one candidate per 16 lanes
-    if (p.lanes == 16) {
-        try_shape(16, p.profile_len);
+    // 16-bit); when no per-lane state fits, one candidate per 16 lanes
+    // (time-indexed) or per 8 lanes (capacity-indexed)
+    if (p.lanes > 1) {
+        try_shape(p.lanes, p.profile_len);
     } else if (s->dec == kEvalTime) {
         try_shape(2, p.profile_len);
         if (st == RCPSP_E_TOO_LARGE) try_shape(1, p.profile_len);
     } else {
         try_shape(1, p.profile_len);
     }
-    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0 && s->dec == kEvalTime) try_shape(16, p.profile_len);
+    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0) try_shape(s->dec == kEvalTime ? 16 : 8, p.profile_len);
     if (st == RCPSP_E_TOO_LARGE && p.eval == RCPSP_EVAL_AUTO && s->dec == kEvalTime) {
         // automatic choice: no time-indexed profile fits, take the capacity-indexed decoder
         s->dec = kEvalCapacity;
         try_shape(1, 0);
+        if (st == RCPSP_E_TOO_LARGE && p.lanes == 0) try_shape(8, 0);
     }
     if (st != RCPSP_OK) return st;
     s->T = T;
@@ -1159,6 +1165,7 @@ extern "C" rcpsp_status rcpsp_tabu_search_reselect(const rcpsp_instance *inst, c
                 alt.p.threads = 0;
                 alt.p.lanes = 0;
             }
+            if (dec == kEvalTime && alt.p.lanes == 8) alt.p.lanes = 0;
             rcpsp_status sst = shape_plan(&alt);
             if (sst == RCPSP_E_TOO_LARGE) continue;
             if (sst != RCPSP_OK) return sst;
@@ -1295,10 +1302,10 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
     int trials = 0;
     std::vector<int> lanes_c;
     if (params->lanes) lanes_c.push_back(params->lanes);
-    else lanes_c = {1, 16};
+    else lanes_c = {1, 8, 16};
     for (int ev : evals) {
       for (int G : lanes_c) {
-        if (G > 1 && ev != kEvalTime) continue;
+        if ((G == 16 && ev != kEvalTime) || (G == 8 && ev != kEvalCapacity)) continue;
         for (int T : threads) {
             if (T == 192 && (ev != kEvalTime || G != 1)) continue;
             std::vector<int> Ls;
@@ -1719,13 +1726,13 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         else threads = {64, 128, 192, 256};
         std::vector<int> lanes_c;
         if (p0.lanes) lanes_c.push_back(p0.lanes);
-        else lanes_c = {1, 16};
+        else lanes_c = {1, 8, 16};
         bool found = false;
         double best_rate = 0.0;
         int best_eval = 0, best_T = 0, best_G = 1;
         for (int ev : evals) {
           for (int G : lanes_c) {
-            if (G > 1 && ev != kEvalTime) continue;
+            if ((G == 16 && ev != kEvalTime) || (G == 8 && ev != kEvalCapacity)) continue;
             for (int T : threads) {
                 if (T == 192 && (ev != kEvalTime || G != 1)) continue;
                 for (auto &q : sp) {

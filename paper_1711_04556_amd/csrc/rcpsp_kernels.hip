@@ -947,38 +947,132 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
     return p1 == D.n ? fget(D.n - 1) : 0;
 }
 
+// Capacity-indexed decode with G lanes per candidate (G in {4, 8, 16}):
+// lane g owns resources g, g + G, ...  Eq. 7's lookups and Alg. 4's updates
+// of different resources are independent, so the group runs them side by
+// side and combines the lanes' starts (with the predecessors' finish times,
+// also split over the lanes) by a group maximum.  State at cb: 16-bit
+// finish times by activity (F0 dwords), the c_k arrays as in decode_ci,
+// then one copy ring of copy_p entries per lane.  Each lane's loops run to
+// completion before the group maximum, so the group is converged there.
+// With COUNT, lane 0 counts one operation per activity and per predecessor
+// read, every lane its own eq. 7 lookups and Alg. 4 loop steps (the sum over
+// the group equals decode_ci's count).
+template <int G, bool COUNT = false>
+__device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, int v, int p0, int p1,
+                         long long *wk) {
+    static_assert(G == 4 || G == 8 || G == 16, "lanes per candidate");
+    const int g = threadIdx.x & (G - 1);
+    const int Mr = D.m;
+    const int F0 = (D.n + 1) >> 1, Cd = (D.sum_r + 1) >> 1;
+    uint16_t *F = reinterpret_cast<uint16_t *>(cb);
+    uint16_t *Cc = reinterpret_cast<uint16_t *>(cb + F0);
+    uint16_t *ring = reinterpret_cast<uint16_t *>(cb + F0 + Cd) + g * D.copy_p;
+    const int pmask = D.copy_p - 1;
+    const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
+    long long w_ops = 0;
+    for (int p = p0; p < p1; ++p) {
+        const int q = (p == u) ? v : ((p == v) ? u : p);
+        const uint4 r = rec[q];
+        const int d = r.y & 0xffff, np = r.y >> 16, a = (int)r.w;
+        int s = 0;
+        for (int e = g; e < np; e += G) s = max(s, (int)F[S.pred[r.z + e]]);
+        for (int k = g; k < Mr; k += G) {
+            const int rk = S.reqk[a * Mr + k];
+            if (rk > 0) {
+                s = max(s, (int)Cc[(int)S.res[2 * k + 1] + (int)S.res[2 * k] - rk]);
+                if (COUNT) ++w_ops;
+            }
+        }
+        s = group_max<G>(s);
+        if (d > 0) {
+            for (int k = g; k < Mr; k += G) {
+                const int rk = S.reqk[a * Mr + k];
+                if (rk == 0) continue;
+                uint16_t *ck = Cc + (int)S.res[2 * k + 1];
+                const int Rk = (int)S.res[2 * k];
+                int effort = rk * d, ci = 0, newTime = s + d;
+                // leading entries >= s + d are left alone (see decode_ci)
+                int lo = 0, hi = Rk;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if ((int)ck[mid] < newTime) hi = mid;
+                    else lo = mid + 1;
+                }
+                int ri = lo;
+                if (COUNT) w_ops += lo;
+                while (effort > 0 && ri < Rk) {
+                    if (COUNT) ++w_ops;
+                    const int cv = ck[ri];
+                    if (cv < newTime) {
+                        if (ci >= rk) newTime = ring[(ci - rk) & pmask];
+                        const int td = newTime - max(cv, s);
+                        if (effort - td > 0) {
+                            effort -= td;
+                            ring[ci & pmask] = (uint16_t)cv;
+                            ++ci;
+                            ck[ri] = (uint16_t)newTime;
+                        } else {
+                            ck[ri] = (uint16_t)(max(cv, s) + effort);
+                            effort = 0;
+                        }
+                    }
+                    ++ri;
+                }
+            }
+        }
+        if (COUNT && g == 0) w_ops += 1 + np;
+        if (g == 0) F[a] = (uint16_t)(s + d);
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (COUNT) *wk += w_ops;
+    return p1 == D.n ? (int)F[D.n - 1] : 0;
+}
+
+// Group decode of either kind (time-indexed: decode_tg).
+template <int NW, int DEC, int G, bool COUNT = false>
+__device__ inline int decode_grp(const Sh &S, const InstDesc &D, uint32_t *cb, int L, int u, int v, int p0, int p1,
+                                 int &front, bool &ovf, long long *wk) {
+    if constexpr (DEC == kEvalCapacity) return decode_cg<G, COUNT>(S, D, cb, u, v, p0, p1, wk);
+    else return decode_tg<NW, G, COUNT>(S, D, cb, L, u, v, p0, p1, front, ovf, wk);
+}
+
 // Group version of evaluate_moves: T/G candidates per round, one per group
 // of G lanes.  The shared prefix is decoded by group 0 into the base area;
 // candidates that overflow their profile are decoded afterwards by group 0
 // over the whole candidate region (>= horizon units).
-template <int NW, int T, int G, bool COUNT = false>
+template <int NW, int T, int DEC, int G, bool COUNT = false>
 __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
                                                int L, int delta, TabuSrc tabu, int asp, int *out_mk,
                                                long long *ovf_total, long long *work_total = nullptr,
                                                bool share = true) {
     constexpr int C = T / G;
+    constexpr bool CAP = DEC == kEvalCapacity;
     const int tid = threadIdx.x, grp = tid / G, g = tid & (G - 1);
     unsigned long long best = ~0ull;
     long long lw = 0;
     int *ovf_n = S.scal;
     int *bstate = S.scal + 1;
     const bool use_base = share && !COUNT;
+    const int F0 = (D.n + 1) >> 1, Cd = (D.sum_r + 1) >> 1;
     if (tid == 0) {
         *ovf_n = 0;
         bstate[0] = 0;
         bstate[1] = 0;
         bstate[2] = 0;
     }
+    // capacity-indexed states start with every c_k entry at zero
+    if (CAP && use_base)
+        for (int i = tid; i < Cd; i += T) S.bst[F0 + i] = 0u;
     __syncthreads();
     uint32_t *cb = S.region + grp * Ly.per_lane;
-    const int F0 = (D.n + 1) >> 1;
     for (int j0 = 0; j0 < nfeas; j0 += C) {
         if (use_base) {
             const int ulo = S.moves[j0] & 0xffff;
             if (grp == 0 && !bstate[2] && bstate[0] < ulo) {
                 bool bovf = false;
                 int bf = bstate[1];
-                decode_tg<NW, G, false>(S, D, S.bst, L, 0, 0, bstate[0], ulo, bf, bovf, nullptr);
+                decode_grp<NW, DEC, G, false>(S, D, S.bst, L, 0, 0, bstate[0], ulo, bf, bovf, nullptr);
                 if (g == 0) {
                     bstate[0] = ulo;
                     bstate[1] = bf;
@@ -995,18 +1089,22 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
             if (use_base && !bstate[2]) {
                 p0 = bstate[0];
                 front = bstate[1];
-                const int nd = F0 + front * NW;
+                const int nd = F0 + (CAP ? Cd : front * NW);
                 const uint4 *src = reinterpret_cast<const uint4 *>(S.bst);
                 uint4 *dst = reinterpret_cast<uint4 *>(cb);
                 for (int i = g; i < (nd >> 2); i += G) dst[i] = src[i];
                 for (int i = (nd & ~3) + g; i < nd; i += G) cb[i] = S.bst[i];
                 __builtin_amdgcn_wave_barrier();
+            } else if (CAP) {
+                for (int i = g; i < Cd; i += G) cb[F0 + i] = 0u;
+                __builtin_amdgcn_wave_barrier();
             }
             bool ovf = false;
             long long cw = 0;
-            const int c = decode_tg<NW, G, COUNT>(S, D, cb, L, u, v, p0, D.n, front, ovf, &cw);
+            const int c = decode_grp<NW, DEC, G, COUNT>(S, D, cb, L, u, v, p0, D.n, front, ovf, &cw);
+            // every lane adds its own count (a time-indexed group counts on lane 0 only)
+            if (COUNT && !ovf) lw += cw;
             if (g == 0) {
-                if (COUNT && !ovf) lw += cw;
                 if (ovf) {
                     S.moves[j] = mv | 0x80000000u;
                     atomicAdd(ovf_n, 1);
@@ -1020,7 +1118,8 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
         if (use_base) __syncthreads();
     }
     __syncthreads();
-    if (*ovf_n > 0) {
+    // capacity-indexed states have no horizon and never overflow
+    if (!CAP && *ovf_n > 0) {
         if (grp == 0) {
             for (int j = 0; j < nfeas; ++j) {
                 const uint32_t mv = S.moves[j];
@@ -1029,7 +1128,8 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
                     bool ovf = false;
                     int front = 0;
                     long long cw = 0;
-                    const int c = decode_tg<NW, G, COUNT>(S, D, S.region, Ly.long_len, u, v, 0, D.n, front, ovf, &cw);
+                    const int c = decode_grp<NW, DEC, G, COUNT>(S, D, S.region, Ly.long_len, u, v, 0, D.n, front,
+                                                                ovf, &cw);
                     if (g == 0) {
                         if (COUNT) lw += cw;
                         const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
@@ -1051,18 +1151,18 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
     return block_min_u64<T>(best, S.red);
 }
 
-// Lane-per-candidate (G = 1) or group decode (G > 1, time-indexed only).
+// Lane-per-candidate (G = 1) or group decode (G > 2).
 // Layout codes: G = 1 one candidate per lane with 16-bit finish times,
 // G = 2 one candidate per lane with 8-bit finish times (lane profiles of at
-// most 255 units), G = 16 one candidate per 16 lanes (time-indexed).
+// most 255 units), G = 16 one candidate per 16 lanes (time-indexed), G = 8
+// one candidate per 8 lanes (capacity-indexed, a lane per resource).
 template <int NW, int T, int DEC, int G, bool COUNT = false>
 __device__ inline unsigned long long evaluate_any(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas, int L,
                                                   int delta, TabuSrc tabu, int asp, int *out_mk, long long *ovf_total,
                                                   long long *work_total = nullptr, bool share = true) {
     if constexpr (G > 2) {
-        static_assert(DEC == kEvalTime, "group decode is time-indexed");
-        return evaluate_moves_g<NW, T, G, COUNT>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk, ovf_total, work_total,
-                                                 share);
+        return evaluate_moves_g<NW, T, DEC, G, COUNT>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk, ovf_total,
+                                                      work_total, share);
     } else {
         return evaluate_moves<NW, T, DEC, COUNT, G == 2 ? 8 : 16>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk,
                                                                  ovf_total, work_total, share);
@@ -1215,22 +1315,27 @@ __global__ __launch_bounds__(64) void k_reset(SearchArgs A) {
 }
 
 // Makespan of the order in S.W decoded from scratch over the whole decode
-// region (at least the horizon): time-indexed by lanes 0-15 together (group
-// decode), capacity-indexed by thread 0.  Every thread of the workgroup calls
-// it; the value is that of thread 0.
+// region (at least the horizon): time-indexed by lanes 0-15 together,
+// capacity-indexed by lanes 0-7 (group decodes).  Every thread of the
+// workgroup calls it; the value is that of thread 0.
 template <int NW, int DEC>
 __device__ inline int decode_order(const Sh &S, const InstDesc &D, const Layout &Ly) {
+    int c = 0;
     if constexpr (DEC == kEvalTime) {
-        int c = 0;
         if (threadIdx.x < 16) {
             bool ovf = false;
             int front = 0;
             c = decode_tg<NW, 16, false, 16>(S, D, S.region, Ly.long_len, 0, 0, 0, D.n, front, ovf, nullptr);
         }
-        return c;
     } else {
-        return threadIdx.x == 0 ? decode_long<NW, DEC>(S, D, Ly, 0, 0) : 0;
+        if (threadIdx.x < 8) {
+            const int F0 = (D.n + 1) >> 1, Cd = (D.sum_r + 1) >> 1;
+            for (int i = threadIdx.x; i < Cd; i += 8) S.region[F0 + i] = 0u;
+            __builtin_amdgcn_wave_barrier();
+            c = decode_cg<8>(S, D, S.region, 0, 0, 0, D.n, nullptr);
+        }
     }
+    return c;
 }
 
 // Activities in decreasing order of key (16-bit, by activity), ties by
@@ -1997,11 +2102,13 @@ __global__ void k_clock(long long *out) {
 #define RCPSP_DISPATCH(NWV, TV, DECV, GV, CALL)                                                                      \
     switch (DECV) {                                                                                                  \
     case kEvalCapacity:                                                                                              \
-        if ((GV) != 1) return hipErrorInvalidValue;                                                                  \
-        switch (TV) {                                                                                                \
-        case 64: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;                      \
-        case 128: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;                    \
-        case 256: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;                    \
+        switch ((TV) * 32 + (GV)) {                                                                                  \
+        case 64 * 32 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;             \
+        case 128 * 32 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;           \
+        case 256 * 32 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;           \
+        case 64 * 32 + 8: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;             \
+        case 128 * 32 + 8: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;           \
+        case 256 * 32 + 8: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;           \
         default: return hipErrorInvalidValue;                                                                        \
         }                                                                                                            \
         break;                                                                                                       \

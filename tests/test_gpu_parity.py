@@ -451,6 +451,76 @@ def test_batch_mixes_lane_and_group_decode(rc):
     bt.close()
 
 
+# ---------------------------------------------------------------------------
+# Capacity-indexed group decode: 8 lanes per candidate, a lane per resource.
+# Same results as one candidate per lane and as the oracle.
+
+CAP_GROUP_CASES = GROUP_CASES[:4] + [
+    ("m12", lambda: synth.generate(40, 12, 10, 0.5, rs=0.5, seed=4012), 10),   # lanes own two resources
+    ("m3", lambda: synth.generate(45, 3, 10, 0.7, rs=0.3, seed=4013), 12),     # lanes without a resource
+]
+
+
+@pytest.mark.parametrize("name,make,delta", CAP_GROUP_CASES, ids=[c[0] for c in CAP_GROUP_CASES])
+@pytest.mark.parametrize("threads", [64, 256])
+def test_capacity_group_decode_search_parity(rc, name, make, delta, threads):
+    inst = make()
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=CAP)
+    kw = dict(swap_range=delta, tabu_len=30, iterations=25, searches=6, elite=3, phi_max=2, phi_steps=4, seed=8)
+    plan = rc.SearchPlan(gi, rc.search_params(threads=threads, lanes=8, **kw))
+    assert plan.config["lanes"] == 8 and plan.config["eval"] == CAP
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(delta, 30, 25, searches=6, elite=3, phi_max=2, phi_steps=4, decoder=CAP, seed=8)
+    _compare_search(g, o, elite=3)
+
+
+def test_capacity_group_decode_counts_same_work(rc):
+    inst = synth.generate(40, 4, 10, 0.5, rs=0.3, seed=24)
+    gi = rc.Instance(inst, eval=CAP)
+    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True)
+    a = rc.tabu_search(gi, lanes=1, **kw)
+    b = rc.tabu_search(gi, lanes=8, **kw)
+    for k in ("trajectory", "best_makespan", "evaluations"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["total_work"] == b["total_work"] > 0
+
+
+def test_large_instance_capacity_group(rc):
+    """300 activities, 8 resources: a short cooperative search with a lane
+    per resource equals the oracle, independent searches too."""
+    inst = synth.large_batch(1)[0]
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=CAP)
+    plan = rc.SearchPlan(gi, rc.search_params(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, seed=3,
+                                              lanes=8, threads=256))
+    assert plan.config["lanes"] == 8 and plan.config["eval"] == CAP
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, decoder=CAP, seed=3)
+    _compare_search(g, o, elite=4)
+    g = rc.tabu_search(gi, swap_range=20, tabu_len=60, iterations=2, searches=3, seed=4, lanes=8, threads=128)
+    o = orc.tabu_search(20, 60, 2, searches=3, decoder=CAP, seed=4)
+    _compare_search(g, o)
+
+
+def test_batch_mixes_capacity_lane_and_group_decode(rc):
+    insts = _batch_case()[:4]
+    gis = [rc.Instance(i, eval=CAP) for i in insts]
+    params = [rc.search_params(7, 30, 10, searches=5, elite=3, phi_max=2, phi_steps=4, threads=64,
+                               lanes=(1 if k % 2 else 8), seed=50 + k) for k in range(len(insts))]
+    bt = rc.Batch(gis, params)
+    bt.run()
+    for k, inst in enumerate(insts):
+        o = oracle.Oracle(inst).tabu_search(7, 30, 10, searches=5, elite=3, phi_max=2, phi_steps=4, decoder=CAP,
+                                            seed=50 + k)
+        _compare_search(bt.results(k), o, elite=3)
+    bt.close()
+
+
 @pytest.mark.parametrize("threads,profile_len,bits", [(192, 0, 8), (64, 300, 16), (128, 0, 8)])
 def test_finish_time_width_and_three_waves(rc, threads, profile_len, bits):
     """Lane states hold 8-bit finish times while the lane profile is at most
