@@ -346,11 +346,13 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
     for n, lst in gis.items():
         d, tl = SERVE_DELTA_TL[n + 2]
         base = rcpsp.search_params(d, tl, SERVE["iterations"], searches=SERVE["searches"], elite=SERVE["elite"],
-                                   phi_max=SERVE["phi_max"], phi_steps=SERVE["phi_steps"], threads=64,
-                                   record_trajectory=False, seed=SERVE["seed"])
+                                   phi_max=SERVE["phi_max"], phi_steps=SERVE["phi_steps"],
+                                   threads=128 if n >= 300 else 64, record_trajectory=False, seed=SERVE["seed"])
         # decoder and lanes per size from the batch autotuner on a sample; one
-        # wave per search for every size, so that sizes share launch classes
-        # (classes split the CUs between them)
+        # wave per search for the sizes that share the time-indexed launch
+        # class (classes split the CUs between them); the 300-activity size,
+        # a class of its own, also tunes its threads (its iterations are the
+        # longest tasks)
         tuned, info = rcpsp.batch_autotune(lst[:8], base, trial_iterations=1, sample=8, stream=stream)
         params[n] = tuned[0]
         tuning[str(n)] = dict(eval=info["group_eval"][0], threads=info["group_threads"][0],

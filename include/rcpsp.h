@@ -362,7 +362,10 @@ rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_param
  * request ends at the first iteration boundary where its iteration
  * allowance is used up, its time budget (counted from admission) has passed,
  * every search has stopped, the working set reached the critical path, or
- * it was cancelled.  Its results equal those of a plain run with
+ * it was cancelled; a request whose budget has passed (or that was
+ * cancelled) by the end of its set-up runs no iteration and ends with its
+ * initial solutions (status iterations = 0).  Its results equal those of a
+ * plain run with
  * iterations = the request's `iterations` status field, except that eq. 8
  * keeps the full allowance (params.iterations) as I_block.  State stays
  * resident until rcpsp_server_release.  All entry points are thread-safe.

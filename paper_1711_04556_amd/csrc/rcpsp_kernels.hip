@@ -2013,11 +2013,21 @@ __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
                 for (int k = 0; k < A.NF; ++k) decode_record<NW, T, DEC>(A, S, k);
                 exchange_round<T>(A, 0, 1, reinterpret_cast<int *>(S.region));
             }
-            next = 0;
+            // a request whose budget ran out during set-up (it waited for a
+            // workgroup) runs no iteration: its searches only finish their
+            // set-up, and it ends with its initial solutions
+            if (tid == 0) {
+                const int cancel = __hip_atomic_load(&R->cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                flag = ((long long)wall_clock64() >= R->deadline || cancel) ? 1 : 0;
+            }
+            __syncthreads();
+            next = flag ? kServeNoIteration : 0;
+            __syncthreads();
         } else {
+            const bool none = it == kServeNoIteration;
             stage_blob<T>(lds, A.D, A.Ly);
             __syncthreads();
-            search_step<NW, T, DEC, G, false>(A, S, ss, b, it, 1);
+            search_step<NW, T, DEC, G, false>(A, S, ss, b, none ? 0 : it, none ? 0 : 1);
             if (tid == 0) {
                 const int old = __hip_atomic_fetch_add(&R->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
                 int fin = -1;
@@ -2035,11 +2045,11 @@ __global__ __launch_bounds__(T) void k_serve(ServeArgs C) {
                     for (int k = 0; k < A.NF; ++k) best = min(best, A.Fmeta[k].C);
                     const int gstop = A.NF > 0 && A.g->gstop != 0;
                     const int cancel = __hip_atomic_load(&R->cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    fin = it + 1 >= R->max_iters || now >= R->deadline || all_stopped || gstop || cancel;
+                    fin = none || it + 1 >= R->max_iters || now >= R->deadline || all_stopped || gstop || cancel;
                     if (fin) {
                         R->best = best;
                         R->evals = evals;
-                        R->replay_iters = it + 1;
+                        R->replay_iters = none ? 0 : it + 1;
                         R->done_ticks = now;
                         R->next_iter = -1;
                         __hip_atomic_store(&R->finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

@@ -91,6 +91,11 @@ struct ServeArgs {
 // Marks a task slot whose task has run.
 constexpr unsigned long long kServeTaskDone = ~0ull;
 
+// Iteration field of the search tasks of a request that ends before its
+// first iteration (its budget ran out during set-up): each task completes
+// its search's set-up (initial decode, first read) and runs no iteration.
+constexpr int kServeNoIteration = (1 << 27) - 1;
+
 // task: slot (20 bits) | kind (1: search step, 0: set-up) | search (16 bits) | iteration (27 bits)
 __host__ __device__ inline unsigned long long serve_task(int slot, int kind, int b, int it) {
     return ((unsigned long long)slot << 44) | ((unsigned long long)kind << 43) | ((unsigned long long)b << 27) |

@@ -630,7 +630,8 @@ extern "C" rcpsp_status rcpsp_server_submit(rcpsp_server *s, const rcpsp_instanc
     if (!s || !inst || !params || !ticket) return fail(RCPSP_E_ARG, "null pointer");
     rcpsp_status st = validate_params(*params);
     if (st != RCPSP_OK) return st;
-    if (params->iterations < 1) return fail(RCPSP_E_ARG, "a served request needs an iteration allowance >= 1");
+    if (params->iterations < 1 || params->iterations >= kServeNoIteration)
+        return fail(RCPSP_E_ARG, "a served request needs an iteration allowance in 1..%d", kServeNoIteration - 1);
     if (params->fbi) return fail(RCPSP_E_ARG, "forward-backward improvement is for search plans only");
     if (budget_us < 0) return fail(RCPSP_E_ARG, "negative budget");
     // footprint: the plan's state in the arena and its workgroup's LDS

@@ -29,7 +29,7 @@ def _check_against_oracle(rc, srv, ticket, inst, dec, p):
     st = srv.poll(ticket)
     assert st["state"] == rc.REQ_DONE, st
     k = st["iterations"]
-    assert 1 <= k <= p.iterations
+    assert 0 <= k <= p.iterations
     g = srv.results(ticket)
     o = oracle.Oracle(inst).tabu_search(p.swap_range, p.tabu_len, k, searches=p.searches, elite=p.elite,
                                         phi_max=p.phi_max, phi_steps=p.phi_steps, decoder=dec, seed=p.seed,
@@ -81,6 +81,30 @@ def test_server_requests_match_oracle_replay(rc):
     assert not pending, [srv.poll(x[0]) for x in pending]
     s = srv.stats
     assert s["completed"] == len(tickets) and s["resident"] == 0 and s["arena_used"] == 0
+    srv.close()
+
+
+def test_server_budget_spent_during_set_up(rc):
+    """A budget that runs out before a request's set-up ends: the request
+    runs no iteration and returns its initial solutions (the oracle run of
+    zero iterations), with and without a working set."""
+    srv = rc.Server(max_active=8, slice_us=500)
+    items = []
+    for i in range(6):
+        inst = synth.generate(25 + 5 * i, 4, 10, 0.5, rs=0.4, seed=970 + i)
+        dec = TIME if i % 2 else CAP
+        gi = rc.Instance(inst, eval=dec)
+        p = rc.search_params(7, 20, 50, searches=4, elite=(3 if i < 3 else 0), phi_max=1, phi_steps=3,
+                             threads=64, seed=60 + i)
+        items.append((srv.submit(gi, p, 1), inst, gi, dec, p))
+    srv.drain(30000)
+    zero = 0
+    for t, inst, gi, dec, p in items:
+        st = _check_against_oracle(rc, srv, t, inst, dec, p)
+        assert st["iterations"] <= 1
+        zero += st["iterations"] == 0
+        srv.release(t)
+    assert zero > 0
     srv.close()
 
 
