@@ -474,8 +474,10 @@ static rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, i
     int L = 0;
     Layout Ly;
     rcpsp_status s = RCPSP_E_TOO_LARGE;
-    for (int g : {2, 1, 16}) {
-        if (g != 1 && I->eval != kEvalTime) continue;
+    // one candidate per lane first; groups when no lane state fits
+    for (int g : {2, 1, 16, 8}) {
+        if ((g == 2 || g == 16) && I->eval != kEvalTime) continue;
+        if (g == 8 && I->eval != kEvalCapacity) continue;
         for (T = 256; T >= 64; T /= 2) {
             s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly, g);
             if (s != RCPSP_E_TOO_LARGE) break;

@@ -413,8 +413,11 @@ __device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int p
 // requests over [s, s+d).  Only the first L time units are held (the lane's
 // storage has L+4 so the scan may read four units at a time); a candidate
 // whose schedule would pass L reports overflow and is decoded again with a
-// longer profile.  Time units at or beyond `front` have never been written and
-// hold the full capacity, so a scan that reaches `front` ends there.  Each
+// longer profile.  Time units at or beyond `front` have never been used and
+// stand for the full capacity, so a scan that reaches `front` ends there; the
+// four units from `front` on are kept at the full capacity (the caller sets
+// them up, frontier_full), so a step reading past the frontier needs no
+// test of its own.  Each
 // scan step tests four units with selects only, so their loads are in
 // flight together.  Alg. 6 is a fill of never-written units up to s + d with
 // the full capacity, then LDS atomic subtractions: neither waits for a
@@ -496,7 +499,7 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                         const uint32_t A = P[(k * NW + w) * STRIDE];
                         o = o && ((((A | G[w]) - rq[w]) & G[w]) == G[w]);
                     }
-                    ok[k] = o || (t + k >= fr);
+                    ok[k] = o;   // units past the frontier hold the full capacity
                 }
                 const int r0 = ok[0] ? run + 1 : 0;
                 const int r1 = ok[1] ? r0 + 1 : 0;
@@ -517,7 +520,9 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 return -1;
             }
             if (COUNT) w_ops += (e - es) + d;
-            for (int x = fr; x < e; ++x) {
+            // [fr, fr + 4) already hold the full capacity; keep four such
+            // units past the new frontier
+            for (int x = fr + 4; x < e + 4; ++x) {
 #pragma unroll
                 for (int w = 0; w < NW; ++w) prof[(x * NW + w) * STRIDE] = FULL[w];
             }
@@ -616,6 +621,16 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
     return p1 == D.n ? M.ld16(D.n - 1) : 0;
 }
 
+// The four time units from `front` on of a lane's time-indexed profile at
+// the full capacity (the state decode_ti expects at its frontier).
+template <int STRIDE, int FB>
+__device__ inline void frontier_full(const InstDesc &D, uint32_t *lane_base, int front) {
+    LaneMem<STRIDE> M{lane_base};
+    const int b = f_dwords<FB>(D.n) + front * D.nw;
+    for (int x = 0; x < 4; ++x)
+        for (int w = 0; w < D.nw; ++w) M.st(b + x * D.nw + w, D.full[w]);
+}
+
 // Fresh decoder state: capacity-indexed arrays start at zero; the
 // time-indexed profile needs nothing (front = 0).
 template <int DEC, int STRIDE>
@@ -655,6 +670,7 @@ __device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int
     if (DEC == kEvalTime) {
         bool ovf = false;
         int front = 0;
+        frontier_full<1, 16>(D, S.region, 0);
         return decode_ti<NW, 1, COUNT>(S, D, S.region, Ly.long_len, u, v, 0, D.n, front, ovf, wk);
     }
     return decode_ci<1, COUNT>(S, D, S.region, u, v, 0, D.n, wk);
@@ -737,6 +753,7 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
             } else {
                 init_state<DEC, T>(D, lane_base);
             }
+            if constexpr (DEC == kEvalTime) frontier_full<T, FB>(D, lane_base, front);
             bool ovf = false;
             int c;
             long long cw = 0;

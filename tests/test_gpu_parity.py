@@ -587,13 +587,13 @@ def test_forward_backward_improvement_of_initial_solutions(rc, dec):
     assert any(orc.fbi(orc.initial_order(4, b), dec)[1] < orc.decode(orc.initial_order(4, b), dec) for b in (1, 3))
 
 
-@pytest.mark.parametrize("dec,n", [(TIME, 800), (CAP, 300)])
+@pytest.mark.parametrize("dec,n", [(TIME, 800), (CAP, 300), (CAP, 800)])
 def test_neighbourhood_large_instances(rc, dec, n):
-    """Large instances (800 activities time-indexed, 300 capacity-indexed,
-    whose one-candidate-per-lane state is larger): every makespan of the
-    neighbourhood equals the oracle's.  Beyond what fits (the activity limit,
-    2,046 + 2 dummies; 800 activities capacity-indexed) the evaluation is
-    either exact on sampled moves or refused with RCPSP_E_TOO_LARGE."""
+    """Large instances (800 activities; capacity-indexed states that do not
+    fit one per lane take 8 lanes per candidate): every makespan of the
+    neighbourhood equals the oracle's.  At the activity limit (2,046 + 2
+    dummies) the evaluation is either exact on sampled moves or refused with
+    RCPSP_E_TOO_LARGE."""
     inst = synth.generate(n, 4, 10, 0.5, rs=0.5, seed=801)
     orc = oracle.Oracle(inst)
     gi = rc.Instance(inst, eval=dec)
@@ -602,7 +602,7 @@ def test_neighbourhood_large_instances(rc, dec, n):
     mk_o, best_o = orc.evaluate_neighbourhood(W, 2, dec)
     assert np.array_equal(mk_g, mk_o)
     assert [best_g["u"], best_g["v"], best_g["makespan"], best_g["n_feasible"]] == best_o
-    for nb in ((2046,) if dec == TIME else (800, 2046)):
+    for nb in (2046,):
         big = synth.generate(nb, 4, 10, 0.5, rs=0.5, seed=802)
         ob = oracle.Oracle(big)
         gb = rc.Instance(big, eval=dec)
