@@ -415,9 +415,9 @@ __device__ inline int prec_earliest(const Sh &S, const LaneMem<STRIDE> &M, int p
 // whose schedule would pass L reports overflow and is decoded again with a
 // longer profile.  Time units at or beyond `front` have never been used and
 // stand for the full capacity, so a scan that reaches `front` ends there; the
-// four units from `front` on are kept at the full capacity (the caller sets
-// them up, frontier_full), so a step reading past the frontier needs no
-// test of its own.  Each
+// four units from `front` on are kept at the full capacity (set at entry,
+// then by every Alg. 6 that moves the frontier), so a step reading past the
+// frontier needs no test of its own.  Each
 // scan step tests four units with selects only, so their loads are in
 // flight together.  Alg. 6 is a fill of never-written units up to s + d with
 // the full capacity, then LDS atomic subtractions: neither waits for a
@@ -450,6 +450,11 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
     uint32_t *prof = lane_base + F0 * STRIDE;   // time unit t, word w at prof[(t*NW + w)*STRIDE]
     long long w_ops = 0;
     int fr = front;
+    // units from the frontier on are unused: four of them at the full capacity
+    for (int x = fr; x < fr + 4; ++x) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) prof[(x * NW + w) * STRIDE] = FULL[w];
+    }
     // the record and predecessor offsets of a position (clamped to the last
     // one, so the load one position ahead stays in range)
     auto qof = [&](int p) {
@@ -621,16 +626,6 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
     return p1 == D.n ? M.ld16(D.n - 1) : 0;
 }
 
-// The four time units from `front` on of a lane's time-indexed profile at
-// the full capacity (the state decode_ti expects at its frontier).
-template <int STRIDE, int FB>
-__device__ inline void frontier_full(const InstDesc &D, uint32_t *lane_base, int front) {
-    LaneMem<STRIDE> M{lane_base};
-    const int b = f_dwords<FB>(D.n) + front * D.nw;
-    for (int x = 0; x < 4; ++x)
-        for (int w = 0; w < D.nw; ++w) M.st(b + x * D.nw + w, D.full[w]);
-}
-
 // Fresh decoder state: capacity-indexed arrays start at zero; the
 // time-indexed profile needs nothing (front = 0).
 template <int DEC, int STRIDE>
@@ -670,7 +665,6 @@ __device__ int decode_long(const Sh &S, const InstDesc &D, const Layout &Ly, int
     if (DEC == kEvalTime) {
         bool ovf = false;
         int front = 0;
-        frontier_full<1, 16>(D, S.region, 0);
         return decode_ti<NW, 1, COUNT>(S, D, S.region, Ly.long_len, u, v, 0, D.n, front, ovf, wk);
     }
     return decode_ci<1, COUNT>(S, D, S.region, u, v, 0, D.n, wk);
@@ -753,7 +747,6 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
             } else {
                 init_state<DEC, T>(D, lane_base);
             }
-            if constexpr (DEC == kEvalTime) frontier_full<T, FB>(D, lane_base, front);
             bool ovf = false;
             int c;
             long long cw = 0;
