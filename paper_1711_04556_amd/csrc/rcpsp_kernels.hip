@@ -1486,7 +1486,8 @@ struct StepShared {
 // instance blob must be staged.  COUNT adds the algorithmic operations of
 // every decode to the search's work counter.
 template <int NW, int T, int DEC, int G, bool COUNT>
-__device__ void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, int b, int it0, int n_it) {
+__device__ __attribute__((always_inline)) void search_step(const SearchArgs &A, const Sh &S, StepShared &ss, int b, int it0,
+                                                         int n_it) {
     const InstDesc &D = A.D;
     const Layout &Ly = A.Ly;
     SearchScalars &sc = ss.sc;
