@@ -450,6 +450,12 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
     uint32_t *prof = lane_base + F0 * STRIDE;   // time unit t, word w at prof[(t*NW + w)*STRIDE]
     long long w_ops = 0;
     int fr = front;
+    // the positions are the same for every lane of the wave (a shared prefix
+    // or none), so the loop over them is scalar; a lane whose schedule passes
+    // its profile stays in it (over) instead of leaving it alone
+    p0 = __builtin_amdgcn_readfirstlane(p0);
+    p1 = __builtin_amdgcn_readfirstlane(p1);
+    bool over = false;
     // units from the frontier on are unused: four of them at the full capacity
     for (int x = fr; x < fr + 4; ++x) {
 #pragma unroll
@@ -490,7 +496,7 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         const uint4 pn = kPin ? pin[qn] : make_uint4(0u, 0u, 0u, 0u);
         if (COUNT) w_ops += 1 + np;
         int s = es;
-        if (any != 0 && d > 0) {
+        if (!over && any != 0 && d > 0) {
             int t = es, run = 0;   // run: free units just before t
             s = -1;
             while (s < 0 && t < fr) {
@@ -521,21 +527,23 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
             if (s < 0) s = t - run;  // reached the frontier: all later units are free
             const int e = s + d;
             if (e > L) {
-                ovf = true;
-                return -1;
-            }
-            if (COUNT) w_ops += (e - es) + d;
-            // [fr, fr + 4) already hold the full capacity; keep four such
-            // units past the new frontier
-            for (int x = fr + 4; x < e + 4; ++x) {
+                // past the lane's profile: the lane only runs along with the
+                // wave from here (no more profile access) and reports overflow
+                over = true;
+            } else {
+                if (COUNT) w_ops += (e - es) + d;
+                // [fr, fr + 4) already hold the full capacity; keep four such
+                // units past the new frontier
+                for (int x = fr + 4; x < e + 4; ++x) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) prof[(x * NW + w) * STRIDE] = FULL[w];
-            }
-            for (int x = s; x < e; ++x) {
+                    for (int w = 0; w < NW; ++w) prof[(x * NW + w) * STRIDE] = FULL[w];
+                }
+                for (int x = s; x < e; ++x) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) lds_sub(prof + (x * NW + w) * STRIDE, rq[w]);
+                    for (int w = 0; w < NW; ++w) lds_sub(prof + (x * NW + w) * STRIDE, rq[w]);
+                }
+                fr = max(fr, e);
             }
-            fr = max(fr, e);
         } else if (COUNT) {
             w_ops += 2 * d;
         }
@@ -543,6 +551,10 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         q = qn;
         r = rn;
         pi = pn;
+    }
+    if (over) {
+        ovf = true;
+        return -1;
     }
     front = fr;
     if (COUNT) *wk += w_ops;
