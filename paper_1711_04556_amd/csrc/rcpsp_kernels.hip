@@ -498,8 +498,9 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         int s = es;
         if (!over && any != 0 && d > 0) {
             int t = es, run = 0;   // run: free units just before t
-            s = -1;
-            while (s < 0 && t < fr) {
+            int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+            bool found = false;
+            while (!found && t < fr) {
                 const uint32_t *P = prof + t * NW * STRIDE;
                 bool ok[4];
 #pragma unroll
@@ -512,19 +513,26 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                     }
                     ok[k] = o;   // units past the frontier hold the full capacity
                 }
-                const int r0 = ok[0] ? run + 1 : 0;
-                const int r1 = ok[1] ? r0 + 1 : 0;
-                const int r2 = ok[2] ? r1 + 1 : 0;
-                const int r3 = ok[3] ? r2 + 1 : 0;
-                // earliest unit where the run reaches d (selects, no branches)
-                s = (r3 == d) ? t + 4 - d : -1;
-                s = (r2 == d) ? t + 3 - d : s;
-                s = (r1 == d) ? t + 2 - d : s;
-                s = (r0 == d) ? t + 1 - d : s;
+                r0 = ok[0] ? run + 1 : 0;
+                r1 = ok[1] ? r0 + 1 : 0;
+                r2 = ok[2] ? r1 + 1 : 0;
+                r3 = ok[3] ? r2 + 1 : 0;
+                // runs grow by one from below d, so one of them equals d
+                // exactly when their maximum reaches it
+                found = max(max(r0, r1), max(r2, r3)) >= d;
                 run = r3;
                 t += 4;
             }
-            if (s < 0) s = t - run;  // reached the frontier: all later units are free
+            if (found) {
+                // earliest unit of the last step where the run reaches d
+                const int tb = t - 4;
+                s = (r3 == d) ? tb + 4 - d : -1;
+                s = (r2 == d) ? tb + 3 - d : s;
+                s = (r1 == d) ? tb + 2 - d : s;
+                s = (r0 == d) ? tb + 1 - d : s;
+            } else {
+                s = t - run;  // reached the frontier: all later units are free
+            }
             const int e = s + d;
             if (e > L) {
                 // past the lane's profile: the lane only runs along with the
