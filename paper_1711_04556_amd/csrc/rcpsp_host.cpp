@@ -197,7 +197,7 @@ static rcpsp_status validate_and_derive(rcpsp_instance *I, int32_t n, int32_t m,
             if (k < m) f |= (uint32_t)I->R[k] << sh;
         }
         D.guard[w] = g;
-        D.full[w] = f;
+        D.full[w] = f | g;   // stored units keep the guard bits set
     }
     Blob bl;
     std::vector<int> v16;

@@ -26,7 +26,7 @@ struct InstDesc {
     int copy_p;      // capacity-indexed copy ring length (power of two >= max request)
     int n_levels;
     uint32_t guard[kMaxNW];  // top bit of every field
-    uint32_t full[kMaxNW];   // R_k of every field
+    uint32_t full[kMaxNW];   // R_k of every field, with its guard bit set
     int R[kMaxM];
     int cbase[kMaxM];        // first entry of c_k in the capacity-indexed state
     // blob sections (dword offsets)

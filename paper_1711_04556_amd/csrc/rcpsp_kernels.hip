@@ -12,9 +12,10 @@
 //    lane-interleaved layout (dword i of lane l at i*T+l), so lanes never
 //    conflict on a bank;
 //  - the time-indexed profile packs all resources of one time unit into one
-//    or more dwords (8- or 16-bit fields with a guard bit), so the capacity
-//    test of Alg. 5 for all resources is one subtract and mask, and Alg. 6 is
-//    one subtract;
+//    or more dwords (8- or 16-bit fields whose top bit, the guard, is kept
+//    set in every stored unit), so the capacity test of Alg. 5 for all
+//    resources is one subtract and mask (a field short of capacity borrows
+//    its guard), and Alg. 6 is one subtract;
 //  - the best admissible move is a 64-bit key (non-admissible, C_max, u, v)
 //    reduced with cross-lane shuffles inside a wave and LDS across waves.
 #include <hip/hip_runtime.h>
@@ -509,7 +510,7 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
 #pragma unroll
                     for (int w = 0; w < NW; ++w) {
                         const uint32_t A = P[(k * NW + w) * STRIDE];
-                        o = o && ((((A | G[w]) - rq[w]) & G[w]) == G[w]);
+                        o = o && (((A - rq[w]) & G[w]) == G[w]);
                     }
                     ok[k] = o;   // units past the frontier hold the full capacity
                 }
@@ -932,7 +933,7 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
                 if (x < fr) {
                     const uint32_t *P = prof + x * NW;
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) ok = ok && ((((P[w] | Gd[w]) - rq[w]) & Gd[w]) == Gd[w]);
+                    for (int w = 0; w < NW; ++w) ok = ok && (((P[w] - rq[w]) & Gd[w]) == Gd[w]);
                 }
                 const unsigned long long m = (__ballot(ok) >> gbase) & gm;
                 const uint32_t mz = (uint32_t)(~m & gm);          // units that do not fit
