@@ -204,7 +204,8 @@ __device__ inline unsigned long long block_min_u64(unsigned long long x, unsigne
 //   predT[e]       = byte offset of f[pred[e]] in a lane's storage,
 //   pin[4p..4p+3]  = the same offsets for the first four predecessors of w_p
 //                    (one 16-byte load; present for one-candidate-per-lane
-//                    time-indexed layouts only).
+//                    time-indexed layouts only); absent predecessors get
+//                    offset 0, the finish time of the source activity (0).
 template <int T, int FB = 16>
 __device__ inline void build_records(const Sh &S, const InstDesc &D) {
     const int N = D.n, NW = D.nw;
@@ -457,6 +458,12 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
     p0 = __builtin_amdgcn_readfirstlane(p0);
     p1 = __builtin_amdgcn_readfirstlane(p1);
     bool over = false;
+    // the source (position 0, duration 0) finishes at 0; the predecessor
+    // table reads that slot for absent predecessors, so it is set before
+    // anything reads it
+    if constexpr (kPin) {
+        if (p0 == 0) M.template stf<FB>(0u, 0);
+    }
     // units from the frontier on are unused: four of them at the full capacity
     for (int x = fr; x < fr + 4; ++x) {
 #pragma unroll
@@ -486,7 +493,8 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         if constexpr (kPin) {
             const int f0 = M.template ldf<FB>(pi.x), f1 = M.template ldf<FB>(pi.y);
             const int f2 = M.template ldf<FB>(pi.z), f3 = M.template ldf<FB>(pi.w);
-            es = max(max(np > 0 ? f0 : 0, np > 1 ? f1 : 0), max(np > 2 ? f2 : 0, np > 3 ? f3 : 0));
+            // entries past the predecessors point to the source's finish time (0)
+            es = max(max(f0, f1), max(f2, f3));
             for (int e = 4; e < np; ++e) es = max(es, M.template ldf<FB>(S.predT[r.z + e]));
         } else {
             es = prec_earliest<STRIDE, FB>(S, M, (int)r.z, np);
@@ -500,8 +508,7 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         if (!over && any != 0 && d > 0) {
             int t = es, run = 0;   // run: free units just before t
             int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
-            bool found = false;
-            while (!found && t < fr) {
+            while (t < fr) {
                 const uint32_t *P = prof + t * NW * STRIDE;
                 bool ok[4];
 #pragma unroll
@@ -518,13 +525,13 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 r1 = ok[1] ? r0 + 1 : 0;
                 r2 = ok[2] ? r1 + 1 : 0;
                 r3 = ok[3] ? r2 + 1 : 0;
-                // runs grow by one from below d, so one of them equals d
-                // exactly when their maximum reaches it
-                found = max(max(r0, r1), max(r2, r3)) >= d;
                 run = r3;
                 t += 4;
+                // runs grow by one from below d, so one of them equals d
+                // exactly when their maximum reaches it
+                if (max(max(r0, r1), max(r2, r3)) >= d) break;
             }
-            if (found) {
+            if (max(max(r0, r1), max(r2, r3)) >= d) {
                 // earliest unit of the last step where the run reaches d
                 const int tb = t - 4;
                 s = (r3 == d) ? tb + 4 - d : -1;
