@@ -451,6 +451,28 @@ def test_batch_mixes_lane_and_group_decode(rc):
     bt.close()
 
 
+@pytest.mark.parametrize("threads,elite", [(64, 0), (192, 4)])
+def test_lane_decode_after_requestless_activities(rc, threads, elite):
+    """Most activities request no resource and last long: they never move a
+    lane's resource frontier, so their successors start well past it, over
+    units the lane has not written since an earlier candidate.  Every
+    neighbourhood makespan and the whole search must equal the oracle."""
+    for seed in (1301, 1302, 1303):
+        inst = synth.generate(40, 4, 20, 0.2, rs=0.3, seed=seed)
+        orc = oracle.Oracle(inst)
+        gi = rc.Instance(inst, eval=TIME)
+        for k in range(3):
+            W = orc.initial_order(seed, k)
+            mk_g, _ = gi.evaluate_neighbourhood(W, 12)
+            mk_o, _ = orc.evaluate_neighbourhood(W, 12, TIME)
+            assert np.array_equal(mk_g, mk_o), (seed, k, np.nonzero(mk_g != mk_o)[0][:10])
+        kw = dict(swap_range=12, tabu_len=40, iterations=40, searches=8, elite=elite, phi_max=2, phi_steps=4,
+                  seed=seed)
+        g = rc.tabu_search(gi, threads=threads, **kw)
+        o = orc.tabu_search(12, 40, 40, searches=8, elite=elite, phi_max=2, phi_steps=4, decoder=TIME, seed=seed)
+        _compare_search(g, o, elite=elite)
+
+
 # ---------------------------------------------------------------------------
 # Capacity-indexed group decode: 8 lanes per candidate, a lane per resource.
 # Same results as one candidate per lane and as the oracle.
