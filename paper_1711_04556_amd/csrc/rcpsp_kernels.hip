@@ -1009,6 +1009,9 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
     const int pmask = D.copy_p - 1;
     const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
     long long w_ops = 0;
+    // the positions are the same for every lane of the wave: a scalar loop
+    p0 = __builtin_amdgcn_readfirstlane(p0);
+    p1 = __builtin_amdgcn_readfirstlane(p1);
     for (int p = p0; p < p1; ++p) {
         const int q = (p == u) ? v : ((p == v) ? u : p);
         const uint4 r = rec[q];
