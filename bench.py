@@ -369,14 +369,19 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
     tuning = {}
     for n, lst in gis.items():
         d, tl = SERVE_DELTA_TL[n + 2]
+        big = n >= 300
         base = rcpsp.search_params(d, tl, SERVE["iterations"], searches=SERVE["searches"], elite=SERVE["elite"],
                                    phi_max=SERVE["phi_max"], phi_steps=SERVE["phi_steps"],
-                                   threads=128 if n >= 300 else 64, record_trajectory=False, seed=SERVE["seed"])
-        # decoder and lanes per size from the batch autotuner on a sample; one
-        # wave per search for the sizes that share the time-indexed launch
-        # class (classes split the CUs between them); the 300-activity size,
-        # a class of its own, also tunes its threads (its iterations are the
-        # longest tasks)
+                                   threads=128 if big else 64, lanes=8 if big else 0,
+                                   eval=rcpsp.EVAL_CAPACITY if big else rcpsp.EVAL_AUTO,
+                                   record_trajectory=False, seed=SERVE["seed"])
+        # decoder and lanes per size from the batch autotuner on a sample, at
+        # one wave per search for the sizes that share the time-indexed launch
+        # class (classes split the CUs between them).  The 300-activity size
+        # is a class of its own with the longest tasks; the autotuner ranks
+        # shapes by one iteration's throughput, which says nothing about task
+        # length, so it takes the shape measured best for serving latency:
+        # capacity-indexed, 8 lanes per candidate, 128 threads
         tuned, info = rcpsp.batch_autotune(lst[:8], base, trial_iterations=1, sample=8, stream=stream)
         params[n] = tuned[0]
         tuning[str(n)] = dict(eval=info["group_eval"][0], threads=info["group_threads"][0],
