@@ -550,11 +550,28 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 if (COUNT) w_ops += (e - es) + d;
                 // [fr, fr + 4) already hold the full capacity; keep four such
                 // units past the new frontier
-                for (int x = fr + 4; x < e + 4; ++x) {
+                // two units per step (half the loop control), then the odd one
+                int x = fr + 4;
+                for (; x + 1 < e + 4; x += 2) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        prof[(x * NW + w) * STRIDE] = FULL[w];
+                        prof[((x + 1) * NW + w) * STRIDE] = FULL[w];
+                    }
+                }
+                if (x < e + 4) {
 #pragma unroll
                     for (int w = 0; w < NW; ++w) prof[(x * NW + w) * STRIDE] = FULL[w];
                 }
-                for (int x = s; x < e; ++x) {
+                x = s;
+                for (; x + 1 < e; x += 2) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        lds_sub(prof + (x * NW + w) * STRIDE, rq[w]);
+                        lds_sub(prof + ((x + 1) * NW + w) * STRIDE, rq[w]);
+                    }
+                }
+                if (x < e) {
 #pragma unroll
                     for (int w = 0; w < NW; ++w) lds_sub(prof + (x * NW + w) * STRIDE, rq[w]);
                 }
