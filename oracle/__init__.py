@@ -70,6 +70,7 @@ def lib():
         L.orc_decay_table.argtypes = [u32p, ctypes.c_int]
         L.orc_iterations_assigned.argtypes = [ctypes.c_int] * 4
         L.orc_tabu_search.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_tabu_search.restype = ctypes.c_int
         L.orc_fbi.argtypes = [ctypes.c_void_p, ctypes.c_int, i32p]
         L.orc_fbi.restype = ctypes.c_int
         _lib = L
@@ -89,7 +90,9 @@ class OrcParams(ctypes.Structure):
                 ("searches", ctypes.c_int), ("elite", ctypes.c_int), ("phi_max", ctypes.c_int),
                 ("phi_steps", ctypes.c_int), ("decoder", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("i_block", ctypes.c_int), ("fbi", ctypes.c_int),
-                ("decoder_of_iteration", ctypes.POINTER(ctypes.c_int32))]
+                ("decoder_of_iteration", ctypes.POINTER(ctypes.c_int32)),
+                ("exchange_every", ctypes.c_int), ("round_log", ctypes.POINTER(ctypes.c_int32)),
+                ("round_log_cap", ctypes.c_int)]
 
 
 class OrcResults(ctypes.Structure):
@@ -185,12 +188,17 @@ class Oracle:
     def tabu_search(self, delta: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                     phi_max: int = 3, phi_steps: int = 20, decoder: int = TIME, seed: int = 1,
                     trajectory: bool = True, i_block: int = 0, fbi: bool = False,
-                    decoder_of_iteration: Optional[Sequence[int]] = None) -> dict:
+                    decoder_of_iteration: Optional[Sequence[int]] = None, exchange_every: int = 1,
+                    round_log: bool = False) -> dict:
         """i_block: eq. 8's iteration allowance when it differs from the
         iterations run (a search cut short by a time budget); 0 = iterations.
         fbi: forward-backward improvement of every second initial solution.
         decoder_of_iteration: per iteration, the decoder of its decodes
-        (periodic re-selection); set-up decodes keep `decoder`."""
+        (periodic re-selection); set-up decodes keep `decoder`.
+        exchange_every: iterations between exchange rounds.
+        round_log: also return out["rounds"], the state after every exchange
+        round: a list of dicts with per-record C, IC, reads, W and per-search
+        slot, I_assigned, C_read, C_cur, C_best."""
         B, N = searches, self.n
         out = dict(best_makespan=np.zeros(B, np.int32), best_order=np.zeros((B, N), np.int32),
                    iterations_done=np.zeros(B, np.int32), evaluations=np.zeros(B, np.int64),
@@ -201,22 +209,36 @@ class Oracle:
         if decoder_of_iteration is not None:
             sched = _i32(list(decoder_of_iteration)).copy()
             assert len(sched) == iterations and set(sched.tolist()) <= {TIME, CAPACITY}
+        stride = elite * (3 + N) + 5 * B
+        cap = (iterations // max(exchange_every, 1) + 1) if (round_log and elite > 0) else 0
+        log = np.zeros(max(cap * stride, 1), np.int32)
         prm = OrcParams(delta, tabu_len, iterations, searches, elite, phi_max, phi_steps, decoder, seed, i_block,
-                        int(fbi), _p(sched) if sched is not None else None)
+                        int(fbi), _p(sched) if sched is not None else None, exchange_every,
+                        _p(log) if cap else None, cap)
         res = OrcResults(*[out[k].ctypes.data if out[k] is not None else None for k in
                            ("best_makespan", "best_order", "iterations_done", "evaluations", "trajectory",
                             "elite_makespan", "elite_order")])
-        lib().orc_tabu_search(self.h, ctypes.byref(prm), ctypes.byref(res))
+        rounds = lib().orc_tabu_search(self.h, ctypes.byref(prm), ctypes.byref(res))
         out["elite_makespan"] = out["elite_makespan"][:elite]
         out["elite_order"] = out["elite_order"][:elite]
+        if round_log:
+            out["rounds"] = []
+            for r in range(min(rounds, cap)):
+                row = log[r * stride:(r + 1) * stride]
+                recs = row[:elite * (3 + N)].reshape(elite, 3 + N)
+                srch = row[elite * (3 + N):].reshape(B, 5)
+                out["rounds"].append(dict(C=recs[:, 0].copy(), IC=recs[:, 1].copy(), reads=recs[:, 2].copy(),
+                                          W=recs[:, 3:].copy(), slot=srch[:, 0].copy(),
+                                          I_assigned=srch[:, 1].copy(), C_read=srch[:, 2].copy(),
+                                          C_cur=srch[:, 3].copy(), C_best=srch[:, 4].copy()))
         return out
 
 
 def capacity_update(R: int, c: Sequence[int], r: int, d: int, s: int):
     """Alg. 4 on one resource array; returns (new array, residual effort)."""
     arr = _i32(list(c)).copy()
-    copy = np.zeros(max(R, 1), dtype=np.int32)
-    res = lib().orc_capacity_update(R, _p(arr), r, d, s, _p(copy))
+    was = np.zeros(max(R, 1), dtype=np.int32)
+    res = lib().orc_capacity_update(R, _p(arr), r, d, s, _p(was))
     return arr.tolist(), res
 
 

@@ -159,64 +159,78 @@ int orc_decode_time(const orc_inst *I, const int *order, int *start) {
     return cmax;
 }
 
-/* Alg. 5 and Alg. 6 step by step.  The printed loops run k < M-1; they are
- * taken over all M resources here, since eq. 4 constrains every resource. */
+/* Algs. 5 and 6 as the paper gives them, over all M resources (the printed
+ * resource loops stop one short; eq. 4 constrains every resource).
+ * Alg. 5: starting at the precedence earliest start, walk the time units
+ * below UB and keep the length of the current run of units on which every
+ * resource still has the activity's request free; a unit short on any
+ * resource ends the run; the walk stops once the run is d long, and the
+ * activity starts where that run began.  Alg. 6: take the request off every
+ * resource on each unit of [start, start + d).  The free capacities are
+ * kept per unit and resource, starting at R_k. */
 int orc_decode_time_alg5(const orc_inst *I, const int *order, int *start) {
-    int n = I->n, m = I->m, H = I->H;
-    int *tau = (int *)malloc(sizeof(int) * (size_t)(H + 1) * (m > 0 ? m : 1));
-    for (int t = 0; t <= H; t++)
-        for (int k = 0; k < m; k++) tau[(size_t)t * m + k] = I->R[k];
-    int *s = (int *)malloc(sizeof(int) * n);
+    const int n = I->n, m = I->m, ub = I->H;
+    int *avail = (int *)malloc(sizeof(int) * (size_t)(ub + 1) * (m > 0 ? m : 1));
+    for (int t = 0; t <= ub; t++)
+        for (int k = 0; k < m; k++) avail[(size_t)t * m + k] = I->R[k];
+    int *st = (int *)malloc(sizeof(int) * n);
     int cmax = 0;
-    for (int u = 0; u < n; u++) {
-        int a = order[u];
-        int esp = es_prec(I, a, s);
-        /* Alg. 5 */
-        int load = 0, t;
-        for (t = esp; t < H && load < I->d[a]; ++t) {
-            int ok = 1;
-            for (int k = 0; k < m; k++)
-                if (tau[(size_t)t * m + k] < I->r[a * m + k]) { load = 0; ok = 0; }
-            if (ok) ++load;
+    for (int pos = 0; pos < n; pos++) {
+        const int a = order[pos], d = I->d[a];
+        const int *need = I->r + (size_t)a * m;
+        const int lo = es_prec(I, a, st);
+        int t = lo, run = 0;
+        while (run < d && t < ub) {
+            int fits = 1;
+            for (int k = 0; k < m; k++) fits = fits && avail[(size_t)t * m + k] >= need[k];
+            run = fits ? run + 1 : 0;
+            t++;
         }
-        int es = t - load;
-        int sa = imax(esp, es);
-        /* Alg. 6 */
-        for (int k = 0; k < m; k++)
-            for (int x = sa; x < sa + I->d[a]; x++) tau[(size_t)x * m + k] -= I->r[a * m + k];
-        s[a] = sa;
-        cmax = imax(cmax, sa + I->d[a]);
+        const int begin = imax(lo, t - run);
+        for (int x = begin; x < begin + d; x++)
+            for (int k = 0; k < m; k++) avail[(size_t)x * m + k] -= need[k];
+        st[a] = begin;
+        cmax = imax(cmax, begin + d);
     }
-    if (start) memcpy(start, s, sizeof(int) * n);
-    free(tau); free(s);
+    if (start) memcpy(start, st, sizeof(int) * n);
+    free(avail); free(st);
     return cmax;
 }
 
-/* Alg. 4, taken step by step on one resource. */
-int orc_capacity_update(int R, int *c, int r, int d, int s, int *copy) {
-    int requiredEffort = r * d;
-    if (requiredEffort > 0) {
-        int resIdx = 0, copyIdx = 0;
-        int newTime = s + d;
-        while (requiredEffort > 0 && resIdx < R) {
-            g_work[2]++;
-            if (c[resIdx] < newTime) {
-                if (copyIdx >= r) newTime = copy[copyIdx - r];
-                int timeDiff = newTime - imax(c[resIdx], s);
-                if (requiredEffort - timeDiff > 0) {
-                    requiredEffort -= timeDiff;
-                    copy[copyIdx++] = c[resIdx];
-                    c[resIdx] = newTime;
-                } else {
-                    c[resIdx] = imax(c[resIdx], s);
-                    c[resIdx] += requiredEffort;
-                    requiredEffort = 0;
-                }
-            }
-            resIdx = resIdx + 1;
+/* Section 5.1: the capacity array of one resource after an activity takes
+ * r units for d time units from s (what Alg. 4 computes, restated).
+ * c[0..R) holds for every unit of the resource the time from which it is
+ * free, non-increasing, so c[R-r] is the earliest time at which r units are
+ * free (eq. 7).  The activity's effort r*d is charged to the units in array
+ * order.  A unit is charged only while its time is below the bound, which
+ * is the finish s+d until a unit has been raised and then the time the
+ * last raised unit was given.  The first r charged units are raised to
+ * s+d; from then on each charged unit is raised to the time that the unit
+ * charged r charges earlier had before its own raise (the array shifted by
+ * r places; `was` keeps those earlier times).  A raise of a unit from c to
+ * t costs t - max(c, s) of the effort; the unit whose raise would cost all
+ * the effort left, or more, only gets max(c, s) plus what is left, and the
+ * update ends there.  Returns the effort left when the array runs out (0
+ * whenever s is at least eq. 7's resource earliest start). */
+int orc_capacity_update(int R, int *c, int r, int d, int s, int *was) {
+    int left = r * d;
+    int raised = 0;
+    int bound = s + d;
+    for (int j = 0; j < R && left > 0; j++) {
+        g_work[2]++;
+        if (c[j] >= bound) continue;
+        if (raised >= r) bound = was[raised - r];
+        const int from = imax(c[j], s);
+        if (bound - from >= left) {
+            c[j] = from + left;
+            left = 0;
+        } else {
+            left -= bound - from;
+            was[raised++] = c[j];
+            c[j] = bound;
         }
     }
-    return requiredEffort;
+    return left;
 }
 
 /* Capacity-indexed SSGS: eq. 7 for the resource earliest start, Alg. 4 for
@@ -569,7 +583,8 @@ static void exchange_round(const orc_inst *I, const orc_params *p, int dec, sear
     int n = I->n;
     for (int b = 0; b < p->searches; b++) {
         search_t *s = &S[b];
-        if (!s->fired) continue;
+        /* a search that stopped (no feasible move) takes part in no round */
+        if (!s->fired || s->stopped) continue;
         s->fired = 0;
         int k = s->slot;
         record_t *R = &F[k];
@@ -585,9 +600,25 @@ static void exchange_round(const orc_inst *I, const orc_params *p, int dec, sear
     }
 }
 
+/* The state after an exchange round, for the tests (orc_params.round_log). */
+static void log_round(const orc_params *p, int n, const search_t *S, const record_t *F, int round) {
+    if (!p->round_log || round >= p->round_log_cap) return;
+    int *o = p->round_log + (size_t)round * ORC_ROUND_LOG_INTS(n, p->elite, p->searches);
+    for (int k = 0; k < p->elite; k++) {
+        *o++ = F[k].C; *o++ = F[k].IC; *o++ = F[k].reads;
+        memcpy(o, F[k].W, sizeof(int) * n);
+        o += n;
+    }
+    for (int b = 0; b < p->searches; b++) {
+        *o++ = S[b].slot; *o++ = S[b].I_assigned; *o++ = S[b].C_read; *o++ = S[b].C_cur; *o++ = S[b].C_best;
+    }
+}
+
 int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
     int n = I->n, B = p->searches, NF = p->elite, TL = p->tabu_len, IT = p->iterations;
     int P = orc_count_potential(n, p->delta);
+    const int every = p->exchange_every > 1 ? p->exchange_every : 1;
+    int rounds = 0;
     search_t *S = (search_t *)calloc(B, sizeof(search_t));
     for (int b = 0; b < B; b++) {
         S[b].W_cur = (int *)malloc(sizeof(int) * n);
@@ -628,6 +659,7 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
             S[b].C_imp = S[b].C_read = INT_MAX;
         }
         exchange_round(I, p, p->decoder, S, F);
+        log_round(p, n, S, F, rounds++);
     }
 
     int cp = I->cp;
@@ -675,9 +707,10 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
                 s->fired = (s->C_imp < s->C_read) || (s->it_read > s->I_assigned);
             }
         }
-        if (NF > 0 && it < IT - 1) {
+        if (NF > 0 && it < IT - 1 && (it + 1) % every == 0) {
             /* the reads of this round are completed by iteration it + 1 */
             exchange_round(I, p, p->decoder_of_iteration ? p->decoder_of_iteration[it + 1] : p->decoder, S, F);
+            log_round(p, n, S, F, rounds++);
             if (elite_min(F, NF) == cp) gstop = 1;
         }
     }
@@ -700,5 +733,5 @@ int orc_tabu_search(const orc_inst *I, const orc_params *p, orc_results *res) {
     free(S);
     for (int k = 0; k < NF; k++) { free(F[k].W); free(F[k].ring_u); free(F[k].ring_v); free(F[k].tc); }
     free(F);
-    return 0;
+    return rounds;
 }

@@ -43,10 +43,10 @@ int orc_decode_capacity(const orc_inst *inst, const int *order, int *start);
 /* decoder: 1 = time-indexed, 2 = capacity-indexed */
 int orc_decode(const orc_inst *inst, int decoder, const int *order, int *start);
 
-/* Alg. 4 on one resource array c[R] (non-increasing).  copy must hold R ints.
+/* Alg. 4 on one resource array c[R] (non-increasing).  was must hold R ints.
  * Returns the residual required effort when the loop ends (0 when the effort
  * was fully placed). */
-int orc_capacity_update(int R, int *c, int r, int d, int s, int *copy);
+int orc_capacity_update(int R, int *c, int r, int d, int s, int *was);
 
 /* Work counters of the last decode on this thread (instrumentation for the
  * algorithmic work model): profile slots scanned, slots updated, Alg. 4 loop
@@ -113,7 +113,21 @@ typedef struct {
                          experimental set-up (Section 7); set-up decodes
                          (initial orders, records, the first reads) keep
                          `decoder` */
+    int exchange_every;  /* iterations between exchange rounds (0 or 1: after
+                            every iteration, as in the paper); the exchange
+                            conditions only grow while a read is held, so a
+                            search whose condition fired at any iteration of
+                            the block takes part in the round after it */
+    int *round_log;      /* NULL, or room for round_log_cap rounds of
+                            ORC_ROUND_LOG_INTS(N, elite, searches) ints: the
+                            state after every exchange round (the first one
+                            included), written for the tests: per record
+                            k = 0..elite-1: C, IC, reads, W[N]; then per search
+                            b: slot, I_assigned, C_read, C_cur, C_best */
+    int round_log_cap;
 } orc_params;
+
+#define ORC_ROUND_LOG_INTS(n, elite, searches) ((elite) * (3 + (n)) + 5 * (searches))
 
 typedef struct {
     int *best_makespan;      /* [B] */
@@ -129,7 +143,8 @@ typedef struct {
  * (in place); returns the makespan of the result.  Reading in the source. */
 int orc_fbi(const orc_inst *inst, int decoder, int *order);
 
-/* Tabu search (Sections 3, 4, 6; working set of Section 6.1).  Returns 0. */
+/* Tabu search (Sections 3, 4, 6; working set of Section 6.1).  Returns the
+ * number of exchange rounds run (0 without a working set). */
 int orc_tabu_search(const orc_inst *inst, const orc_params *p, orc_results *res);
 
 #ifdef __cplusplus

@@ -233,6 +233,51 @@ def test_capacity_update_invariants():
             c = c2
 
 
+def _usage_envelope(acts, horizon):
+    """Right envelope of the usage of one resource: at t, the largest total
+    request of the placed activities at any time t' >= t."""
+    use = [0] * (horizon + 1)
+    for r, d, s in acts:
+        for t in range(s, s + d):
+            use[t] += r
+    env = [0] * (horizon + 2)
+    for t in range(horizon, -1, -1):
+        env[t] = max(use[t], env[t + 1])
+    return env
+
+
+def test_capacity_update_never_optimistic():
+    """Alg. 4 against the true right envelope of usage (the largest usage at
+    or after t): the array c (unit j free from c[j] on) must never claim
+    fewer busy units than the envelope at any t, so an activity started at
+    eq. 7's time never overloads the resource.  It may claim more (it is
+    conservative): the hand case R=2, (r=1,d=1,s=1) then (r=1,d=1,s=0)
+    gives c=(2,1) while the envelope says one unit until 2 and none after."""
+    c, _ = oracle.capacity_update(2, [0, 0], 1, 1, 1)
+    c, _ = oracle.capacity_update(2, c, 1, 1, 0)
+    assert c == [2, 1]
+    assert _usage_envelope([(1, 1, 1), (1, 1, 0)], 3)[:3] == [1, 1, 0]
+    rng = synth.Stream(123, 4)
+    conservative = 0
+    for trial in range(3000):
+        R = 1 + rng.below(6)
+        c = [0] * R
+        acts = []
+        for step in range(1 + rng.below(7)):
+            r = 1 + rng.below(R)
+            d = 1 + rng.below(4)
+            s = c[R - r] + rng.below(3)      # at or after eq. 7's resource start
+            c, res = oracle.capacity_update(R, c, r, d, s)
+            assert res == 0
+            acts.append((r, d, s))
+            horizon = max(x[2] + x[1] for x in acts) + 1
+            env = _usage_envelope(acts, horizon)
+            busy = [sum(1 for cj in c if cj > t) for t in range(horizon + 1)]
+            assert all(busy[t] >= env[t] for t in range(horizon + 1)), (R, acts, c)
+            conservative += any(busy[t] > env[t] for t in range(horizon + 1))
+    assert conservative > 0
+
+
 # --------------------------------------------------------------------------
 # brute force on tiny instances
 
@@ -248,7 +293,9 @@ def test_ssgs_min_over_orders_is_optimum(idx):
     ti = [o.decode(W, TIME) for W in orders]
     ci = [o.decode(W, CAP) for W in orders]
     assert min(ti) == opt
-    assert min(ci) >= opt
+    # the capacity-indexed decoder never back-fills, yet some list still
+    # reaches the optimum (an optimal schedule's activities by start time)
+    assert min(ci) == opt
     for W in orders:
         for dec in (TIME, CAP):
             c, s = o.decode(W, dec, starts=True)
@@ -464,8 +511,12 @@ def test_cooperative_search_invariants(dec):
         assert r1["best_makespan"][b] >= cp
         done = r1["iterations_done"][b]
         tr = r1["trajectory"][b, :done]
-        for it in range(done):
-            assert tr[it, 3] <= tr[it, 2] or tr[it, 3] < 2 ** 31 - 1
+        # the best never rises, is never above the move just taken, and the
+        # final best is the last row's
+        assert (np.diff(tr[:, 3]) <= 0).all()
+        assert (tr[:, 3] <= tr[:, 2]).all()
+        assert done == 0 or tr[-1, 3] == r1["best_makespan"][b]
+        assert (r1["trajectory"][b, done:] == -1).all()
     for k in range(4):
         assert r1["elite_makespan"][k] == o.decode(r1["elite_order"][k], dec)
         assert o.is_feasible_order(r1["elite_order"][k])
