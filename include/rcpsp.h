@@ -173,6 +173,28 @@ typedef struct {
                                  strictly decreases, with the search's decoder.
                                  Search plans only (batches and servers reject
                                  it).  0 = off */
+    int32_t exchange_every;   /* iterations between working-set exchange rounds
+                                 (Section 6.1): 0 or 1 = after every iteration,
+                                 as in the paper; k > 1 = after iterations
+                                 k, 2k, ... (a search whose exchange condition
+                                 fired at any iteration of the block takes part;
+                                 the conditions only grow while a read is held).
+                                 Search plans only (batches, servers and
+                                 re-selecting searches take 0 or 1) */
+    int32_t time_budget_us;   /* wall-time budget of a run in microseconds,
+                                 counted on the device clock from the start of
+                                 the run's first kernel; 0 = none.  Checked at
+                                 iteration boundaries: with a working set the
+                                 exchange round after an iteration ends the run
+                                 when the budget has passed (no round, no further
+                                 iteration); independent searches each stop at
+                                 their first iteration boundary past it.  The
+                                 results equal those of a run of that many
+                                 iterations whose eq. 8 still takes `iterations`
+                                 as I_block (iterations_done tells how many).
+                                 Search plans only (batches reject it; servers
+                                 take it as the request's budget when submit's
+                                 budget_us is 0) */
 } rcpsp_search_params;
 
 /* Results; every pointer may be NULL (not copied).  Sizes in parentheses. */
@@ -325,6 +347,17 @@ typedef struct {
 } rcpsp_batch_info;
 rcpsp_status rcpsp_batch_get_info(const rcpsp_batch *b, rcpsp_batch_info *out);
 void rcpsp_batch_destroy(rcpsp_batch *b);
+
+/* create + run + results + destroy of a batch: count instances, instance i
+ * searched with per_inst[i] (its own searches, working set and seed; the
+ * results equal rcpsp_tabu_search's for that instance and parameters);
+ * out[i] receives its results as rcpsp_search_results would (each out[i]
+ * with its own caller buffers, any of them NULL).  Synchronous on
+ * hip_stream.  Errors: those of rcpsp_batch_create, rcpsp_batch_run and
+ * rcpsp_batch_results (the first failing instance's). */
+rcpsp_status rcpsp_tabu_search_batch(const rcpsp_instance *const *inst, int32_t count,
+                                     const rcpsp_search_params *per_inst, rcpsp_search_result *out,
+                                     void *hip_stream);
 
 /* Decoder and launch shape for one instance and search configuration.
  * Section 5.4 fixes the resource evaluation algorithm per instance before the

@@ -3,13 +3,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rcpsp.h"
@@ -664,11 +668,16 @@ static hipError_t enqueue_run(rcpsp_search *s, hipStream_t st, RunTimer *tm) {
         if ((e = launch_decode_records(a, T, s->nw, s->dec, s->lds, st)) != hipSuccess) return e;
         if ((e = round(0, 1)) != hipSuccess) return e;
         ++nrd;
-        for (int it = 0; it < p.iterations; ++it) {
-            if ((e = search(it, 1)) != hipSuccess) return e;
+        // blocks of `every` iterations, each followed by an exchange round
+        // (none after the last); exports and rounds alternate their buffers
+        // by the parity of the block
+        const int every = a.every;
+        for (int it = 0; it < p.iterations; it += every) {
+            const int n = std::min(every, p.iterations - it);
+            if ((e = search(it, n)) != hipSuccess) return e;
             ++nit;
-            if (it < p.iterations - 1) {
-                if ((e = round(it & 1, 0)) != hipSuccess) return e;
+            if (it + n < p.iterations) {
+                if ((e = round((it / every) & 1, 0)) != hipSuccess) return e;
                 ++nrd;
             }
         }
@@ -757,6 +766,39 @@ static rcpsp_status plan_grid(const rcpsp_search *s, int *grid) {
     return RCPSP_OK;
 }
 
+// Device wall-clock ticks per microsecond, measured once per device: two
+// readings of the clock kernel 20 ms apart on the host's steady clock (the
+// rate the driver reports has disagreed with the counter).
+static rcpsp_status wall_ticks_per_us(double *out) {
+    static std::mutex mu;
+    static std::map<int, double> rate;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto found = rate.find(dev);
+    if (found != rate.end()) {
+        *out = found->second;
+        return RCPSP_OK;
+    }
+    long long *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(long long)));
+    long long ticks[2] = {0, 0};
+    std::chrono::steady_clock::time_point host[2];
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        if (i) std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        e = launch_clock(d, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(&ticks[i], d, sizeof(long long), hipMemcpyDeviceToHost);
+        host[i] = std::chrono::steady_clock::now();
+    }
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(RCPSP_E_DEVICE, "device clock: %s", hipGetErrorString(e));
+    const double us = std::chrono::duration<double, std::micro>(host[1] - host[0]).count();
+    if (!(us > 0.0) || ticks[1] <= ticks[0]) return fail(RCPSP_E_DEVICE, "device wall clock does not advance");
+    rate[dev] = *out = (double)(ticks[1] - ticks[0]) / us;
+    return RCPSP_OK;
+}
+
 // Layout and device state of a plan (no launches).
 rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     const rcpsp_instance *I = s->inst;
@@ -782,6 +824,14 @@ rcpsp_status rcpsp::alloc_plan(rcpsp_search *s) {
     a.count_work = p.count_work ? 1 : 0;
     a.full_decode = p.full_decode ? 1 : 0;
     a.seed = p.seed;
+    a.every = std::max(1, p.exchange_every);
+    a.budget_ticks = 0;
+    if (p.time_budget_us > 0) {
+        double per_us = 0.0;
+        rcpsp_status cst = wall_ticks_per_us(&per_us);
+        if (cst != RCPSP_OK) return cst;
+        a.budget_ticks = std::max(1ll, (long long)std::llround(per_us * (double)p.time_budget_us));
+    }
     const int tcn = N * s->tcw;
     HIP_TRY(dalloc(s, &a.sc, sizeof(SearchScalars) * B));
     HIP_TRY(dalloc(s, &a.Wcur, sizeof(uint16_t) * (size_t)B * N2));
@@ -1000,6 +1050,7 @@ extern "C" rcpsp_status rcpsp_tabu_search_hosted(const rcpsp_instance *inst, con
     if (p.count_work) return fail(RCPSP_E_ARG, "count_work is not available for host-driven searches");
     if (p.eval != 0 && p.eval != inst->eval)
         return fail(RCPSP_E_ARG, "host-driven searches decode with the instance's decoder");
+    if (p.time_budget_us != 0) return fail(RCPSP_E_ARG, "host-driven searches take no time budget");
     hipStream_t hs = (hipStream_t)hip_stream;
     const int N = inst->n, B = p.searches, iters = p.iterations, tl = p.tabu_len;
     // initial orders and makespans
@@ -1139,6 +1190,8 @@ extern "C" rcpsp_status rcpsp_tabu_search_reselect(const rcpsp_instance *inst, c
     rcpsp_status st = validate_params(p);
     if (st != RCPSP_OK) return st;
     if (p.eval != 0) return fail(RCPSP_E_ARG, "the decoder is chosen by timing (eval must be 0)");
+    if (p.exchange_every > 1 || p.time_budget_us != 0)
+        return fail(RCPSP_E_ARG, "re-selecting searches exchange after every iteration and take no time budget");
     if ((long long)p.searches * std::max(p.iterations, 1) * 4 > (1ll << 40))
         return fail(RCPSP_E_TOO_LARGE, "trajectory too large");
     hipStream_t hs = (hipStream_t)hip_stream;
@@ -1405,6 +1458,8 @@ rcpsp_status rcpsp::validate_params(const rcpsp_search_params &p) {
     if (p.phi_max < 0 || p.phi_steps < 0) return fail(RCPSP_E_ARG, "phi_max and phi_steps must be >= 0");
     if (p.eval < 0 || p.eval > 2) return fail(RCPSP_E_ARG, "unknown decoder %d", p.eval);
     if (p.fbi != 0 && p.fbi != 1) return fail(RCPSP_E_ARG, "fbi must be 0 or 1");
+    if (p.exchange_every < 0) return fail(RCPSP_E_ARG, "exchange_every must be >= 0");
+    if (p.time_budget_us < 0) return fail(RCPSP_E_ARG, "time_budget_us must be >= 0");
     return RCPSP_OK;
 }
 
@@ -1420,6 +1475,8 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         rcpsp_status st = validate_params(p);
         if (st != RCPSP_OK) return st;
         if (p.fbi) return fail(RCPSP_E_ARG, "batch member %d: forward-backward improvement is for search plans only", i);
+        if (p.exchange_every > 1 || p.time_budget_us != 0)
+            return fail(RCPSP_E_ARG, "batch member %d: batches exchange after every iteration and take no time budget", i);
         if (p.threads == 0) p.threads = 64;
         p.count_work = 0;
         // the threads per search (chosen per group by the autotuner) are a
@@ -1791,4 +1848,18 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         info->trials = trials;
     }
     return RCPSP_OK;
+}
+
+extern "C" rcpsp_status rcpsp_tabu_search_batch(const rcpsp_instance *const *inst, int32_t count,
+                                                const rcpsp_search_params *per_inst, rcpsp_search_result *out,
+                                                void *hip_stream) {
+    if (!inst || !per_inst || !out) return fail(RCPSP_E_ARG, "null pointer");
+    if (count < 1) return fail(RCPSP_E_ARG, "count must be >= 1");
+    rcpsp_batch *b = nullptr;
+    rcpsp_status st = rcpsp_batch_create(inst, count, per_inst, hip_stream, &b);
+    if (st != RCPSP_OK) return st;
+    st = rcpsp_batch_run(b, hip_stream);
+    for (int i = 0; st == RCPSP_OK && i < count; ++i) st = rcpsp_batch_results(b, i, &out[i], hip_stream);
+    rcpsp_batch_destroy(b);
+    return st;
 }

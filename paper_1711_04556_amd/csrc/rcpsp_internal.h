@@ -72,6 +72,7 @@ struct Global {
     int gstop;
     int queue;     // next search of the current iteration launch (plain plans)
     int pad;
+    long long deadline;   // device wall-clock tick after which no iteration starts (time budget)
 };
 
 constexpr uint64_t kStreamInit = 0ull;
@@ -85,6 +86,9 @@ struct SearchArgs {
     int it0, n_it;
     int grid;      // iteration-kernel workgroups (each takes searches from A.g->queue)
     int decay_len;
+    int every;     // iterations between exchange rounds (>= 1)
+    int pad_every;
+    long long budget_ticks;   // time budget in device wall-clock ticks (0 = none)
     unsigned long long seed;
     SearchScalars *sc;
     uint16_t *Wcur, *Wimp, *Wbest;       // [B][N2] (N2 = N rounded up to even)

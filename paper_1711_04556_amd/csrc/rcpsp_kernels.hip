@@ -580,6 +580,11 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
         } else if (COUNT) {
             w_ops += 2 * d;
         }
+        // 8-bit finish times hold at most 255: a later finish (possible for
+        // an activity that requests nothing, which never touches the
+        // profile) takes the candidate to the long-profile path like a
+        // profile overflow
+        if constexpr (FB == 8) over = over || (s + d > 255);
         M.template stf<FB>(fo, s + d);
         q = qn;
         r = rn;
@@ -594,13 +599,14 @@ __device__ int decode_ti(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
     return p1 == D.n ? M.template ldf<FB>(STRIDE == 1 ? (FB / 8) * (uint32_t)(D.n - 1) : offF<STRIDE, FB>(D.n - 1)) : 0;
 }
 
-// Capacity-indexed: eq. 7 gives the resource earliest start, Alg. 4 updates
-// each c_k.  c_k holds R_k 16-bit times; Alg. 4's auxiliary copy array is
-// only read r_ik entries behind its write position, so a ring of copy_p
-// (a power of two >= every request) entries replaces it.  Alg. 4 does
-// nothing but advance its index while c_k[i] >= s + d; because c_k stays
-// non-increasing (s is never below the eq. 7 start), those leading steps are
-// skipped by a binary search for the first entry below s + d.
+// Capacity-indexed: eq. 7 gives the resource earliest start, the update of
+// Section 5.1 (Alg. 4) raises the c_k entries.  c_k holds R_k 16-bit times
+// (the time from which each unit is free, non-increasing); the times the
+// raised units had before are only read r_ik raises later, so a ring of
+// copy_p (a power of two >= every request) entries holds them.  Units free
+// only at or after s + d are passed over; before the first raise they form
+// a prefix (c_k stays non-increasing because s is never below the eq. 7
+// start), which a binary search skips.
 // With COUNT, *wk receives one operation per activity, per predecessor read,
 // per eq. 7 lookup and per Alg. 4 loop step (skipped steps included).
 template <int STRIDE, bool COUNT = false>
@@ -636,32 +642,33 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 const int rk = S.reqk[a * Mr + k];
                 if (rk == 0) continue;
                 const int cb = ce0 + (int)S.res[2 * k + 1], Rk = (int)S.res[2 * k];
-                int effort = rk * d, ci = 0, newTime = s + d;
+                // effort r*d charged to the units below the bound (the finish,
+                // then the time the last raised unit got); the first r raised
+                // to the finish, later ones to the time of the unit raised r
+                // raises before (the ring), the last one by what is left
+                int left = rk * d, raised = 0, bound = s + d;
                 int lo = 0, hi = Rk;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if (M.ld16(cb + mid) < newTime) hi = mid;
+                    if (M.ld16(cb + mid) < bound) hi = mid;
                     else lo = mid + 1;
                 }
-                int ri = lo;
                 if (COUNT) w_ops += lo;
-                while (effort > 0 && ri < Rk) {
+                for (int j = lo; j < Rk && left > 0; ++j) {
                     if (COUNT) ++w_ops;
-                    const int cv = M.ld16(cb + ri);
-                    if (cv < newTime) {
-                        if (ci >= rk) newTime = M.ld16(pe0 + ((ci - rk) & pmask));
-                        const int td = newTime - max(cv, s);
-                        if (effort - td > 0) {
-                            effort -= td;
-                            M.st16(pe0 + (ci & pmask), cv);
-                            ++ci;
-                            M.st16(cb + ri, newTime);
-                        } else {
-                            M.st16(cb + ri, max(cv, s) + effort);
-                            effort = 0;
-                        }
+                    const int cv = M.ld16(cb + j);
+                    if (cv >= bound) continue;
+                    if (raised >= rk) bound = M.ld16(pe0 + ((raised - rk) & pmask));
+                    const int from = max(cv, s);
+                    if (bound - from >= left) {
+                        M.st16(cb + j, from + left);
+                        left = 0;
+                    } else {
+                        left -= bound - from;
+                        M.st16(pe0 + (raised & pmask), cv);
+                        ++raised;
+                        M.st16(cb + j, bound);
                     }
-                    ++ri;
                 }
             }
         }
@@ -993,6 +1000,12 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
         } else if (COUNT && g == 0) {
             w_ops += 2 * d;
         }
+        // 8-bit finish times hold at most 255 (an activity without requests
+        // can finish past the profile): report overflow (group-uniform)
+        if (FB == 8 && s + d > 255) {
+            ovf = true;
+            return -1;
+        }
         if (COUNT && g == 0) w_ops += 1 + np;
         if (g == 0) fset(a, s + d);
         __builtin_amdgcn_wave_barrier();
@@ -1049,33 +1062,31 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
                 if (rk == 0) continue;
                 uint16_t *ck = Cc + (int)S.res[2 * k + 1];
                 const int Rk = (int)S.res[2 * k];
-                int effort = rk * d, ci = 0, newTime = s + d;
-                // leading entries >= s + d are left alone (see decode_ci)
+                // the update of decode_ci; leading units at or past the
+                // finish are passed over by a binary search
+                int left = rk * d, raised = 0, bound = s + d;
                 int lo = 0, hi = Rk;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if ((int)ck[mid] < newTime) hi = mid;
+                    if ((int)ck[mid] < bound) hi = mid;
                     else lo = mid + 1;
                 }
-                int ri = lo;
                 if (COUNT) w_ops += lo;
-                while (effort > 0 && ri < Rk) {
+                for (int j = lo; j < Rk && left > 0; ++j) {
                     if (COUNT) ++w_ops;
-                    const int cv = ck[ri];
-                    if (cv < newTime) {
-                        if (ci >= rk) newTime = ring[(ci - rk) & pmask];
-                        const int td = newTime - max(cv, s);
-                        if (effort - td > 0) {
-                            effort -= td;
-                            ring[ci & pmask] = (uint16_t)cv;
-                            ++ci;
-                            ck[ri] = (uint16_t)newTime;
-                        } else {
-                            ck[ri] = (uint16_t)(max(cv, s) + effort);
-                            effort = 0;
-                        }
+                    const int cv = ck[j];
+                    if (cv >= bound) continue;
+                    if (raised >= rk) bound = ring[(raised - rk) & pmask];
+                    const int from = max(cv, s);
+                    if (bound - from >= left) {
+                        ck[j] = (uint16_t)(from + left);
+                        left = 0;
+                    } else {
+                        left -= bound - from;
+                        ring[raised & pmask] = (uint16_t)cv;
+                        ++raised;
+                        ck[j] = (uint16_t)bound;
                     }
-                    ++ri;
                 }
             }
         }
@@ -1362,6 +1373,8 @@ __device__ void reset_unit(const SearchArgs &A, int i, uint16_t *w) {
         A.g->Cstar = 0x7fffffff;
         A.g->gstop = 0;
         A.g->queue = 0;
+        // a time budget runs from the start of the run's first kernel
+        A.g->deadline = A.budget_ticks > 0 ? (long long)wall_clock64() + A.budget_ticks : 0;
     }
     __threadfence();
     __syncthreads();
@@ -1526,6 +1539,7 @@ __device__ inline void copy_dw(uint32_t *dst, const uint32_t *src, int n) {
 struct StepShared {
     SearchScalars sc;
     int dirty_best, dirty_imp;
+    int expired;   // independent searches: the time budget has passed
 };
 
 // Search b, iterations [it0, it0 + n_it): complete a pending read (record
@@ -1633,7 +1647,16 @@ __device__ __attribute__((always_inline)) void search_step(const SearchArgs &A, 
 
     TabuSrc tb{S.tc, nullptr, A.tcw, N};
     for (int it = it0; it < it_end; ++it) {
-        bool stop = sc.it_done >= A.iters || (!coop && sc.C_best == D.cp);
+        // independent searches check a time budget at every iteration
+        // boundary (one reading of the clock, shared by the workgroup); with
+        // a working set the exchange round does
+        bool past = false;
+        if (!coop && A.budget_ticks > 0) {
+            if (tid == 0) ss.expired = (long long)wall_clock64() >= A.g->deadline;
+            __syncthreads();
+            past = ss.expired != 0;
+        }
+        bool stop = sc.it_done >= A.iters || (!coop && sc.C_best == D.cp) || past;
         const int asp = coop ? min(sc.C_best, A.g->Cstar) : sc.C_best;
         __syncthreads();
         if (stop) {
@@ -1697,9 +1720,11 @@ __device__ __attribute__((always_inline)) void search_step(const SearchArgs &A, 
         }
         __syncthreads();
     }
-    // export for the exchange round
+    // export for the exchange round (two buffers by the parity of the block
+    // of iterations between rounds: readers of this round's exports run in
+    // the next block, while their writers may export again)
     if (coop && sc.fired && sc.C_imp < sc.C_read) {
-        const int par = it0 & 1;
+        const int par = (it0 / A.every) & 1;
         const size_t r = (size_t)par * A.B + b;
         copy_dw<T>(reinterpret_cast<uint32_t *>(A.Xw + r * N2), reinterpret_cast<uint32_t *>(S.Wimp), N2 / 2);
         copy_dw<T>(A.Xring + r * A.tl, S.ring, A.tl);
@@ -1855,6 +1880,20 @@ __device__ void exchange_round(const SearchArgs &A, int parity, int init, int *r
 
 __global__ __launch_bounds__(256) void k_round(SearchArgs A, int parity, int init) {
     extern __shared__ int rs[];
+    // a time budget that has passed ends the run at this iteration boundary:
+    // no round, and every later iteration launch finds the stop flag
+    if (!init && A.budget_ticks > 0) {
+        __shared__ int past;
+        if (threadIdx.x == 0) past = (long long)wall_clock64() >= A.g->deadline;
+        __syncthreads();
+        if (past) {
+            if (threadIdx.x == 0) {
+                A.g->gstop = 1;
+                A.g->queue = 0;
+            }
+            return;
+        }
+    }
     exchange_round<256>(A, parity, init, rs);
     if (threadIdx.x == 0) A.g->queue = 0;   // the next iteration launch starts from search 0
 }

@@ -633,7 +633,14 @@ extern "C" rcpsp_status rcpsp_server_submit(rcpsp_server *s, const rcpsp_instanc
     if (params->iterations < 1 || params->iterations >= kServeNoIteration)
         return fail(RCPSP_E_ARG, "a served request needs an iteration allowance in 1..%d", kServeNoIteration - 1);
     if (params->fbi) return fail(RCPSP_E_ARG, "forward-backward improvement is for search plans only");
+    if (params->exchange_every > 1) return fail(RCPSP_E_ARG, "served requests exchange after every iteration");
     if (budget_us < 0) return fail(RCPSP_E_ARG, "negative budget");
+    // the request's budget (the parameters' one when none is given here) is
+    // checked by the serving kernel, not by the plan's own rounds
+    if (budget_us == 0) budget_us = params->time_budget_us;
+    rcpsp_search_params q = *params;
+    q.time_budget_us = 0;
+    params = &q;
     // footprint: the plan's state in the arena and its workgroup's LDS
     MeasureAllocator m;
     rcpsp_search probe;

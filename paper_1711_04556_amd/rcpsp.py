@@ -44,8 +44,9 @@ class rcpsp_move(ctypes.Structure):
 class rcpsp_search_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
-        "profile_len", "record_trajectory", "count_work", "full_decode", "eval", "lanes")] + [("seed", ctypes.c_uint64),
-                                                                                              ("fbi", ctypes.c_int32)]
+        "profile_len", "record_trajectory", "count_work", "full_decode", "eval", "lanes")] + [
+        ("seed", ctypes.c_uint64), ("fbi", ctypes.c_int32), ("exchange_every", ctypes.c_int32),
+        ("time_budget_us", ctypes.c_int32)]
 
 
 class rcpsp_tuning(ctypes.Structure):
@@ -170,6 +171,9 @@ def lib():
     L.rcpsp_batch_get_info.restype = ctypes.c_int
     L.rcpsp_batch_destroy.argtypes = [vp]
     L.rcpsp_batch_destroy.restype = None
+    L.rcpsp_tabu_search_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(rcpsp_search_params),
+                                          ctypes.POINTER(rcpsp_search_result), vp]
+    L.rcpsp_tabu_search_batch.restype = ctypes.c_int
     L.rcpsp_batch_autotune.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(rcpsp_search_params), i32, i32, vp,
                                        ctypes.POINTER(rcpsp_search_params), ctypes.POINTER(rcpsp_batch_tuning)]
     L.rcpsp_batch_autotune.restype = ctypes.c_int
@@ -266,10 +270,10 @@ class Instance:
         tb = None
         if tabu is not None:
             tb = np.ascontiguousarray(np.asarray(tabu, dtype=np.uint8).reshape(self.n * self.n))
-        _check(lib().rcpsp_evaluate_neighbourhood(self.h, _ptr(_i32(order)), swap_range,
-                                                  tb.ctypes.data if tb is not None else None, aspiration,
-                                                  _ptr(mk), mk.size, ctypes.byref(npot), ctypes.byref(best),
-                                                  _stream_ptr(stream)))
+        fn = lib().rcpsp_evaluate_neighbourhood
+        order_a = _i32(order)
+        _check(fn(self.h, _ptr(order_a), swap_range, tb.ctypes.data if tb is not None else None, aspiration,
+                  _ptr(mk), mk.size, ctypes.byref(npot), ctypes.byref(best), _stream_ptr(stream)))
         return mk[:P], dict(u=best.u, v=best.v, makespan=best.makespan, n_feasible=best.n_feasible)
 
     def evaluate_neighbourhood_device(self, order, swap_range: int, makespan, best, tabu=None,
@@ -284,10 +288,11 @@ class Instance:
 def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int = 1, elite: int = 0,
                   phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
                   record_trajectory: bool = True, count_work: bool = False, full_decode: bool = False,
-                  eval: int = EVAL_AUTO, seed: int = 1, lanes: int = 0, fbi: bool = False) -> rcpsp_search_params:
+                  eval: int = EVAL_AUTO, seed: int = 1, lanes: int = 0, fbi: bool = False, exchange_every: int = 0,
+                  time_budget_us: int = 0) -> rcpsp_search_params:
     return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
                                profile_len, int(record_trajectory), int(count_work), int(full_decode), eval, lanes,
-                               seed, int(fbi))
+                               seed, int(fbi), exchange_every, time_budget_us)
 
 
 def autotune(instance: "Instance", params: rcpsp_search_params, trial_iterations: int = 10, stream=None):
@@ -451,6 +456,40 @@ class Batch:
     def results(self, index: int, stream=None, orders: bool = True, trajectory: bool = True) -> dict:
         return _results(lib().rcpsp_batch_results, (self.h, index), self.params[index], self.instances[index].n,
                         stream, orders, trajectory)
+
+
+def tabu_search_batch(instances: Sequence[Instance], params, stream=None, orders: bool = True,
+                      trajectory: bool = True) -> list:
+    """rcpsp_tabu_search_batch: one batch created, run, read and destroyed;
+    returns one results dict per instance (as SearchPlan.results)."""
+    if not isinstance(params, (list, tuple)):
+        params = [params] * len(instances)
+    n = len(instances)
+    hs = (ctypes.c_void_p * n)(*[i.h.value for i in instances])
+    ps = (rcpsp_search_params * n)(*params)
+    outs, ress = [], (rcpsp_search_result * n)()
+    for i, p in enumerate(params):
+        B, N, F = p.searches, instances[i].n, p.elite
+        o = dict(best_makespan=np.zeros(B, np.int32), iterations_done=np.zeros(B, np.int32),
+                 evaluations=np.zeros(B, np.int64), best_order=np.zeros((B, N), np.int32) if orders else None,
+                 trajectory=np.zeros((B, p.iterations, 4), np.int32) if (trajectory and p.record_trajectory) else None,
+                 elite_makespan=np.zeros(max(F, 1), np.int32),
+                 elite_order=np.zeros((max(F, 1), N), np.int32) if orders else None)
+        ress[i] = rcpsp_search_result(*[o[k].ctypes.data if o[k] is not None else None for k in
+                                        ("best_makespan", "best_order", "iterations_done", "evaluations",
+                                         "trajectory", "elite_makespan", "elite_order")])
+        outs.append(o)
+    _check(lib().rcpsp_tabu_search_batch(hs, n, ps, ress, _stream_ptr(stream)))
+    for i, o in enumerate(outs):
+        F = params[i].elite
+        o["elite_makespan"] = o["elite_makespan"][:F]
+        if o["elite_order"] is not None:
+            o["elite_order"] = o["elite_order"][:F]
+        o["global_best"] = ress[i].global_best
+        o["total_evaluations"] = ress[i].total_evaluations
+        o["overflow_decodes"] = ress[i].overflow_decodes
+        o["total_work"] = ress[i].total_work
+    return outs
 
 
 class Server:

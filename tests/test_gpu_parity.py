@@ -640,3 +640,72 @@ def test_neighbourhood_large_instances(rc, dec, n):
                 w = list(Wb)
                 w[u], w[u + 1] = w[u + 1], w[u]
                 assert mk_g[j] == ob.decode(w, dec)
+
+
+def _stretched(seed, factor):
+    """Activities that request no resource made `factor` times longer: they
+    never touch a lane's profile, so schedules run past 255 time units
+    while every resource-requesting activity still fits a short profile."""
+    b = synth.generate(40, 2, 20, 0.3, rs=0.2, seed=seed)
+    d = list(b.duration)
+    for i in range(1, b.n - 1):
+        if all(b.r(i, k) == 0 for k in range(b.m)):
+            d[i] *= factor
+    return synth.Instance(n=b.n, m=b.m, duration=d, capacity=b.capacity, request=b.request, succ=b.succ,
+                          name=f"stretched{seed}x{factor}")
+
+
+def test_8bit_finish_times_past_255_hand_case(rc):
+    """0->1->2->4, 0->3->4, one resource of 1 unit; d = (0, 250, 10, 1, 0),
+    r = (0, 1, 0, 1, 0).  Order (0,1,3,2,4): 1 on [0,250), 3 on [250,251),
+    2 (no request) on [250,260): C_max = 260, past what an 8-bit finish time
+    holds.  By hand, the only feasible swap of (0,1,2,3,4) within range 2 is
+    (2,3), giving 260; the order itself also gives 260."""
+    inst = synth.Instance(n=5, m=1, duration=[0, 250, 10, 1, 0], capacity=[1], request=[0, 1, 0, 1, 0],
+                          succ=[[1, 3], [2], [4], [4], []])
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    mk_g, best_g = gi.evaluate_neighbourhood([0, 1, 2, 3, 4], 2)
+    assert mk_g.tolist() == [-1, -1, 260]
+    assert [best_g["u"], best_g["v"], best_g["makespan"], best_g["n_feasible"]] == [2, 3, 260, 1]
+    mk_o, best_o = orc.evaluate_neighbourhood([0, 1, 2, 3, 4], 2, TIME)
+    assert mk_o.tolist() == mk_g.tolist()
+    plan = rc.SearchPlan(gi, rc.search_params(2, 2, 6, searches=3, threads=64, seed=1))
+    assert plan.config["finish_bits"] == 8
+    plan.run()
+    g = plan.results()
+    plan.close()
+    _compare_search(g, orc.tabu_search(2, 2, 6, searches=3, decoder=TIME, seed=1))
+
+
+@pytest.mark.parametrize("seed,factor", [(1513, 3), (1508, 2), (1505, 2)])
+@pytest.mark.parametrize("threads", [64, 192])
+def test_8bit_finish_times_past_255(rc, seed, factor, threads):
+    """Lane states with 8-bit finish times (profile at most 255 units) on
+    instances whose schedules pass 255 through activities without requests:
+    every such candidate must take the long-profile path, and neighbourhoods
+    and searches equal the oracle."""
+    inst = _stretched(seed, factor)
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    past = 0
+    for k in range(3):
+        W = orc.initial_order(seed, k)
+        mk_g, best_g = gi.evaluate_neighbourhood(W, 10)
+        mk_o, best_o = orc.evaluate_neighbourhood(W, 10, TIME)
+        assert np.array_equal(mk_g, mk_o), (k, np.nonzero(mk_g != mk_o)[0][:10])
+        assert [best_g["u"], best_g["v"], best_g["makespan"], best_g["n_feasible"]] == best_o
+        past += int((mk_o > 255).sum())
+    assert past > 0
+    for elite in (0, 4):
+        kw = dict(swap_range=10, tabu_len=40, iterations=30, searches=6, elite=elite, phi_max=2, phi_steps=4,
+                  seed=seed)
+        # a lane profile of at most 255 units that fits the workgroup's LDS
+        plan = rc.SearchPlan(gi, rc.search_params(threads=threads, eval=TIME, profile_len=200 if threads == 64
+                                                  else 150, **kw))
+        assert plan.config["finish_bits"] == 8 and plan.config["profile_len"] <= 255
+        plan.run()
+        g = plan.results()
+        plan.close()
+        o = orc.tabu_search(10, 40, 30, searches=6, elite=elite, phi_max=2, phi_steps=4, decoder=TIME, seed=seed)
+        _compare_search(g, o, elite=elite)
