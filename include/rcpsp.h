@@ -124,6 +124,26 @@ rcpsp_status rcpsp_evaluate_neighbourhood_device(const rcpsp_instance *inst, con
                                                  int32_t aspiration, int32_t *makespan,
                                                  rcpsp_move *best, void *hip_stream);
 
+/* The host variant above without any device allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and errors as rcpsp_evaluate_neighbourhood.  The order, the tabu matrix,
+ * the makespans and the best move are staged through one fixed scratch
+ * array of RCPSP_NOALLOC_SCRATCH_BYTES in device memory per GPU, reserved
+ * when the library is loaded and held until the process ends; every call
+ * overwrites what the previous one left there (nothing in it has to start
+ * at zero).  A call needs 4N + 4P + 16 bytes, plus N*N with a tabu matrix,
+ * each part rounded up to 256 bytes; beyond RCPSP_NOALLOC_SCRATCH_BYTES it
+ * returns RCPSP_E_TOO_LARGE.  Calls that overlap on one GPU (from several
+ * host threads, or on several streams) race on the array: the caller
+ * serialises them.  Synchronous on hip_stream. */
+#define RCPSP_NOALLOC_SCRATCH_BYTES (1u << 20)
+rcpsp_status rcpsp_evaluate_neighbourhood_noalloc(const rcpsp_instance *inst, const int32_t *order,
+                                                  int32_t swap_range, const uint8_t *tabu,
+                                                  int32_t aspiration, int32_t *makespan, int32_t cap,
+                                                  int32_t *n_potential, rcpsp_move *best,
+                                                  void *hip_stream);
+
 /* Number of potential swap moves P for (N, swap_range). */
 int32_t rcpsp_potential_moves(int32_t n, int32_t swap_range);
 

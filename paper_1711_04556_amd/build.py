@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librcpsp.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = [os.path.join(CSRC, "rcpsp_host.cpp"), os.path.join(CSRC, "rcpsp_serve.cpp"),
-           os.path.join(CSRC, "rcpsp_kernels.hip")]
+           os.path.join(CSRC, "rcpsp_kernels.hip"), os.path.join(CSRC, "rcpsp_noalloc.hip")]
 HEADERS = [os.path.join(ROOT, "include", "rcpsp.h"), os.path.join(CSRC, "rcpsp_internal.h"),
            os.path.join(CSRC, "rcpsp_launch.h"), os.path.join(CSRC, "rcpsp_runtime.h")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",

@@ -470,7 +470,7 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
 // ---------------------------------------------------------------------------
 // neighbourhood evaluation
 
-static rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, int32_t delta, const uint8_t *tabu,
+rcpsp_status rcpsp::eval_device(const rcpsp_instance *I, const int32_t *order, int32_t delta, const uint8_t *tabu,
                                 int32_t asp, int32_t *makespan, rcpsp_move *best, hipStream_t st) {
     if (delta < 1 || delta > kMaxDelta) return fail(RCPSP_E_ARG, "swap_range %d outside 1..%d", delta, kMaxDelta);
     const int P = potential_moves(I->n, delta);
@@ -513,7 +513,7 @@ extern "C" rcpsp_status rcpsp_evaluate_neighbourhood_device(const rcpsp_instance
     return eval_device(inst, order, swap_range, tabu, aspiration, makespan, best, (hipStream_t)hip_stream);
 }
 
-static bool feasible_order(const rcpsp_instance *I, const int32_t *order) {
+bool rcpsp::feasible_order(const rcpsp_instance *I, const int32_t *order) {
     const int n = I->n;
     if (order[0] != 0 || order[n - 1] != n - 1) return false;
     std::vector<int> pos(n, -1);

@@ -67,6 +67,12 @@ namespace rcpsp {
 
 // Layout and device state of a plan (no launches, no graph).
 rcpsp_status alloc_plan(rcpsp_search *s);
+// Neighbourhood evaluation of device arrays (allocates nothing): launch shape
+// chosen for the instance, one workgroup, asynchronous on st.
+rcpsp_status eval_device(const rcpsp_instance *I, const int32_t *order, int32_t delta, const uint8_t *tabu,
+                         int32_t asp, int32_t *makespan, rcpsp_move *best, hipStream_t st);
+// order is a precedence-feasible permutation with w_0 = 0 and w_{N-1} = N-1.
+bool feasible_order(const rcpsp_instance *I, const int32_t *order);
 rcpsp_status validate_params(const rcpsp_search_params &p);
 
 }  // namespace rcpsp

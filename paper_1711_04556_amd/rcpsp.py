@@ -129,6 +129,9 @@ def lib():
     L.rcpsp_evaluate_neighbourhood.argtypes = [vp, i32p, i32, u8p, i32, i32p, i32, i32p,
                                                ctypes.POINTER(rcpsp_move), vp]
     L.rcpsp_evaluate_neighbourhood.restype = ctypes.c_int
+    L.rcpsp_evaluate_neighbourhood_noalloc.argtypes = [vp, i32p, i32, u8p, i32, i32p, i32, i32p,
+                                                       ctypes.POINTER(rcpsp_move), vp]
+    L.rcpsp_evaluate_neighbourhood_noalloc.restype = ctypes.c_int
     L.rcpsp_evaluate_neighbourhood_device.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.rcpsp_evaluate_neighbourhood_device.restype = ctypes.c_int
     L.rcpsp_potential_moves.argtypes = [i32, i32]
@@ -260,9 +263,10 @@ class Instance:
         return {k: getattr(out, k) for k, _ in rcpsp_info._fields_}
 
     def evaluate_neighbourhood(self, order: Sequence[int], swap_range: int, tabu: Optional[np.ndarray] = None,
-                               aspiration: int = INT32_MAX, stream=None):
+                               aspiration: int = INT32_MAX, stream=None, noalloc: bool = False):
         """Host arrays in and out: returns (makespan[P] with -1 for infeasible
-        moves, dict(u, v, makespan, n_feasible))."""
+        moves, dict(u, v, makespan, n_feasible)).  noalloc: through
+        rcpsp_evaluate_neighbourhood_noalloc (no device allocation)."""
         P = potential_moves(self.n, swap_range)
         mk = np.zeros(max(P, 1), dtype=np.int32)
         best = rcpsp_move()
@@ -270,7 +274,7 @@ class Instance:
         tb = None
         if tabu is not None:
             tb = np.ascontiguousarray(np.asarray(tabu, dtype=np.uint8).reshape(self.n * self.n))
-        fn = lib().rcpsp_evaluate_neighbourhood
+        fn = lib().rcpsp_evaluate_neighbourhood_noalloc if noalloc else lib().rcpsp_evaluate_neighbourhood
         order_a = _i32(order)
         _check(fn(self.h, _ptr(order_a), swap_range, tb.ctypes.data if tb is not None else None, aspiration,
                   _ptr(mk), mk.size, ctypes.byref(npot), ctypes.byref(best), _stream_ptr(stream)))
