@@ -31,22 +31,23 @@ os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "SSGS neighbour evals/s (batched vs plain) at bit-exact makespan; p50/p99 latency"
 PEAK_INT_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
+PEAK_LDS_BYTES = 256 * 128 * 2.4e9   # 256 CUs x 128 B per clock x 2.4 GHz
 TRAFFIC_PROBE_BYTES = 1 << 30
 
 WORKLOAD = dict(swap_range=20, tabu_len=329, iterations=1000, searches=480, elite=16, phi_max=3, phi_steps=20,
                 seed=2)
 # batched leg: swap range and tabu list by size (N incl. dummies); the tabu
 # list is max(60, 0.15 x potential swaps), as for the plain workload
-BATCH = dict(count=1024, base_seed=3000, searches=32, elite=16, phi_max=3, phi_steps=20, iterations=100)
+BATCH = dict(count=1024, base_seed=3000, searches=32, elite=16, phi_max=3, phi_steps=20, iterations=1000)
 BATCH_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329)}
 # serving leg: open-loop Poisson arrivals, 50 ms budget from admission
 SERVE = dict(rate=2000.0, warmup_s=2.0, measure_s=10.0, budget_us=50000, searches=16, elite=16, iterations=1000,
              phi_max=3, phi_steps=20, seed=5, pool=256, max_active=1024)
 SERVE_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329), 302: (20, 869)}
 # large-instance leg: 256 instances of 300 activities, 8 resources; the
-# workload's 2000 iterations take over an hour at the measured rate, so a
-# few iterations are timed and the rate is reported
-LARGE = dict(count=256, base_seed=4000, searches=16, elite=16, phi_max=3, phi_steps=20, iterations=4,
+# workload's 2000 iterations take tens of minutes at the measured rate, so
+# the first iterations are timed and the rate is reported
+LARGE = dict(count=256, base_seed=4000, searches=16, elite=16, phi_max=3, phi_steps=20, iterations=16,
              swap_range=20, tabu_len=869)
 # heterogeneous-model leg: independent searches of the plain workload's
 # instance and move parameters, host-driven vs in-kernel
@@ -58,7 +59,7 @@ def log(*a):
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_search_plain480_ti_hbm.txt")
-TRAFFIC_SOURCES = ["paper_1711_04556_amd/csrc/rcpsp_kernels.hip", "paper_1711_04556_amd/csrc/rcpsp_internal.h",
+TRAFFIC_SOURCES = ["paper_1711_04556_amd/csrc/rcpsp_device.h", "paper_1711_04556_amd/csrc/rcpsp_internal.h",
                    "paper_1711_04556_amd/csrc/rcpsp_host.cpp"]
 
 
@@ -83,6 +84,57 @@ def measured_traffic(cfg):
             return None
         return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
+        return None
+
+
+def lds_bytes(work, cells, dec, nw, finish_bits):
+    """Algorithmic LDS bytes of decodes from their counted work: every
+    resource-state cell touched moves one packed profile unit (time-indexed:
+    4 * dwords per unit, all resources of the unit) or one 16-bit capacity
+    entry (capacity-indexed); every other operation (an activity placed, a
+    predecessor finish time read) moves one finish time."""
+    if dec == 1:
+        return cells * 4 * nw + (work - cells) * (finish_bits // 8)
+    return cells * 2 + (work - cells) * 2
+
+
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "k_search_plain480_ti_sq.txt")
+
+
+def counter_fractions(cfg, avg_ms):
+    """Counter-based fractions of the iteration kernel from the committed
+    rocprofv3 SQ summary (per dispatch: SQ_INSTS_VALU, SQ_INSTS_LDS,
+    SQ_WAVES, SQ_WAVE_CYCLES, SQ_WAIT_ANY), or None when the library sources
+    or the launch shape differ from those the counters were taken on."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(SQ_SUMMARY):
+            if ": " in line and not line.startswith((" ", "#", "|")):
+                k, v = line.rstrip("\n").split(": ", 1)
+                kv[k] = v
+        h = hashlib.sha256()
+        for f in TRAFFIC_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if kv.get("sources_sha256") != h.hexdigest():
+            return None
+        if any(kv.get(k) != str(cfg[k]) for k in ("eval", "threads", "profile_len", "lanes", "finish_bits")):
+            return None
+        valu, lds = float(kv["sq_insts_valu"]), float(kv["sq_insts_lds"])
+        ms = float(kv["avg_launch_ms"])
+        return {
+            "source": os.path.relpath(SQ_SUMMARY, ROOT),
+            "valu_lane_ops_per_s": valu * 64 / (ms * 1e-3),
+            "valu_frac": valu * 64 / (ms * 1e-3) / PEAK_INT_OPS,
+            "lds_bytes_per_s_at_4B_per_lane": lds * 256 / (ms * 1e-3),
+            "lds_frac_at_4B_per_lane": lds * 256 / (ms * 1e-3) / PEAK_LDS_BYTES,
+            "waves_per_launch": float(kv["sq_waves"]),
+            "wait_share": float(kv["sq_wait_any"]) / float(kv["sq_wave_cycles"]),
+            "valu_issue_share": float(kv["sq_insts_valu"]) / float(kv["sq_wave_cycles"]),
+            "profiled_avg_launch_ms": ms,
+            "bench_avg_launch_ms": avg_ms,
+        }
+    except (OSError, KeyError, ValueError, ZeroDivisionError):
         return None
 
 
@@ -128,7 +180,7 @@ def cpu_parallel(inst, decoder, passes=4):
                        f"{dt:.1f} s on {threads} threads)")
 
 
-def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
+def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=12):
     import torch
     t0 = time.perf_counter()
     insts = synth.mixed_batch(BATCH["count"], BATCH["base_seed"])
@@ -157,20 +209,19 @@ def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
     dt = time.perf_counter() - t0
     res = [bt.results(k, stream, orders=False, trajectory=False) for k in range(len(insts))]
     evals = sum(r["total_evaluations"] for r in res)
-    device_ms = bt.run_timed(stream)
     value = evals * steps / dt
-    log(f"batched: {dt / steps * 1e3:.1f} ms/step, {evals} evaluations/step, {value:.4g} evals/s, "
-        f"device {device_ms:.1f} ms")
+    log(f"batched: {dt / steps * 1e3:.1f} ms/step, {evals} evaluations/step, {value:.4g} evals/s")
     # plain form on an evenly spaced sample: one plan per instance, run one after the other
     sample = list(range(0, len(insts), max(1, len(insts) // plain_sample)))[:plain_sample]
     p_ms = 0.0
     p_ev = 0
     exact = True
+    s_work = s_cells = s_ev = 0
     for k in sample:
         q = type(params[k]).from_buffer_copy(params[k])
         q.threads = 0
         q.profile_len = 0
-        plan = rcpsp.SearchPlan(gis[k], q, stream)
+        plan = member_plan(rcpsp, gis[k], q, stream)
         plan.run(stream)
         timed = plan.run_timed(stream)
         r = plan.results(stream, orders=False, trajectory=False)
@@ -179,9 +230,26 @@ def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
         p_ev += r["total_evaluations"]
         exact = exact and r["total_evaluations"] == res[k]["total_evaluations"] and \
             r["global_best"] == res[k]["global_best"] and (r["best_makespan"] == res[k]["best_makespan"]).all()
+        # the batch member's own shape, counting kernels: its algorithmic work
+        c = type(params[k]).from_buffer_copy(params[k])
+        c.count_work = 1
+        cplan = member_plan(rcpsp, gis[k], c, stream)
+        cplan.run(stream)
+        cr = cplan.results(stream, orders=False, trajectory=False)
+        cplan.close()
+        s_work += cr["total_work"]
+        s_cells += cr["total_cells"]
+        s_ev += cr["total_evaluations"]
     plain = p_ev / (p_ms * 1e-3)
     sample_ev = sum(res[k]["total_evaluations"] for k in sample)
     log(f"plain sample: {len(sample)} instances, {p_ms:.1f} ms, {plain:.4g} evals/s, results equal: {exact}")
+    ops_ev = s_work / max(s_ev, 1)
+    achieved = value * ops_ev
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
+                    frac=achieved / PEAK_INT_OPS, ops_per_evaluation=ops_ev,
+                    basis=f"operations per evaluation counted on {len(sample)} sampled members in their own "
+                          f"shape (instrumented kernels, {s_ev} evaluations) x the batch's evaluations per "
+                          "second (all classes of the one graph)")
     cp = [g.info["critical_path"] for g in gis]
     dev = [100.0 * (r["global_best"] - c) / c for r, c in zip(res, cp)]
     return {
@@ -193,7 +261,7 @@ def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=24):
         "ms_per_step": dt / steps * 1e3,
         "steps": steps,
         "evaluations_per_step": evals,
-        "device_ms_per_step": device_ms,
+        "roofline": roofline,
         "plain_value": plain,
         "plain_sample": f"{len(sample)} evenly spaced instances ({sample_ev} evaluations), one plan each, "
                         f"device time summed",
@@ -247,8 +315,12 @@ def convergence_leg(rcpsp, gi, dec, stream, seeds, searches=(1, 4, 16, 64, 256, 
     searches (working set 16) on the plain workload's instance, each point the
     mean over `seeds` seeded runs of 1000 iterations; 480 independent
     searches (no working set) as the reference without cooperation.  The
-    best at iteration i is the minimum over the searches of their best after
-    i + 1 iterations."""
+    best after iteration i is the global best: the minimum over the searches
+    of their best after i + 1 iterations and over the working set's records.
+    A record only ever receives a search's best since its read (never below
+    that search's best), so the records' part is their initial makespans
+    (those no search has read when there are fewer searches than records),
+    read from a run of no iteration."""
     import numpy as np
     checkpoints = (0, 9, 49, 99, 249, 499, 999)
     rows = []
@@ -261,10 +333,17 @@ def convergence_leg(rcpsp, gi, dec, stream, seeds, searches=(1, 4, 16, 64, 256, 
             plan.run(stream)
             r = plan.results(stream, orders=False)
             plan.close()
+            rec0 = np.iinfo(np.int32).max
+            if elite:
+                p0 = rcpsp.SearchPlan(gi, rcpsp.search_params(record_trajectory=False, **dict(kw, iterations=0)),
+                                      stream)
+                p0.run(stream)
+                rec0 = int(p0.results(stream, orders=False, trajectory=False)["elite_makespan"].min())
+                p0.close()
             traj = np.asarray(r["trajectory"])[:, :, 3].astype(np.int64)   # best per search per iteration
             # iterations not run (a search stopped early) keep the last best
             best = np.where(traj < 0, np.iinfo(np.int32).max, traj)
-            best = np.minimum.accumulate(best, axis=1).min(axis=0)
+            best = np.minimum(np.minimum.accumulate(best, axis=1).min(axis=0), rec0)
             curves.append(best)
         c = np.mean(np.asarray(curves, dtype=np.float64), axis=0)
         rows.append(dict(searches=B, working_set=elite,
@@ -325,7 +404,6 @@ def large_leg(rcpsp, synth, stream, steps):
     log("large autotune", tuning)
     bt = rcpsp.Batch(gis, params, stream)
     info = bt.info
-    bt.run(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -335,15 +413,37 @@ def large_leg(rcpsp, synth, stream, steps):
     res = [bt.results(k, stream, orders=False, trajectory=False) for k in range(len(insts))]
     evals = sum(r["total_evaluations"] for r in res)
     bt.close()
+    # algorithmic work per evaluation: two members as plans of their own
+    # shape with the counting kernels (same searches, same evaluations)
+    s_work = s_cells = s_ev = 0
+    for k in (0, len(insts) // 2):
+        c = type(params[k]).from_buffer_copy(params[k])
+        c.count_work = 1
+        cplan = member_plan(rcpsp, gis[k], c, stream)
+        cplan.run(stream)
+        cr = cplan.results(stream, orders=False, trajectory=False)
+        cplan.close()
+        assert cr["total_evaluations"] == res[k]["total_evaluations"]
+        s_work += cr["total_work"]
+        s_cells += cr["total_cells"]
+        s_ev += cr["total_evaluations"]
+    value = evals * steps / dt
+    ops_ev = s_work / max(s_ev, 1)
     out = {
         "workload": f"{len(insts)} instances of 300 activities (8 resources, durations 1..20, capacities 10..60), "
                     f"{LARGE['searches']} searches and working set {LARGE['elite']} each, swap range 20, tabu list "
                     f"869, {LARGE['iterations']} iterations timed (the workload's 2000 would take "
                     f"{dt / steps / LARGE['iterations'] * 2000 / 60:.0f} min at this rate)",
-        "value": evals * steps / dt,
+        "value": value,
         "unit": "evals/s",
+        "iterations_timed": LARGE["iterations"],
         "ms_per_iteration": dt / steps / LARGE["iterations"] * 1e3,
         "evaluations_per_step": evals,
+        "roofline": dict(bound="alu", achieved=value * ops_ev / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
+                         frac=value * ops_ev / PEAK_INT_OPS, ops_per_evaluation=ops_ev,
+                         cells_per_evaluation=s_cells / max(s_ev, 1),
+                         basis="operations per evaluation counted on two members run as plans of their own shape "
+                               "(instrumented kernels) x the batch's evaluations per second"),
         "classes": info,
         "autotune": tuning,
     }
@@ -475,6 +575,78 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
     return out
 
 
+def lds_words(info):
+    """Dwords per packed time unit of the time-indexed profile (8-bit fields:
+    four resources per dword; 16-bit: two)."""
+    per = 4 if info["field_bits"] == 8 else 2
+    return max(1, -(-info["m"] // per))
+
+
+def member_plan(rcpsp, gi, q, stream):
+    """A plan of a batch member's parameters, with the fallbacks the batch
+    itself takes when a member's workgroup does not fit: the lane profile
+    in LDS instead of registers, then fewer threads."""
+    q = type(q).from_buffer_copy(q)
+    while True:
+        try:
+            return rcpsp.SearchPlan(gi, q, stream)
+        except rcpsp.RcpspError as e:
+            if e.status != -9:
+                raise
+            if q.lane_profile == 2:
+                q.lane_profile = 1
+            elif q.threads > 64:
+                q.threads = 128 if q.threads == 192 else q.threads // 2
+            else:
+                raise
+
+
+def count_work(rcpsp, gi, kw, stream, evals, full=False):
+    """Algorithmic operations and state cells of one run of the plan, from
+    the instrumented kernels (same search, same evaluations)."""
+    cplan = rcpsp.SearchPlan(gi, rcpsp.search_params(record_trajectory=False, count_work=True,
+                                                     **dict(kw, full_decode=full)), stream)
+    cplan.run(stream)
+    cres = cplan.results(stream, orders=False, trajectory=False)
+    cplan.close()
+    assert cres["total_evaluations"] == evals
+    return cres["total_work"], cres["total_cells"]
+
+
+def full_decode_leg(rcpsp, gi, kw, stream, evals):
+    """The headline plan with prefix reuse off: every candidate decoded from
+    its first position, as the method states it.  One warm-up and one timed
+    graph replay, an event-timed run for the kernel's launch time, and a
+    counting run for its work; same search and results."""
+    import torch
+    plan = rcpsp.SearchPlan(gi, rcpsp.search_params(record_trajectory=False, **dict(kw, full_decode=True)), stream)
+    cfg = plan.config
+    plan.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = plan.results(stream, orders=False, trajectory=False)
+    assert r["total_evaluations"] == evals
+    timed = plan.run_timed(stream)
+    plan.close()
+    n_launch = cfg["iteration_launches"]
+    avg_ms = timed["iteration_ms"] / n_launch
+    work, cells = count_work(rcpsp, gi, kw, stream, evals, full=True)
+    achieved = (work / n_launch) / (avg_ms * 1e-3)
+    lds_b = lds_bytes(work, cells, cfg["eval"], lds_words(gi.info), cfg["finish_bits"])
+    out = dict(value=evals / dt, unit="evals/s", ms_per_step=dt * 1e3, ops_per_evaluation=work / evals,
+               roofline=dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
+                             frac=achieved / PEAK_INT_OPS, avg_launch_ms=avg_ms,
+                             lds=dict(achieved=(lds_b / n_launch) / (avg_ms * 1e-3) / 1e12,
+                                      peak=PEAK_LDS_BYTES / 1e12, unit="TB/s",
+                                      frac=(lds_b / n_launch) / (avg_ms * 1e-3) / PEAK_LDS_BYTES,
+                                      bytes_per_evaluation=lds_b / evals)))
+    log("full decode", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,12 +662,12 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for HBM counter runs: one elementwise kernel over 1 GiB (read 1 GiB, write 1 GiB), "
                          "then one run of the headline plan")
-    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--batch-steps", type=int, default=1)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-large", action="store_true", help="skip the large-instance leg")
     ap.add_argument("--no-hosted", action="store_true", help="skip the heterogeneous-model leg")
-    ap.add_argument("--convergence", type=int, default=0, metavar="SEEDS",
-                    help="also run the convergence study with this many seeds per point (off by default)")
+    ap.add_argument("--convergence", type=int, default=3, metavar="SEEDS",
+                    help="convergence study with this many seeds per point (0 = off; the paper used 50)")
     ap.add_argument("--reselect", type=int, default=0, metavar="PERIOD",
                     help="also run periodic decoder re-selection with this period (two periods)")
     ap.add_argument("--serve-rate", type=float, default=SERVE["rate"])
@@ -528,7 +700,8 @@ def main():
         params, tuning = rcpsp.autotune(gi, params, trial_iterations=10, stream=stream)
         tuning["seconds"] = time.perf_counter() - t0
         log("autotune", tuning)
-    kw.update(eval=params.eval, threads=params.threads, profile_len=params.profile_len)
+    kw.update(eval=params.eval, threads=params.threads, profile_len=params.profile_len, lanes=params.lanes,
+              lane_profile=params.lane_profile)
 
     if args.traffic_probe:
         # calibration kernel of known traffic, then the plan's kernels once
@@ -573,15 +746,18 @@ def main():
     n_launch = cfg["iteration_launches"]
     avg_ms = timed["iteration_ms"] / n_launch
     log("event-timed run", timed, "iteration launches", n_launch, f"avg {avg_ms:.4f} ms")
-    # algorithmic operations of the same (deterministic) run, from the instrumented kernels
-    cplan = rcpsp.SearchPlan(gi, rcpsp.search_params(record_trajectory=False, count_work=True, **kw), stream)
-    cplan.run(stream)
-    cres = cplan.results(stream, orders=False, trajectory=False)
-    assert cres["total_evaluations"] == evals
-    work = cres["total_work"]
-    cplan.close()
+    # algorithmic work of the same (deterministic) run, from the instrumented
+    # kernels: the decodes this plan makes (shared prefixes once per wave,
+    # each candidate from its first swapped position) ...
+    work, cells = count_work(rcpsp, gi, kw, stream, evals)
     achieved = (work / n_launch) / (avg_ms * 1e-3)
-    log(f"work {work} ops ({work / evals:.1f} per evaluation), achieved {achieved / 1e12:.3f} Tops/s")
+    lds_b = lds_bytes(work, cells, dec, lds_words(info), cfg["finish_bits"])
+    lds_rate = (lds_b / n_launch) / (avg_ms * 1e-3)
+    log(f"work {work} ops ({work / evals:.1f} per evaluation), achieved {achieved / 1e12:.3f} Tops/s, "
+        f"LDS {lds_rate / 1e12:.3f} TB/s")
+    # ... and the method's work per evaluation: every candidate decoded from
+    # its first position (prefix reuse off), timed and counted on its own
+    full = full_decode_leg(rcpsp, gi, kw, stream, evals) if not args.full_decode else None
 
     cp = info["critical_path"]
     out = {
@@ -604,6 +780,7 @@ def main():
             "decoder": {1: "time-indexed", 2: "capacity-indexed"}[dec],
             "threads_per_search": cfg["threads"],
             "profile_len": cfg["profile_len"],
+            "register_profile": bool(cfg["register_profile"]),
             "lds_bytes": cfg["lds_bytes"],
             "evaluations_per_step": evals,
             "best_makespan": res["global_best"],
@@ -624,8 +801,18 @@ def main():
             "kernel": "k_search (iteration kernel)",
             "avg_launch_ms": avg_ms,
             "ops_per_evaluation": work / evals,
+            "ops_basis": "decodes the timed kernel runs (shared prefix once per wave, each candidate from its "
+                         "first swapped position; int32 lane operations of Algs. 5-7)",
+            "method_ops_per_evaluation": full["ops_per_evaluation"] if full else work / evals,
             "launches_per_step": n_launch,
+            "lds": {"achieved": lds_rate / 1e12, "peak": PEAK_LDS_BYTES / 1e12, "unit": "TB/s",
+                    "frac": lds_rate / PEAK_LDS_BYTES, "bytes_per_evaluation": lds_b / evals,
+                    "basis": "4 B x dwords per packed profile unit per cell touched (all resources of a time "
+                             "unit), one finish time per other operation"},
+            "counters": counter_fractions(cfg, avg_ms),
         },
+        "full_decode": full,
+        "prefix_reuse_speedup": (value / full["value"]) if full else None,
         "batched": None,
         "hosted": None,
         "serving": None,
@@ -636,13 +823,17 @@ def main():
     if not args.no_hosted:
         out["hosted"] = hosted_leg(rcpsp, gi, gi.info["eval"], stream)
     if args.convergence > 0:
-        out["convergence"] = convergence_leg(rcpsp, gi, gi.info["eval"], stream, args.convergence)
+        # the default is a short study (1..480 searches, 3 seeds); the paper's
+        # figure averages 50 runs (--convergence 50, about 10 minutes)
+        short = args.convergence < 10
+        out["convergence"] = convergence_leg(rcpsp, gi, gi.info["eval"], stream, args.convergence,
+                                             searches=(1, 4, 16, 64, 480) if short else (1, 4, 16, 64, 256, 480))
     if args.reselect > 0:
         ti = kw["eval"] == rcpsp.EVAL_TIME
         out["reselect"] = reselect_leg(rcpsp, gi, stream, args.reselect, max(1, args.reselect // 100),
                                        kw["threads"] if ti else 0, kw["profile_len"] if ti else 0)
     if not args.no_batch:
-        out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, min(args.warmup, 1))
+        out["batched"] = batched_leg(rcpsp, synth, stream, args.batch_steps, 0)
     if not args.no_large:
         out["large"] = large_leg(rcpsp, synth, stream, 1)
     if not args.no_serve:

@@ -215,6 +215,14 @@ typedef struct {
                                  Search plans only (batches reject it; servers
                                  take it as the request's budget when submit's
                                  budget_us is 0) */
+    int32_t lane_profile;     /* where a one-candidate-per-lane time-indexed decode
+                                 keeps its resource profile: 0 = automatic (LDS),
+                                 1 = LDS (profile_len units per lane), 2 = registers
+                                 (160 time units of one dword, for instances whose
+                                 time unit packs into one dword, i.e. up to four
+                                 resources of capacity <= 127 or two of <= 32767;
+                                 256 threads per search; schedules past 160 take
+                                 the long-profile path).  Same results */
 } rcpsp_search_params;
 
 /* Results; every pointer may be NULL (not copied).  Sizes in parentheses. */
@@ -229,11 +237,21 @@ typedef struct {
     int32_t global_best;      /* out: minimum over searches and working set */
     int64_t total_evaluations;/* out */
     int32_t overflow_decodes; /* out: candidates that needed the long-profile path */
-    int64_t total_work;       /* out: algorithmic operations (count_work plans only):
-                                 time-indexed: activities + predecessor reads + time
-                                 units examined by Alg. 5 + time units updated by
-                                 Alg. 6; capacity-indexed: activities + predecessor
-                                 reads + eq. 7 lookups + Alg. 4 loop steps */
+    int64_t total_work;       /* out: algorithmic operations of the decodes the run
+                                 made (count_work plans only): time-indexed:
+                                 activities + predecessor reads + time units
+                                 examined by Alg. 5 + time units updated by Alg. 6;
+                                 capacity-indexed: activities + predecessor reads +
+                                 eq. 7 lookups + Alg. 4 loop steps.  With
+                                 full_decode every candidate is decoded from its
+                                 first position (the method's work per
+                                 evaluation); without it, the shared schedule
+                                 prefixes are decoded once per wave or group and
+                                 every candidate from its first swapped position
+                                 on (the work the run did) */
+    int64_t total_cells;      /* out: the resource-state cells among total_work
+                                 (time units examined or updated; eq. 7 lookups and
+                                 Alg. 4 steps) */
 } rcpsp_search_result;
 
 typedef struct rcpsp_search rcpsp_search;
@@ -330,6 +348,7 @@ typedef struct {
     int32_t iteration_launches, round_launches;
     int32_t lanes;            /* lanes per candidate */
     int32_t finish_bits;      /* bits per finish time in the lane states (8 or 16) */
+    int32_t register_profile; /* 1 when the lane profiles live in registers */
 } rcpsp_search_config;
 rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_search_config *out);
 
@@ -386,7 +405,8 @@ rcpsp_status rcpsp_tabu_search_batch(const rcpsp_instance *const *inst, int32_t 
  * described by params for trial_iterations iterations with every candidate
  * (decoder x lanes per candidate x threads per search x profile length) and
  * keeps the one with the least device time per evaluation.  *out receives
- * params with eval, threads, profile_len and lanes filled in; *info (may be NULL) the choice and its cost.
+ * params with eval, threads, profile_len, lanes and lane_profile filled in;
+ * *info (may be NULL) the choice and its cost.
  * The decoder changes the schedules and so the search, so the choice is made
  * once, before the search, and is part of the result's identity.
  * Synchronous; allocates and frees its own trial plans. */
@@ -395,6 +415,8 @@ typedef struct {
     int32_t trials;           /* candidates timed */
     int32_t lanes;            /* lanes per candidate */
     double ns_per_evaluation; /* of the chosen candidate */
+    int32_t register_profile; /* 1 when the chosen lane profile is in registers
+                                 (out->lane_profile = 2) */
 } rcpsp_tuning;
 rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_search_params *params,
                             int32_t trial_iterations, void *hip_stream, rcpsp_search_params *out,
@@ -494,6 +516,7 @@ typedef struct {
     int32_t groups, trials;
     int32_t group_n[8], group_m[8], group_members[8], group_eval[8], group_threads[8], group_lanes[8];
     double group_evals_per_s[8];
+    int32_t group_register[8];   /* 1: lane profiles in registers (lane_profile 2) */
 } rcpsp_batch_tuning;
 rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, int32_t count,
                                   const rcpsp_search_params *params, int32_t trial_iterations, int32_t sample,

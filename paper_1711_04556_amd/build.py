@@ -11,10 +11,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librcpsp.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = [os.path.join(CSRC, "rcpsp_host.cpp"), os.path.join(CSRC, "rcpsp_serve.cpp"),
-           os.path.join(CSRC, "rcpsp_kernels.hip"), os.path.join(CSRC, "rcpsp_noalloc.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("rcpsp_host.cpp", "rcpsp_serve.cpp", "rcpsp_kernels.hip",
+                                           "rcpsp_k_search.hip", "rcpsp_k_count.hip", "rcpsp_k_batch.hip",
+                                           "rcpsp_k_serve.hip", "rcpsp_noalloc.hip")]
 HEADERS = [os.path.join(ROOT, "include", "rcpsp.h"), os.path.join(CSRC, "rcpsp_internal.h"),
-           os.path.join(CSRC, "rcpsp_launch.h"), os.path.join(CSRC, "rcpsp_runtime.h")]
+           os.path.join(CSRC, "rcpsp_launch.h"), os.path.join(CSRC, "rcpsp_runtime.h"),
+           os.path.join(CSRC, "rcpsp_device.h")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
@@ -39,7 +41,7 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
 
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
+    with ThreadPoolExecutor(min(len(SOURCES), 8)) as ex:
         list(ex.map(compile_one, range(len(SOURCES))))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs

@@ -352,7 +352,8 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     Ly.predT = o; o += std::max(D.n_arcs, 1);
     // one candidate per lane, time-indexed: the lane offsets of the first
     // four predecessors' finish times per position (16-byte entries)
-    const bool group = G > 2;
+    const bool group = layout_is_group(G);
+    const bool reg = G == kLayoutRegs;
     o = (o + 3) & ~3;
     Ly.pin = 0;
     if (dec == kEvalTime && !group) {
@@ -366,15 +367,20 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     // plus 4 of slack for the 4-wide scan) or the capacity arrays and the
     // copy ring
     // G = 2: one candidate per lane with 8-bit finish times
-    const int Fl = (dec == kEvalTime && G == 2) ? (D.n + 3) / 4 : F0;
-    if (group && dec == kEvalTime) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
+    const int Fl = (dec == kEvalTime && layout_finish_bits(G) == 8) ? finish_dwords(D.n, 8) : F0;
+    if (reg) Ly.per_lane = Fl;   // finish times only: the profile lives in registers
+    else if (group && dec == kEvalTime) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
     else if (group) Ly.per_lane = (F0 + (D.sum_r + 1) / 2 + (G * D.copy_p + 1) / 2 + 3) & ~3;   // a copy ring per lane
     else if (dec == kEvalTime) Ly.per_lane = Fl + (L + 4) * D.nw;
     else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
     Ly.cands = group ? T / G : T;
     o = (o + 3) & ~3;
     Ly.bst = o;
-    o += group ? Ly.per_lane : (T / 64) * ((Ly.per_lane + 3) & ~3);   // one base state per wave
+    // one base state per wave (the register layout's base keeps its profile
+    // in LDS: finish times placed so that the L + 4 units after them start
+    // 16-byte aligned)
+    Ly.base_stride = reg ? ((Fl + 3) & ~3) + (L + 4) * D.nw : ((Ly.per_lane + 3) & ~3);
+    o += group ? Ly.per_lane : (T / 64) * Ly.base_stride;
     o = (o + 3) & ~3;
     Ly.region = o;
     o += Ly.cands * Ly.per_lane;
@@ -402,6 +408,18 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
         if ((size_t)Ly.total * 4 > (size_t)budget)
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d)", Ly.total * 4, budget, T);
         *L_out = 0;
+        *Ly_out = Ly;
+        return RCPSP_OK;
+    }
+    if (G == kLayoutRegs) {
+        // the lane profile is kRegUnits units in registers (one dword per unit)
+        if (D.nw != 1 || (L_req > 0 && L_req != kRegUnits))
+            return fail(RCPSP_E_TOO_LARGE, "register profiles hold %d units of one dword", kRegUnits);
+        Layout Ly = make_layout(D, T, tcw, tl, pmax, kRegUnits, dec, G);
+        if (Ly.long_len < I->H || (size_t)Ly.total * 4 > (size_t)budget)
+            return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, register profile)", Ly.total * 4,
+                        budget, T);
+        *L_out = kRegUnits;
         *Ly_out = Ly;
         return RCPSP_OK;
     }
@@ -478,11 +496,13 @@ rcpsp_status rcpsp::eval_device(const rcpsp_instance *I, const int32_t *order, i
     int L = 0;
     Layout Ly;
     rcpsp_status s = RCPSP_E_TOO_LARGE;
-    // one candidate per lane first; groups when no lane state fits
-    for (int g : {2, 1, 16, 8}) {
-        if ((g == 2 || g == 16) && I->eval != kEvalTime) continue;
+    // one candidate per lane first (the profile in registers where a time
+    // unit packs into one dword, else in LDS); groups when no lane state fits
+    for (int g : {kLayoutRegs, 2, 1, 16, 8}) {
+        if ((g == kLayoutRegs || g == 2 || g == 16) && I->eval != kEvalTime) continue;
+        if (g == kLayoutRegs && I->desc.nw != 1) continue;
         if (g == 8 && I->eval != kEvalCapacity) continue;
-        for (T = 256; T >= 64; T /= 2) {
+        for (T = 256; T >= (g == kLayoutRegs ? 256 : 64); T /= 2) {
             s = plan_layout(I, I->eval, T, 0, 0, P, 0, 256, &L, &Ly, g);
             if (s != RCPSP_E_TOO_LARGE) break;
         }
@@ -705,7 +725,7 @@ static rcpsp_status shape_plan(rcpsp_search *s) {
         return fail(RCPSP_E_TOO_LARGE, "time-indexed profile needs more than %d dwords per time unit", kMaxNW);
     s->tcw = (p.swap_range + 31) / 32;
     s->P = potential_moves(N, p.swap_range);
-    const int T0 = p.threads ? p.threads : (B >= 256 ? 64 : (B >= 64 ? 128 : 256));
+    int T0 = p.threads ? p.threads : (B >= 256 ? 64 : (B >= 64 ? 128 : 256));
     if (T0 != 64 && T0 != 128 && T0 != 192 && T0 != 256)
         return fail(RCPSP_E_ARG, "threads must be 0, 64, 128, 192 or 256");
     if (T0 == 192 && (s->dec != kEvalTime || p.lanes > 1))
@@ -719,7 +739,7 @@ static rcpsp_status shape_plan(rcpsp_search *s) {
     rcpsp_status st = RCPSP_E_TOO_LARGE;
     auto try_shape = [&](int G, int Lreq) {
         // 192 threads exist for the one-candidate-per-lane time-indexed layouts only
-        T = (T0 == 192 && (s->dec != kEvalTime || G > 2)) ? 128 : T0;
+        T = (T0 == 192 && (s->dec != kEvalTime || layout_is_group(G) || G == kLayoutRegs)) ? 128 : T0;
         st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, Lreq, s->reserve, &s->L, &s->Ly, G);
         while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
             T /= 2;
@@ -731,10 +751,26 @@ static rcpsp_status shape_plan(rcpsp_search *s) {
     // finish times when the lane profile stays within 255 units, else
     // 16-bit); when no per-lane state fits, one candidate per 16 lanes
     // (time-indexed) or per 8 lanes (capacity-indexed)
-    if (p.lanes > 1) {
+    if (p.lane_profile == 2) {
+        // time-indexed profile in registers: one candidate per lane, 256 threads
+        if (s->dec != kEvalTime || p.lanes > 1 || (p.threads != 0 && p.threads != 256))
+            return fail(RCPSP_E_ARG, "a register profile needs the time-indexed decoder, one candidate per lane "
+                                     "and 256 threads");
+        T0 = 256;
+        try_shape(kLayoutRegs, p.profile_len);
+        if (st != RCPSP_OK) return st;
+    } else if (p.lanes > 1) {
         try_shape(p.lanes, p.profile_len);
     } else if (s->dec == kEvalTime) {
-        try_shape(2, p.profile_len);
+        // automatic: the register profile where it applies (a time unit in
+        // one dword, 256 threads, no profile length asked for), else LDS
+        if (p.lane_profile == 0 && s->nw == 1 && (p.threads == 0 || p.threads == 256) && p.profile_len == 0) {
+            const int T0s = T0;
+            T0 = 256;
+            try_shape(kLayoutRegs, 0);
+            if (st != RCPSP_OK) T0 = T0s;
+        }
+        if (st == RCPSP_E_TOO_LARGE) try_shape(2, p.profile_len);
         if (st == RCPSP_E_TOO_LARGE) try_shape(1, p.profile_len);
     } else {
         try_shape(1, p.profile_len);
@@ -968,8 +1004,9 @@ extern "C" rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_sea
     out->eval = s->dec;
     out->iteration_launches = s->iteration_launches;
     out->round_launches = s->round_launches;
-    out->lanes = s->G > 2 ? s->G : 1;
-    out->finish_bits = s->G == 2 ? 8 : 16;
+    out->lanes = layout_is_group(s->G) ? s->G : 1;
+    out->finish_bits = layout_finish_bits(s->G);
+    out->register_profile = s->G == kLayoutRegs ? 1 : 0;
     return RCPSP_OK;
 }
 
@@ -981,12 +1018,13 @@ extern "C" rcpsp_status rcpsp_search_results(rcpsp_search *s, rcpsp_search_resul
     std::vector<SearchScalars> sc(B);
     HIP_TRY(hipMemcpy(sc.data(), a.sc, sizeof(SearchScalars) * B, hipMemcpyDeviceToHost));
     int gbest = INT_MAX;
-    long long tot = 0, ovf = 0, work = 0;
+    long long tot = 0, ovf = 0, work = 0, cells = 0;
     for (int b = 0; b < B; ++b) {
         gbest = std::min(gbest, sc[b].C_best);
         tot += sc[b].evals;
         ovf += sc[b].overflow;
         work += sc[b].work;
+        cells += sc[b].cells;
         if (res->best_makespan) res->best_makespan[b] = sc[b].C_best;
         if (res->iterations_done) res->iterations_done[b] = sc[b].it_done;
         if (res->evaluations) res->evaluations[b] = sc[b].evals;
@@ -1019,6 +1057,7 @@ extern "C" rcpsp_status rcpsp_search_results(rcpsp_search *s, rcpsp_search_resul
     res->total_evaluations = tot;
     res->overflow_decodes = (int32_t)std::min<long long>(ovf, INT_MAX);
     res->total_work = work;
+    res->total_cells = cells;
     return RCPSP_OK;
 }
 
@@ -1145,6 +1184,7 @@ extern "C" rcpsp_status rcpsp_tabu_search_hosted(const rcpsp_instance *inst, con
     res->total_evaluations = tot;
     res->overflow_decodes = 0;
     res->total_work = 0;
+    res->total_cells = 0;
     return RCPSP_OK;
 }
 
@@ -1358,17 +1398,30 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
     std::vector<int> lanes_c;
     if (params->lanes) lanes_c.push_back(params->lanes);
     else lanes_c = {1, 8, 16};
+    // lane profiles: in LDS (every lane layout), and in registers for the
+    // time-indexed one-candidate-per-lane layout at 256 threads
+    std::vector<int> lps;
+    if (params->lane_profile) lps.push_back(params->lane_profile);
+    else lps = {1, 2};
     for (int ev : evals) {
       for (int G : lanes_c) {
         if ((G == 16 && ev != kEvalTime) || (G == 8 && ev != kEvalCapacity)) continue;
-        for (int T : threads) {
+        // register profiles run at 256 threads whatever the search count
+        std::vector<int> Ts = threads;
+        if (!params->threads && std::find(Ts.begin(), Ts.end(), 256) == Ts.end()) Ts.push_back(256);
+        for (int T : Ts)
+        for (int lp : lps) {
+            if (T == 256 && lp == 1 && std::find(threads.begin(), threads.end(), 256) == threads.end()) continue;
             if (T == 192 && (ev != kEvalTime || G != 1)) continue;
+            if (lp == 2 && (ev != kEvalTime || G != 1 || T != (params->threads ? params->threads : 256) ||
+                            inst->desc.nw != 1))
+                continue;
             std::vector<int> Ls;
-            if (ev == kEvalTime && !params->profile_len) {
+            if (ev == kEvalTime && !params->profile_len && lp == 1) {
                 Ls.push_back(0);
                 Ls.push_back(std::max(Lshort, 16));
             } else {
-                Ls.push_back(params->profile_len);
+                Ls.push_back(lp == 2 ? 0 : params->profile_len);
             }
             for (int L : Ls) {
                 rcpsp_search_params q = *params;
@@ -1376,6 +1429,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
                 q.threads = T;
                 q.profile_len = L;
                 q.lanes = G;
+                q.lane_profile = lp;
                 q.iterations = trial_iterations;
                 q.record_trajectory = 0;
                 q.count_work = 0;
@@ -1400,7 +1454,8 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
                     best.eval = ev;
                     best.threads = T;
                     best.lanes = G;
-                    best.profile_len = ev == kEvalTime ? Lused : 0;
+                    best.lane_profile = lp;
+                    best.profile_len = (ev == kEvalTime && lp == 1) ? Lused : 0;
                 }
             }
         }
@@ -1413,6 +1468,7 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
         info->threads = best.threads;
         info->profile_len = best.profile_len;
         info->lanes = best.lanes;
+        info->register_profile = best.lane_profile == 2 ? 1 : 0;
         info->trials = trials;
         info->ns_per_evaluation = best_ns;
     }
@@ -1459,6 +1515,7 @@ rcpsp_status rcpsp::validate_params(const rcpsp_search_params &p) {
     if (p.eval < 0 || p.eval > 2) return fail(RCPSP_E_ARG, "unknown decoder %d", p.eval);
     if (p.fbi != 0 && p.fbi != 1) return fail(RCPSP_E_ARG, "fbi must be 0 or 1");
     if (p.exchange_every < 0) return fail(RCPSP_E_ARG, "exchange_every must be >= 0");
+    if (p.lane_profile < 0 || p.lane_profile > 2) return fail(RCPSP_E_ARG, "lane_profile must be 0, 1 or 2");
     if (p.time_budget_us < 0) return fail(RCPSP_E_ARG, "time_budget_us must be >= 0");
     return RCPSP_OK;
 }
@@ -1489,6 +1546,12 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
             s->p = p;
             s->reserve = kBatchStaticLds;
             st = alloc_plan(s);
+            if (st == RCPSP_E_TOO_LARGE && p.lane_profile == 2) {
+                // no register profile for this member: its profile in LDS
+                rcpsp_search_destroy(s);
+                p.lane_profile = 1;
+                continue;
+            }
             if (st == RCPSP_E_TOO_LARGE && p.threads > 64) {
                 rcpsp_search_destroy(s);
                 p.threads = p.threads == 192 ? 128 : p.threads / 2;
@@ -1786,18 +1849,26 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         std::vector<int> lanes_c;
         if (p0.lanes) lanes_c.push_back(p0.lanes);
         else lanes_c = {1, 8, 16};
+        std::vector<int> lps;
+        if (p0.lane_profile) lps.push_back(p0.lane_profile);
+        else lps = {1, 2};
+        bool nw1 = true;
+        for (int k = 0; k < ns; ++k) nw1 = nw1 && si[k]->desc.nw == 1;
         bool found = false;
         double best_rate = 0.0;
-        int best_eval = 0, best_T = 0, best_G = 1;
+        int best_eval = 0, best_T = 0, best_G = 1, best_lp = 1;
         for (int ev : evals) {
           for (int G : lanes_c) {
             if ((G == 16 && ev != kEvalTime) || (G == 8 && ev != kEvalCapacity)) continue;
-            for (int T : threads) {
+            for (int T : threads)
+            for (int lp : lps) {
                 if (T == 192 && (ev != kEvalTime || G != 1)) continue;
+                if (lp == 2 && (ev != kEvalTime || G != 1 || T != 256 || !nw1)) continue;
                 for (auto &q : sp) {
                     q.eval = ev;
                     q.threads = T;
                     q.lanes = G;
+                    q.lane_profile = lp;
                 }
                 rcpsp_batch *bt = nullptr;
                 rcpsp_status st = rcpsp_batch_create(si.data(), ns, sp.data(), hip_stream, &bt);
@@ -1822,6 +1893,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
                     best_eval = ev;
                     best_T = T;
                     best_G = G;
+                    best_lp = lp;
                 }
             }
           }
@@ -1832,6 +1904,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
             out[i].eval = best_eval;
             out[i].threads = best_T;
             out[i].lanes = best_G;
+            out[i].lane_profile = best_lp;
         }
         if (info && g < 8) {
             info->group_n[g] = keys[g].first;
@@ -1840,6 +1913,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
             info->group_eval[g] = best_eval;
             info->group_threads[g] = best_T;
             info->group_lanes[g] = best_G;
+            info->group_register[g] = best_lp == 2 ? 1 : 0;
             info->group_evals_per_s[g] = best_rate;
         }
     }

@@ -16,6 +16,21 @@ constexpr int kMaxLds = 160 * 1024; // LDS per workgroup on gfx950
 constexpr int kEvalTime = 1;
 constexpr int kEvalCapacity = 2;
 
+// Candidate layouts (the template argument G of the kernels):
+//   1  one candidate per lane, 16-bit finish times, profile in LDS
+//   2  one candidate per lane, 8-bit finish times, profile in LDS
+//   4  one candidate per lane, 8-bit finish times, time-indexed profile of
+//      kRegUnits time units in registers (one dword per unit)
+//   8  one capacity-indexed candidate per 8 lanes (a lane per resource)
+//   16 one time-indexed candidate per 16 lanes
+constexpr int kLayoutRegs = 4;
+constexpr int kRegUnits = 160;
+__host__ __device__ constexpr bool layout_is_group(int G) { return G == 8 || G == 16; }
+__host__ __device__ constexpr int layout_finish_bits(int G) { return (G == 2 || G == kLayoutRegs) ? 8 : 16; }
+
+// Dwords of n finish times of fb bits at the start of a candidate state.
+__host__ __device__ constexpr int finish_dwords(int n, int fb) { return fb == 8 ? (n + 3) >> 2 : (n + 1) >> 1; }
+
 // Packed instance, passed by value to every kernel.  The arrays live in one
 // device blob (dword sections) that kernels copy into LDS.
 struct InstDesc {
@@ -39,6 +54,7 @@ struct InstDesc {
 struct Layout {
     int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, prec, prq, predT, pin, bst, red, scal, region;
     int per_lane;    // dwords of private decode state per candidate slot
+    int base_stride; // dwords of each wave's base decode (one-candidate-per-lane layouts)
     int cands;       // candidate slots per round (threads, or threads / lanes per candidate)
     int long_len;    // time slots available to the single-thread long-profile decode
     int total;       // dwords
@@ -54,6 +70,7 @@ struct SearchScalars {
     long long evals;
     long long overflow;
     long long work;      // algorithmic operations of all decodes (counting runs only)
+    long long cells;     // resource-state cells among them (profile units / capacity entries)
 };
 
 enum : int {

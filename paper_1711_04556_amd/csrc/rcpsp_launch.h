@@ -26,6 +26,11 @@ hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, siz
 hipError_t launch_round(const SearchArgs &A, int parity, int init, hipStream_t st);
 size_t round_lds_bytes(int B, int NF);
 hipError_t prepare_search(int T, int nw, int dec, int G, size_t lds, int B, int NF);
+// parts of the two above that live in the iteration-kernel translation units
+hipError_t prepare_search_kernels(int T, int nw, int dec, int G, size_t lds);
+hipError_t prepare_count_kernels(int T, int nw, int dec, int G, size_t lds);
+hipError_t launch_search_plain(const SearchArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
+hipError_t launch_search_count(const SearchArgs &A, int T, int nw, int dec, int G, size_t lds, hipStream_t st);
 
 struct BatchQueue;
 

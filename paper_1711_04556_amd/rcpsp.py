@@ -46,12 +46,13 @@ class rcpsp_search_params(ctypes.Structure):
         "swap_range", "tabu_len", "iterations", "searches", "elite", "phi_max", "phi_steps", "threads",
         "profile_len", "record_trajectory", "count_work", "full_decode", "eval", "lanes")] + [
         ("seed", ctypes.c_uint64), ("fbi", ctypes.c_int32), ("exchange_every", ctypes.c_int32),
-        ("time_budget_us", ctypes.c_int32)]
+        ("time_budget_us", ctypes.c_int32), ("lane_profile", ctypes.c_int32)]
 
 
 class rcpsp_tuning(ctypes.Structure):
     _fields_ = [("eval", ctypes.c_int32), ("threads", ctypes.c_int32), ("profile_len", ctypes.c_int32),
-                ("trials", ctypes.c_int32), ("lanes", ctypes.c_int32), ("ns_per_evaluation", ctypes.c_double)]
+                ("trials", ctypes.c_int32), ("lanes", ctypes.c_int32), ("ns_per_evaluation", ctypes.c_double),
+                ("register_profile", ctypes.c_int32)]
 
 
 class rcpsp_search_result(ctypes.Structure):
@@ -60,7 +61,7 @@ class rcpsp_search_result(ctypes.Structure):
                 ("trajectory", ctypes.c_void_p), ("elite_makespan", ctypes.c_void_p),
                 ("elite_order", ctypes.c_void_p), ("global_best", ctypes.c_int32),
                 ("total_evaluations", ctypes.c_int64), ("overflow_decodes", ctypes.c_int32),
-                ("total_work", ctypes.c_int64)]
+                ("total_work", ctypes.c_int64), ("total_cells", ctypes.c_int64)]
 
 
 class rcpsp_batch_info(ctypes.Structure):
@@ -73,7 +74,7 @@ class rcpsp_batch_tuning(ctypes.Structure):
     _fields_ = [("groups", ctypes.c_int32), ("trials", ctypes.c_int32)] + [
         (n, ctypes.c_int32 * 8) for n in ("group_n", "group_m", "group_members", "group_eval", "group_threads",
                                           "group_lanes")] + [
-        ("group_evals_per_s", ctypes.c_double * 8)]
+        ("group_evals_per_s", ctypes.c_double * 8), ("group_register", ctypes.c_int32 * 8)]
 
 
 class rcpsp_server_params(ctypes.Structure):
@@ -104,7 +105,7 @@ class rcpsp_decoder_segment(ctypes.Structure):
 class rcpsp_search_config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "threads", "profile_len", "lds_bytes", "eval", "iteration_launches", "round_launches", "lanes",
-        "finish_bits")]
+        "finish_bits", "register_profile")]
 
 
 _lib = None
@@ -293,10 +294,10 @@ def search_params(swap_range: int, tabu_len: int, iterations: int, searches: int
                   phi_max: int = 3, phi_steps: int = 20, threads: int = 0, profile_len: int = 0,
                   record_trajectory: bool = True, count_work: bool = False, full_decode: bool = False,
                   eval: int = EVAL_AUTO, seed: int = 1, lanes: int = 0, fbi: bool = False, exchange_every: int = 0,
-                  time_budget_us: int = 0) -> rcpsp_search_params:
+                  time_budget_us: int = 0, lane_profile: int = 0) -> rcpsp_search_params:
     return rcpsp_search_params(swap_range, tabu_len, iterations, searches, elite, phi_max, phi_steps, threads,
                                profile_len, int(record_trajectory), int(count_work), int(full_decode), eval, lanes,
-                               seed, int(fbi), exchange_every, time_budget_us)
+                               seed, int(fbi), exchange_every, time_budget_us, lane_profile)
 
 
 def autotune(instance: "Instance", params: rcpsp_search_params, trial_iterations: int = 10, stream=None):
@@ -363,6 +364,7 @@ class SearchPlan:
         out["total_evaluations"] = res.total_evaluations
         out["overflow_decodes"] = res.overflow_decodes
         out["total_work"] = res.total_work
+        out["total_cells"] = res.total_cells
         return out
 
 
@@ -389,6 +391,7 @@ def _results(fn, handle_args, params, n, stream, orders=True, trajectory=True, s
     out["total_evaluations"] = res.total_evaluations
     out["overflow_decodes"] = res.overflow_decodes
     out["total_work"] = res.total_work
+    out["total_cells"] = res.total_cells
     return out
 
 
@@ -407,7 +410,7 @@ def batch_autotune(instances: Sequence["Instance"], params, trial_iterations: in
     g = info.groups
     d = {"groups": g, "trials": info.trials}
     for k in ("group_n", "group_m", "group_members", "group_eval", "group_threads", "group_lanes",
-              "group_evals_per_s"):
+              "group_evals_per_s", "group_register"):
         d[k] = list(getattr(info, k))[:min(g, 8)]
     res = []
     for i in range(n):
@@ -493,6 +496,7 @@ def tabu_search_batch(instances: Sequence[Instance], params, stream=None, orders
         o["total_evaluations"] = ress[i].total_evaluations
         o["overflow_decodes"] = ress[i].overflow_decodes
         o["total_work"] = ress[i].total_work
+        o["total_cells"] = ress[i].total_cells
     return outs
 
 

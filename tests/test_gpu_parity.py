@@ -31,8 +31,13 @@ def _serial_instance():
 
 
 def _wide_instance():
-    """Capacities above 127 force 16-bit profile fields (two dwords for M=4)."""
-    return synth.generate(40, 4, 10, 0.75, rs=0.7, seed=3003, name="wide40")
+    """Capacities above 127 force 16-bit profile fields (two dwords for M=4):
+    a generated instance with every request and capacity tripled."""
+    b = synth.generate(40, 4, 10, 0.75, rs=0.7, seed=3003)
+    inst = synth.Instance(n=b.n, m=b.m, duration=b.duration, capacity=[3 * c for c in b.capacity],
+                          request=[3 * r for r in b.request], succ=b.succ, name="wide40")
+    assert max(inst.capacity) > 127
+    return inst
 
 
 EVAL_CASES = [
@@ -181,13 +186,14 @@ def test_overflow_redecode_counts_same_work(rc):
     algorithmic operations as when the lane profile holds them."""
     inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=25)
     gi = rc.Instance(inst, eval=TIME)
-    kw = dict(swap_range=10, tabu_len=60, iterations=10, searches=4, seed=7, count_work=True, threads=192)
+    kw = dict(swap_range=10, tabu_len=60, iterations=10, searches=4, seed=7, count_work=True, threads=192,
+              full_decode=True)
     a = rc.tabu_search(gi, **kw)
     b = rc.tabu_search(gi, profile_len=16, **kw)
     for k in ("trajectory", "best_makespan", "evaluations"):
         assert np.array_equal(a[k], b[k]), k
     assert a["overflow_decodes"] == 0 and b["overflow_decodes"] > 0
-    assert a["total_work"] == b["total_work"] > 0
+    assert a["total_work"] == b["total_work"] > 0 and a["total_cells"] == b["total_cells"] > 0
 
 
 @pytest.mark.parametrize("dec", [TIME, CAP])
@@ -280,12 +286,21 @@ def test_counting_and_timed_runs_match_graph_run(rc, dec):
     cplan = rc.SearchPlan(gi, rc.search_params(count_work=True, **kw))
     cplan.run()
     c = cplan.results()
+    fplan = rc.SearchPlan(gi, rc.search_params(count_work=True, full_decode=True, **kw))
+    fplan.run()
+    f = fplan.results()
     for k in ("trajectory", "best_makespan", "evaluations", "elite_order", "best_order"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(a[k], c[k]), k
-    assert a["total_work"] == 0 and c["total_work"] > c["total_evaluations"] * inst.n
+        assert np.array_equal(a[k], f[k]), k
+    # decoding every candidate from position 0 costs at least one operation
+    # per activity; continuing from the shared prefix costs less, not nothing
+    assert a["total_work"] == 0 and f["total_work"] > f["total_evaluations"] * inst.n
+    assert 0 < c["total_work"] < f["total_work"]
+    assert 0 < c["total_cells"] < c["total_work"] and 0 < f["total_cells"] < f["total_work"]
     plan.close()
     cplan.close()
+    fplan.close()
 
 
 def test_search_decoder_override(rc):
@@ -407,7 +422,8 @@ def test_group_decode_counts_same_work(rc):
     as the one-lane decode (a property of the method, not of the launch)."""
     inst = synth.generate(40, 4, 10, 0.5, rs=0.3, seed=24)
     gi = rc.Instance(inst, eval=TIME)
-    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True)
+    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True,
+              full_decode=True)
     a = rc.tabu_search(gi, lanes=1, **kw)
     b = rc.tabu_search(gi, lanes=16, **kw)
     for k in ("trajectory", "best_makespan", "evaluations"):
@@ -502,7 +518,8 @@ def test_capacity_group_decode_search_parity(rc, name, make, delta, threads):
 def test_capacity_group_decode_counts_same_work(rc):
     inst = synth.generate(40, 4, 10, 0.5, rs=0.3, seed=24)
     gi = rc.Instance(inst, eval=CAP)
-    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True)
+    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True,
+              full_decode=True)
     a = rc.tabu_search(gi, lanes=1, **kw)
     b = rc.tabu_search(gi, lanes=8, **kw)
     for k in ("trajectory", "best_makespan", "evaluations"):
@@ -709,3 +726,64 @@ def test_8bit_finish_times_past_255(rc, seed, factor, threads):
         plan.close()
         o = orc.tabu_search(10, 40, 30, searches=6, elite=elite, phi_max=2, phi_steps=4, decoder=TIME, seed=seed)
         _compare_search(g, o, elite=elite)
+
+
+# ---------------------------------------------------------------------------
+# Register-resident lane profiles (160 time units of one dword per lane):
+# same results as the LDS layouts and the oracle, including schedules that
+# pass the register profile (long-profile path) or 255 (8-bit finish times).
+
+REG_CASES = [
+    ("table1", synth.table1_instance, 10),
+    ("g30", lambda: synth.single_instance_30(1), 8),
+    ("g60", lambda: synth.generate(60, 4, 10, 0.5, rs=0.3, seed=63), 14),
+    ("g120", synth.instance_120_rs30, 20),
+    ("serial14", _serial_instance, 5),
+    ("stretched", lambda: _stretched(1513, 3), 10),
+]
+
+
+@pytest.mark.parametrize("name,make,delta", REG_CASES, ids=[c[0] for c in REG_CASES])
+@pytest.mark.parametrize("elite", [0, 4])
+def test_register_profile_search_parity(rc, name, make, delta, elite):
+    inst = make()
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=delta, tabu_len=30, iterations=25, searches=6, elite=elite, phi_max=2, phi_steps=4,
+              seed=8)
+    plan = rc.SearchPlan(gi, rc.search_params(lane_profile=2, eval=TIME, **kw))
+    cfg = plan.config
+    assert cfg["register_profile"] == 1 and cfg["threads"] == 256 and cfg["finish_bits"] == 8
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(delta, 30, 25, searches=6, elite=elite, phi_max=2, phi_steps=4, decoder=TIME, seed=8)
+    _compare_search(g, o, elite=elite)
+    if name == "stretched":
+        assert g["overflow_decodes"] > 0   # schedules past the 160 register units
+
+
+def test_register_profile_counts_same_work(rc):
+    """The register decode counts the same algorithmic operations and cells
+    as the LDS lane decode, from position 0 and with the shared prefix."""
+    inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=24)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True,
+              full_decode=True)
+    a = rc.tabu_search(gi, lanes=1, threads=256, **kw)
+    b = rc.tabu_search(gi, lane_profile=2, **kw)
+    for k in ("trajectory", "best_makespan", "evaluations"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["total_work"] == b["total_work"] > 0 and a["total_cells"] == b["total_cells"] > 0
+
+
+def test_register_profile_arguments(rc):
+    gi = rc.Instance(_wide_instance(), eval=TIME)   # 16-bit fields, two dwords per unit: no register profile
+    with pytest.raises(rc.RcpspError) as e:
+        rc.SearchPlan(gi, rc.search_params(6, 20, 5, searches=2, lane_profile=2))
+    assert e.value.status == -9
+    gi = rc.Instance(synth.single_instance_30(1), eval=TIME)
+    for bad in (dict(threads=64), dict(lanes=16)):
+        with pytest.raises(rc.RcpspError) as e:
+            rc.SearchPlan(gi, rc.search_params(6, 20, 5, searches=2, lane_profile=2, **bad))
+        assert e.value.status == -1

@@ -44,20 +44,25 @@ def _compare(g, o, elite=0):
 # 120-activity instance, compared with the oracle's full run (stored by
 # tests/golden/make_plain480.py, which calls only the oracle).
 
-@pytest.mark.parametrize("shape", ["default", "tuned"])
+@pytest.mark.parametrize("shape", ["registers", "lds"])
 def test_headline_workload_full_length_equals_oracle(rc, shape):
+    """Both launch shapes the benchmark's autotuner chooses between for this
+    workload: the automatic one (256 threads, lane profiles in registers) and
+    192 threads with 145-unit lane profiles in LDS and 8-bit finish times."""
     g0 = golden("plain480_ti.json")
     w = g0["workload"]
     inst = synth.instance_120_rs30(2)
     gi = rc.Instance(inst, eval=TIME)
-    extra = dict(threads=192, profile_len=145) if shape == "tuned" else {}
+    extra = dict(threads=192, profile_len=145) if shape == "lds" else {}
     plan = rc.SearchPlan(gi, rc.search_params(w["delta"], w["tabu_len"], w["iterations"], searches=w["searches"],
                                               elite=w["elite"], phi_max=w["phi_max"], phi_steps=w["phi_steps"],
                                               eval=TIME, seed=w["seed"], **extra))
     cfg = plan.config
-    if shape == "tuned":
-        # the launch shape the benchmark's autotuner picks for this workload
+    if shape == "lds":
         assert cfg["threads"] == 192 and cfg["finish_bits"] == 8 and cfg["lanes"] == 1
+        assert cfg["register_profile"] == 0
+    else:
+        assert cfg["threads"] == 256 and cfg["register_profile"] == 1
     print(f"headline {shape}: {cfg}", flush=True)
     plan.run()
     g = plan.results()
