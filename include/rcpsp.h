@@ -157,7 +157,9 @@ typedef struct {
     int32_t phi_max;          /* diversify when a record was read more than phi_max times */
     int32_t phi_steps;        /* random feasible swaps per diversification */
     int32_t threads;          /* threads per search: 0 = auto, else 64, 128, 256,
-                                 or 192 (time-indexed, one candidate per lane) */
+                                 192 (time-indexed, one candidate per lane) or
+                                 512 (one candidate per wave, lanes = 64, or 8
+                                 lanes per capacity-indexed candidate) */
     int32_t profile_len;      /* time-indexed LDS profile slots per lane, 0 = auto
                                  (about 1.4 x critical path, stretched while the
                                  workgroups per CU stay the same, never below
@@ -176,12 +178,17 @@ typedef struct {
                                  The resolved decoder is reported by
                                  rcpsp_search_get_config and decides results. */
     int32_t lanes;            /* lanes per candidate decode: 0 = auto (1, or
-                                 16 time-indexed / 8 capacity-indexed when a
-                                 per-lane state does not fit), 1, 16
+                                 when a per-lane state does not fit: one
+                                 candidate per wave / 16 lanes time-indexed,
+                                 8 lanes capacity-indexed), 1, 16
                                  (time-indexed only: 16 lanes test 16 time
-                                 units per step) or 8 (capacity-indexed only:
+                                 units per step), 8 (capacity-indexed only:
                                  a lane per resource, eq. 7 and Alg. 4 of the
-                                 resources side by side); same results */
+                                 resources side by side) or 64 (time-indexed
+                                 only, 512 threads: one candidate per wave,
+                                 its profile of 2048 / words-per-unit time
+                                 units in registers, a lane per unit of a
+                                 64-unit chunk); same results */
     uint64_t seed;            /* seeds the initial orders and diversification */
     int32_t fbi;              /* 1 = forward-backward improvement of every second
                                  initial solution (odd search index, or odd
@@ -503,8 +510,11 @@ void rcpsp_server_destroy(rcpsp_server *s);
  * counterpart of rcpsp_autotune).  Instances are grouped by (N, M); for each
  * group, up to `sample` evenly spaced members run as a batch of
  * trial_iterations iterations under every candidate (decoder time- or
- * capacity-indexed where the instance allows it, threads 64/128/256, lanes
- * per candidate 1/16 for the time-indexed decoder; a nonzero eval, threads or
+ * capacity-indexed where the instance allows it, threads 64/128/192/256,
+ * lanes per candidate 1/16 and one candidate per wave (512 threads) for the
+ * time-indexed decoder, 1/8 (8 also at 512 threads) for the
+ * capacity-indexed one, profiles in LDS or registers; a nonzero eval,
+ * threads or
  * lanes in params fixes that choice), and the candidate
  * with the most evaluations per device second is written to every member of
  * the group.  Results never depend on the choice of threads; the decoder is

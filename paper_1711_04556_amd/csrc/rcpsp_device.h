@@ -37,7 +37,7 @@ struct Sh {
     const uint32_t *rq, *res;
     uint16_t *W, *Wimp, *pos, *fs, *lp;
     int *cnt;
-    uint32_t *tc, *ring, *moves, *prec, *prq, *predT, *pin, *bst;
+    uint32_t *tc, *ring, *moves, *prec, *prq, *predT, *pin, *pid, *bst;
     unsigned long long *red;
     int *scal;
     uint32_t *region;
@@ -69,6 +69,7 @@ __device__ inline Sh make_sh(uint32_t *lds, const InstDesc &D, const Layout &Ly)
     s.prq = lds + Ly.prq;
     s.predT = lds + Ly.predT;
     s.pin = Ly.pin ? lds + Ly.pin : nullptr;
+    s.pid = Ly.pid ? lds + Ly.pid : nullptr;
     s.bst = lds + Ly.bst;
     s.red = reinterpret_cast<unsigned long long *>(lds + Ly.red);
     s.scal = reinterpret_cast<int *>(lds + Ly.scal);
@@ -209,7 +210,10 @@ __device__ inline unsigned long long block_min_u64(unsigned long long x, unsigne
 //   pin[4p..4p+3]  = the same offsets for the first four predecessors of w_p
 //                    (one 16-byte load; present for one-candidate-per-lane
 //                    time-indexed layouts only); absent predecessors get
-//                    offset 0, the finish time of the source activity (0).
+//                    offset 0, the finish time of the source activity (0);
+//   pid[2p..2p+1]  = the ids of the first four predecessors of w_p, 16 bits
+//                    each (one 8-byte load; one-candidate-per-wave layout
+//                    only), absent ones the source activity 0.
 template <int T, int FB = 16>
 __device__ inline void build_records(const Sh &S, const InstDesc &D) {
     const int N = D.n, NW = D.nw;
@@ -233,6 +237,16 @@ __device__ inline void build_records(const Sh &S, const InstDesc &D) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) o[k] = k < np ? offF<T, FB>(S.pred[po + k]) : 0u;
             reinterpret_cast<uint4 *>(S.pin)[p] = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+    }
+    if (S.pid) {
+        for (int p = threadIdx.x; p < N; p += T) {
+            const int a = S.W[p];
+            const int po = S.predoff[a], np = S.predoff[a + 1] - po;
+            uint32_t o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] = k < np ? (uint32_t)S.pred[po + k] : 0u;
+            reinterpret_cast<uint2 *>(S.pid)[p] = make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
         }
     }
 }
@@ -1455,16 +1469,366 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
     return block_min_u64<T>(best, S.red);
 }
 
+// ---------------------------------------------------------------------------
+// Wave decode (layout kLayoutWave, time-indexed): one candidate per wave,
+// its resource profile spread over the wave's registers.  Unit t lives in
+// lane t & 63 of register chunk t >> 6: word w of chunk c in A[w][c] for
+// c < CH, in B[w][c - CH] after that (NB = 2 banks), so the profile holds
+// 64 * CH * NB units.  A single candidate makes every per-activity value
+// wave-uniform (position, record, earliest start, start), so chunk indexes
+// are scalars and index the register file directly (each bank is an array
+// of at most 32 dwords, which the compiler keeps in VGPRs).  Finish times
+// too: activity x in lane x & 63 of register x >> 6, with a 16-bit copy by
+// activity at F in LDS for the predecessors past the first four (read by
+// the lanes side by side).  The records of the next position are loaded
+// while the current one is placed.
+//
+// Per activity: the earliest start from the predecessors' finish times;
+// Alg. 5 walks chunks from the one holding the earliest start,
+// every lane testing its unit for all resources with one subtract and mask
+// per word, a ballot giving the chunk's units short of capacity and each
+// lane the run of free units that ends at its unit (carried across chunks),
+// and the first unit whose run reaches d closing the start; Alg. 6 writes
+// the units of [s, s + d) with the lanes of the chunks covering them.  Units
+// at or past the frontier fr were never written and count as free; units
+// between fr and a start past it are set to full capacity when the frontier
+// moves.  A start whose interval passes the profile reports overflow
+// (wave-uniform).  COUNT counts as decode_tg does (on lane 0).
+// (two banks: both are indexed and the value selected, so that no access
+// goes through a pointer chosen between the arrays, which would move them
+// to scratch memory)
+template <int NW, int CH>
+using WaveBanks = uint32_t[NW][CH];
+
+template <int NW, int CH, int NB>
+__device__ __attribute__((always_inline)) inline uint32_t tw_get(WaveBanks<NW, CH> &A, WaveBanks<NW, CH> &B, int w,
+                                                                 int c) {
+    if (NB == 1) return A[w][min(c, CH - 1)];
+    const uint32_t x = A[w][min(c, CH - 1)], y = B[w][max(min(c - CH, CH - 1), 0)];
+    return c < CH ? x : y;
+}
+template <int NW, int CH, int NB>
+__device__ __attribute__((always_inline)) inline void tw_set(WaveBanks<NW, CH> &A, WaveBanks<NW, CH> &B, int w, int c,
+                                                             uint32_t x) {
+    if (NB == 1) {
+        A[w][min(c, CH - 1)] = x;
+        return;
+    }
+    const int ca = min(c, CH - 1), cb = max(min(c - CH, CH - 1), 0);
+    const uint32_t xa = A[w][ca], xb = B[w][cb];
+    A[w][ca] = c < CH ? x : xa;
+    B[w][cb] = c < CH ? xb : x;
+}
+
+// Finish time of activity x from the wave's registers: lane x & 63 of
+// register x >> 6 (x wave-uniform), and its update.
+constexpr int kWaveFR = kWaveMaxN / 64;
+__device__ __attribute__((always_inline)) inline int fr_get(const uint32_t (&FR)[kWaveFR], int x) {
+    return __builtin_amdgcn_readlane((int)FR[min(x >> 6, kWaveFR - 1)], x & 63);
+}
+__device__ __attribute__((always_inline)) inline void fr_set(uint32_t (&FR)[kWaveFR], int x, int val) {
+    const int i = min(x >> 6, kWaveFR - 1);
+    const uint32_t old = FR[i];
+    FR[i] = (int)(threadIdx.x & 63) == (x & 63) ? (uint32_t)val : old;
+}
+
+template <int NW, int CH, int NB, bool COUNT>
+__device__ __attribute__((always_inline)) int decode_tw(const Sh &S, const InstDesc &D, uint16_t *F,
+                                                        uint32_t (&FR)[kWaveFR], WaveBanks<NW, CH> &A,
+                                                        WaveBanks<NW, CH> &B, int &fr, int u, int v, int p0, int p1,
+                                                        bool &ovf, Work *wk) {
+    constexpr int LW = 64 * CH * NB;
+    const int lane = threadIdx.x & 63;
+    uint32_t Gd[NW], FULL[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        Gd[w] = D.guard[w];
+        FULL[w] = D.full[w];
+    }
+    // lanes at or below this lane (the run of free units ending at its unit)
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
+    const uint2 *pid = reinterpret_cast<const uint2 *>(S.pid);
+    long long w_ops = 0, w_cells = 0;
+    int f = __builtin_amdgcn_readfirstlane(fr);
+    u = __builtin_amdgcn_readfirstlane(u);
+    v = __builtin_amdgcn_readfirstlane(v);
+    p0 = __builtin_amdgcn_readfirstlane(p0);
+    p1 = __builtin_amdgcn_readfirstlane(p1);
+    auto qof = [&](int p) {
+        p = min(p, D.n - 1);
+        return (p == u) ? v : ((p == v) ? u : p);
+    };
+    // the records of a position are loaded one position ahead
+    int q = qof(p0);
+    uint4 r = rec[q];
+    uint2 pd = pid[q];
+    uint32_t rqn[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) rqn[w] = S.prq[q * NW + w];
+    for (int p = p0; p < p1; ++p) {
+        const int d = __builtin_amdgcn_readfirstlane((int)(r.y & 0xffff));
+        const int np = __builtin_amdgcn_readfirstlane((int)(r.y >> 16));
+        const int po = __builtin_amdgcn_readfirstlane((int)r.z);
+        const int a = __builtin_amdgcn_readfirstlane((int)r.w);
+        const uint32_t i01 = __builtin_amdgcn_readfirstlane(pd.x), i23 = __builtin_amdgcn_readfirstlane(pd.y);
+        uint32_t rq[NW];
+        uint32_t any = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            rq[w] = __builtin_amdgcn_readfirstlane(rqn[w]);
+            any |= rq[w];
+        }
+        q = qof(p + 1);
+        r = rec[q];
+        pd = pid[q];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) rqn[w] = S.prq[q * NW + w];
+        // earliest start: the first four predecessors from the registers,
+        // further ones (lanes side by side) from the finish times in LDS
+        int es = max(max(fr_get(FR, (int)(i01 & 0xffff)), fr_get(FR, (int)(i01 >> 16))),
+                     max(fr_get(FR, (int)(i23 & 0xffff)), fr_get(FR, (int)(i23 >> 16))));
+        if (np > 4) {
+            int x = 0;
+            for (int e0 = 4; e0 < np; e0 += 64) {
+                const int e = e0 + lane;
+                if (e < np) x = max(x, (int)F[S.pred[po + e]]);
+            }
+            x = np <= 20 ? __builtin_amdgcn_readlane(group_max<16>(x), 0) : wave_max_uniform(x);
+            es = max(es, x);
+        }
+        int s = es;
+        if (any != 0u && d > 0) {
+            if (es < f) {
+                // Alg. 5 over the written units, chunk by chunk (every chunk
+                // visited starts below the frontier, so inside the profile)
+                int c = es >> 6, run = 0;
+                for (;;) {
+                    const int tb = c << 6, t = tb + lane;
+                    bool ok = true;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) ok = ok && (((tw_get<NW, CH, NB>(A, B, w, c) - rq[w]) & Gd[w]) == Gd[w]);
+                    const bool fit = t >= es && (t >= f || ok);
+                    const unsigned long long mz = ~__builtin_amdgcn_ballot_w64(fit);
+                    const unsigned long long below = mz & upto;
+                    const int rl = below ? lane - (63 - (int)__clzll(below)) : run + lane + 1;
+                    const unsigned long long hm = __builtin_amdgcn_ballot_w64(rl >= d);
+                    if (hm != 0ull) {
+                        s = tb + (__ffsll(hm) - 1) - d + 1;
+                        break;
+                    }
+                    run = mz ? (int)__clzll(mz) : run + 64;
+                    if (tb + 64 >= f) {
+                        // every unit past this chunk is free
+                        s = tb + 64 - run;
+                        break;
+                    }
+                    ++c;
+                }
+            }
+            if (s + d > LW) {
+                ovf = true;
+                return -1;
+            }
+            if (COUNT && lane == 0) {
+                w_ops += (s + d - es) + d;
+                w_cells += (s + d - es) + d;
+            }
+            // Alg. 6 (and full capacity for the units between the frontier and s)
+            const int lo = min(s, f), hi = s + d;
+            for (int c = lo >> 6; c <= (hi - 1) >> 6; ++c) {
+                const int x = (c << 6) + lane;
+                const bool in = x >= lo && x < hi;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t old = tw_get<NW, CH, NB>(A, B, w, c);
+                    const uint32_t base = x < f ? old : FULL[w];
+                    const uint32_t nv = x < s ? FULL[w] : base - rq[w];
+                    tw_set<NW, CH, NB>(A, B, w, c, in ? nv : old);
+                }
+            }
+            f = max(f, hi);
+        } else if (COUNT && lane == 0) {
+            w_ops += 2 * d;
+            w_cells += 2 * d;
+        }
+        if (COUNT && lane == 0) w_ops += 1 + np;
+        fr_set(FR, a, s + d);
+        if (lane == 0) F[a] = (uint16_t)(s + d);
+        __builtin_amdgcn_wave_barrier();
+    }
+    fr = f;
+    if (COUNT && lane == 0) wk->add(Work{w_ops, w_cells});
+    return p1 == D.n ? fr_get(FR, D.n - 1) : 0;
+}
+
+// Evaluation with one candidate per wave (layout kLayoutWave): wave w takes
+// moves w, w + T/64, ... in canonical order (u ascending), so its own base
+// decode (W itself, profile in the register bank Pb) only moves forward:
+// before a candidate the wave extends it up to the candidate's u, copies
+// the bank to P and decodes positions u.. of the candidate there.  Base and
+// candidates share the wave's finish-time area: a candidate writes only the
+// activities at positions u and later, which the base rewrites before it
+// reads them.  Waves never wait for each other inside the loop.  A
+// candidate that passes its bank (or comes after the wave's base passed
+// its own) is decoded afterwards from scratch over both banks (twice the
+// profile; the waves take these in turn), and one that passes both by
+// lanes 0-15 with the group decode over the whole region (a profile of the
+// full horizon).
+template <int NW, int T, bool COUNT = false>
+__device__ unsigned long long evaluate_moves_w(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
+                                               int delta, TabuSrc tabu, int asp, int *out_mk, long long *ovf_total,
+                                               Work *work_total = nullptr, bool share = true) {
+    constexpr int CH = kWaveDwords / NW, NV = T / 64;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    unsigned long long best = ~0ull;
+    Work lw{0, 0};
+    int *ovf_n = S.scal;        // candidates flagged for a re-decode over both banks
+    int *ovf2_n = S.scal + 1;   // ... and for the group decode
+    if (tid == 0) {
+        *ovf_n = 0;
+        *ovf2_n = 0;
+    }
+    __syncthreads();
+    uint16_t *F = reinterpret_cast<uint16_t *>(S.region + wv * Ly.per_lane);
+    // both banks are set here so that their contents do not live on from
+    // one evaluation to the next (registers held across the whole kernel)
+    uint32_t Pb[NW][CH], P[NW][CH], FR[kWaveFR];
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+#pragma unroll
+        for (int k = 0; k < CH; ++k) Pb[w][k] = P[w][k] = 0u;
+#pragma unroll
+    for (int k = 0; k < kWaveFR; ++k) FR[k] = 0u;
+    // flags in the move list: bit 31 for a re-decode over both banks, bit 30
+    // for the group decode (a candidate that passed both keeps bit 31, so
+    // the list the waves deal from does not change under them)
+    auto finish = [&](int j, uint32_t mv, int c, bool ovf, uint32_t flag, const Work &cw) {
+        const int u = mv & 0xffff, v = (mv >> 16) & 0x3fff;
+        if (lane == 0) {
+            if (ovf) {
+                S.moves[j] = mv | flag;
+                atomicAdd((flag & 0x40000000u) ? ovf2_n : ovf_n, 1);
+            } else {
+                if (COUNT) lw.add(cw);
+                const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
+                best = k < best ? k : best;
+                if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+            }
+        }
+    };
+    int bpos = 0, bfr = 0;
+    bool bdead = !share;
+    for (int j = wv; j < nfeas; j += NV) {
+        const uint32_t mv = __builtin_amdgcn_readfirstlane(S.moves[j]);
+        const int u = mv & 0xffff, v = (mv >> 16) & 0x3fff;
+        if (!bdead && bpos < u) {
+            bool bo = false;
+            Work bw{0, 0};
+            decode_tw<NW, CH, 1, COUNT>(S, D, F, FR, Pb, Pb, bfr, 0, 0, bpos, u, bo, &bw);
+            if (bo) bdead = true;
+            else if (COUNT) lw.add(bw);
+            bpos = u;
+        }
+        bool ovf = false;
+        Work cw{0, 0};
+        int c;
+        if (!bdead) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int k = 0; k < CH; ++k) P[w][k] = Pb[w][k];
+            int fr = bfr;
+            c = decode_tw<NW, CH, 1, COUNT>(S, D, F, FR, P, P, fr, u, v, bpos, D.n, ovf, &cw);
+            finish(j, mv, c, ovf, 0x80000000u, cw);
+        } else {
+            // no base: decoded from scratch over both banks after the loop
+            finish(j, mv, 0, true, 0x80000000u, cw);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (*ovf_n > 0) {
+        // over both banks, from scratch: flagged candidates dealt to the waves in turn
+        int rank = 0;
+        for (int j0 = 0; j0 < nfeas; j0 += 64) {
+            const int jj = j0 + lane;
+            const bool flagged = jj < nfeas && (S.moves[jj] & 0x80000000u) != 0u;
+            unsigned long long m = __builtin_amdgcn_ballot_w64(flagged);
+            while (m != 0ull) {
+                const int j = j0 + __ffsll(m) - 1;
+                m &= m - 1ull;
+                if (rank++ % NV != wv) continue;
+                const uint32_t mv = __builtin_amdgcn_readfirstlane(S.moves[j]);
+                const int u = mv & 0xffff, v = (mv >> 16) & 0x3fff;
+                bool ovf = false;
+                int fr = 0;
+                Work cw{0, 0};
+                const int c = decode_tw<NW, CH, 2, COUNT>(S, D, F, FR, Pb, P, fr, u, v, 0, D.n, ovf, &cw);
+                finish(j, mv, c, ovf, 0x40000000u, cw);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+    }
+    if (*ovf2_n > 0) {
+        // past both banks: the group decode over the whole region
+        if (tid < 16) {
+            constexpr unsigned long long gm = 0xffffull;
+            for (int j0 = 0; j0 < nfeas; j0 += 16) {
+                const int jj = j0 + tid;
+                const bool flagged = jj < nfeas && (S.moves[jj] & 0x40000000u) != 0u;
+                unsigned long long m = __builtin_amdgcn_ballot_w64(flagged) & gm;
+                while (m != 0ull) {
+                    const int j = j0 + __ffsll(m) - 1;
+                    m &= m - 1ull;
+                    const uint32_t mv = S.moves[j];
+                    const int u = mv & 0xffff, v = (mv >> 16) & 0x3fff;
+                    bool o = false;
+                    int front = 0;
+                    Work cw{0, 0};
+                    const int c = decode_tg<NW, 16, COUNT>(S, D, S.region, Ly.long_len, u, v, 0, D.n, front, o, &cw);
+                    if (tid == 0) {
+                        if (COUNT) lw.add(cw);
+                        const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
+                        best = k < best ? k : best;
+                        if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // clear the flags, count the decodes that left the register profile
+    if (*ovf_n > 0 || *ovf2_n > 0) {
+        for (int j = tid; j < nfeas; j += T) S.moves[j] &= 0x3fffffffu;
+        if (tid == 0 && ovf_total) *ovf_total += *ovf_n + *ovf2_n;
+        __syncthreads();
+    }
+    if (COUNT) {
+        const long long ops = block_sum_i64<T>(lw.ops, S.red);
+        const long long cells = block_sum_i64<T>(lw.cells, S.red);
+        if (tid == 0) work_total->add(Work{ops, cells});
+    }
+    return block_min_u64<T>(best, S.red);
+}
+
 // Lane-per-candidate (G = 1) or group decode (G > 2).
 // Layout codes: G = 1 one candidate per lane with 16-bit finish times,
 // G = 2 one candidate per lane with 8-bit finish times (lane profiles of at
 // most 255 units), G = 16 one candidate per 16 lanes (time-indexed), G = 8
-// one candidate per 8 lanes (capacity-indexed, a lane per resource).
+// one candidate per 8 lanes (capacity-indexed, a lane per resource),
+// G = 64 one time-indexed candidate per wave, profile in registers.
 template <int NW, int T, int DEC, int G, bool COUNT = false>
 __device__ inline unsigned long long evaluate_any(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas, int L,
                                                   int delta, TabuSrc tabu, int asp, int *out_mk, long long *ovf_total,
                                                   Work *work_total = nullptr, bool share = true) {
-    if constexpr (layout_is_group(G)) {
+    if constexpr (G == kLayoutWave) {
+        static_assert(DEC == kEvalTime, "the wave layout is time-indexed");
+        return evaluate_moves_w<NW, T, COUNT>(S, D, Ly, nfeas, delta, tabu, asp, out_mk, ovf_total, work_total,
+                                              share);
+    } else if constexpr (layout_is_group(G)) {
         return evaluate_moves_g<NW, T, DEC, G, COUNT>(S, D, Ly, nfeas, L, delta, tabu, asp, out_mk, ovf_total,
                                                       work_total, share);
     } else {
@@ -2460,52 +2824,56 @@ __global__ void k_clock(long long *out) {
 #define RCPSP_DISPATCH(NWV, TV, DECV, GV, CALL)                                                                      \
     switch (DECV) {                                                                                                  \
     case kEvalCapacity:                                                                                              \
-        switch ((TV) * 32 + (GV)) {                                                                                  \
-        case 64 * 32 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;             \
-        case 128 * 32 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;           \
-        case 256 * 32 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;           \
-        case 64 * 32 + 8: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;             \
-        case 128 * 32 + 8: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;           \
-        case 256 * 32 + 8: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;           \
+        switch ((TV) * 128 + (GV)) {                                                                                 \
+        case 64 * 128 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;            \
+        case 128 * 128 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;          \
+        case 256 * 128 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 1; CALL; } break;          \
+        case 64 * 128 + 8: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;            \
+        case 128 * 128 + 8: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;          \
+        case 256 * 128 + 8: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;          \
+        case 512 * 128 + 8: { constexpr int T_ = 512, NW_ = 1, DEC_ = kEvalCapacity, G_ = 8; CALL; } break;          \
         default: return hipErrorInvalidValue;                                                                        \
         }                                                                                                            \
         break;                                                                                                       \
     default:                                                                                                         \
-        switch (((TV) * 16 + (NWV)) * 32 + (GV)) {                                                                   \
-        case (64 * 16 + 1) * 32 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
-        case (64 * 16 + 1) * 32 + 2: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;      \
-        case (64 * 16 + 1) * 32 + 16: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
-        case (64 * 16 + 2) * 32 + 1: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
-        case (64 * 16 + 2) * 32 + 2: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;      \
-        case (64 * 16 + 2) * 32 + 16: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
-        case (64 * 16 + 4) * 32 + 1: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;      \
-        case (64 * 16 + 4) * 32 + 2: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;      \
-        case (64 * 16 + 4) * 32 + 16: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;    \
-        case (128 * 16 + 1) * 32 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (128 * 16 + 1) * 32 + 2: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (128 * 16 + 1) * 32 + 16: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
-        case (128 * 16 + 2) * 32 + 1: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (128 * 16 + 2) * 32 + 2: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (128 * 16 + 2) * 32 + 16: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
-        case (128 * 16 + 4) * 32 + 1: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (128 * 16 + 4) * 32 + 2: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (128 * 16 + 4) * 32 + 16: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
-        case (192 * 16 + 1) * 32 + 1: { constexpr int T_ = 192, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (192 * 16 + 1) * 32 + 2: { constexpr int T_ = 192, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (192 * 16 + 2) * 32 + 1: { constexpr int T_ = 192, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (192 * 16 + 2) * 32 + 2: { constexpr int T_ = 192, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (192 * 16 + 4) * 32 + 1: { constexpr int T_ = 192, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (192 * 16 + 4) * 32 + 2: { constexpr int T_ = 192, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (256 * 16 + 1) * 32 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (256 * 16 + 1) * 32 + 2: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (256 * 16 + 1) * 32 + 16: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
-        case (256 * 16 + 1) * 32 + 4: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 4; CALL; } break;    \
-        case (256 * 16 + 2) * 32 + 1: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (256 * 16 + 2) * 32 + 2: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (256 * 16 + 2) * 32 + 16: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
-        case (256 * 16 + 4) * 32 + 1: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;    \
-        case (256 * 16 + 4) * 32 + 2: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;    \
-        case (256 * 16 + 4) * 32 + 16: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;  \
+        switch (((TV) * 16 + (NWV)) * 128 + (GV)) {                                                                  \
+        case (64 * 16 + 1) * 128 + 1: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;     \
+        case (64 * 16 + 1) * 128 + 2: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;     \
+        case (64 * 16 + 1) * 128 + 16: { constexpr int T_ = 64, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break;   \
+        case (64 * 16 + 2) * 128 + 1: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;     \
+        case (64 * 16 + 2) * 128 + 2: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;     \
+        case (64 * 16 + 2) * 128 + 16: { constexpr int T_ = 64, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break;   \
+        case (64 * 16 + 4) * 128 + 1: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;     \
+        case (64 * 16 + 4) * 128 + 2: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;     \
+        case (64 * 16 + 4) * 128 + 16: { constexpr int T_ = 64, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break;   \
+        case (128 * 16 + 1) * 128 + 1: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (128 * 16 + 1) * 128 + 2: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (128 * 16 + 1) * 128 + 16: { constexpr int T_ = 128, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break; \
+        case (128 * 16 + 2) * 128 + 1: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (128 * 16 + 2) * 128 + 2: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (128 * 16 + 2) * 128 + 16: { constexpr int T_ = 128, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break; \
+        case (128 * 16 + 4) * 128 + 1: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (128 * 16 + 4) * 128 + 2: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (128 * 16 + 4) * 128 + 16: { constexpr int T_ = 128, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break; \
+        case (192 * 16 + 1) * 128 + 1: { constexpr int T_ = 192, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (192 * 16 + 1) * 128 + 2: { constexpr int T_ = 192, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (192 * 16 + 2) * 128 + 1: { constexpr int T_ = 192, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (192 * 16 + 2) * 128 + 2: { constexpr int T_ = 192, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (192 * 16 + 4) * 128 + 1: { constexpr int T_ = 192, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (192 * 16 + 4) * 128 + 2: { constexpr int T_ = 192, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (256 * 16 + 1) * 128 + 1: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (256 * 16 + 1) * 128 + 2: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (256 * 16 + 1) * 128 + 16: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 16; CALL; } break; \
+        case (256 * 16 + 1) * 128 + 4: { constexpr int T_ = 256, NW_ = 1, DEC_ = kEvalTime, G_ = 4; CALL; } break;   \
+        case (256 * 16 + 2) * 128 + 1: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (256 * 16 + 2) * 128 + 2: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (256 * 16 + 2) * 128 + 16: { constexpr int T_ = 256, NW_ = 2, DEC_ = kEvalTime, G_ = 16; CALL; } break; \
+        case (256 * 16 + 4) * 128 + 1: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 1; CALL; } break;   \
+        case (256 * 16 + 4) * 128 + 2: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 2; CALL; } break;   \
+        case (256 * 16 + 4) * 128 + 16: { constexpr int T_ = 256, NW_ = 4, DEC_ = kEvalTime, G_ = 16; CALL; } break; \
+        case (512 * 16 + 1) * 128 + 64: { constexpr int T_ = 512, NW_ = 1, DEC_ = kEvalTime, G_ = 64; CALL; } break;\
+        case (512 * 16 + 2) * 128 + 64: { constexpr int T_ = 512, NW_ = 2, DEC_ = kEvalTime, G_ = 64; CALL; } break;\
+        case (512 * 16 + 4) * 128 + 64: { constexpr int T_ = 512, NW_ = 4, DEC_ = kEvalTime, G_ = 64; CALL; } break;\
         default: return hipErrorInvalidValue;                                                                        \
         }                                                                                                            \
     }

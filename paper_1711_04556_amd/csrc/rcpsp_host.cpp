@@ -354,11 +354,18 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     // four predecessors' finish times per position (16-byte entries)
     const bool group = layout_is_group(G);
     const bool reg = G == kLayoutRegs;
+    const bool wave = G == kLayoutWave;
     o = (o + 3) & ~3;
     Ly.pin = 0;
-    if (dec == kEvalTime && !group) {
+    if (dec == kEvalTime && !group && !wave) {
         Ly.pin = o;
         o += 4 * D.n;
+    }
+    // one candidate per wave: the first four predecessors' ids per position
+    Ly.pid = 0;
+    if (wave) {
+        Ly.pid = o;
+        o += 2 * D.n;
     }
     o = (o + 1) & ~1;
     Ly.red = o; o += 2 * (T / 64);
@@ -369,18 +376,25 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     // G = 2: one candidate per lane with 8-bit finish times
     const int Fl = (dec == kEvalTime && layout_finish_bits(G) == 8) ? finish_dwords(D.n, 8) : F0;
     if (reg) Ly.per_lane = Fl;   // finish times only: the profile lives in registers
+    else if (wave) {
+        // a wave's finish times (the profile lives in registers); the region
+        // also holds the finish times and a profile of L units for the
+        // group decode of candidates past the register profile (L: the horizon)
+        const int waves = T / 64;
+        Ly.per_lane = std::max((F0 + 3) & ~3, ((F0 + (L + 4) * D.nw + waves - 1) / waves + 3) & ~3);
+    }
     else if (group && dec == kEvalTime) Ly.per_lane = (F0 + L * D.nw + 3) & ~3;
     else if (group) Ly.per_lane = (F0 + (D.sum_r + 1) / 2 + (G * D.copy_p + 1) / 2 + 3) & ~3;   // a copy ring per lane
     else if (dec == kEvalTime) Ly.per_lane = Fl + (L + 4) * D.nw;
     else Ly.per_lane = F0 + (D.sum_r + 1) / 2 + D.copy_p / 2;
-    Ly.cands = group ? T / G : T;
+    Ly.cands = group ? T / G : (wave ? T / 64 : T);
     o = (o + 3) & ~3;
     Ly.bst = o;
     // one base state per wave (the register layout's base keeps its profile
     // in LDS: finish times placed so that the L + 4 units after them start
     // 16-byte aligned)
     Ly.base_stride = reg ? ((Fl + 3) & ~3) + (L + 4) * D.nw : ((Ly.per_lane + 3) & ~3);
-    o += group ? Ly.per_lane : (T / 64) * Ly.base_stride;
+    o += wave ? 0 : (group ? Ly.per_lane : (T / 64) * Ly.base_stride);
     o = (o + 3) & ~3;
     Ly.region = o;
     o += Ly.cands * Ly.per_lane;
@@ -403,11 +417,26 @@ static rcpsp_status plan_layout(const rcpsp_instance *I, int dec, int T, int tcw
                                 int reserve, int *L_out, Layout *Ly_out, int G = 1) {
     const InstDesc &D = I->desc;
     const int budget = kMaxLds - 1024;  // static shared variables
+    if (G == kLayoutWave && dec != kEvalTime) return fail(RCPSP_E_ARG, "one candidate per wave is time-indexed");
     if (dec == kEvalCapacity) {
         Layout Ly = make_layout(D, T, tcw, tl, pmax, 0, dec, G);
         if ((size_t)Ly.total * 4 > (size_t)budget)
             return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d)", Ly.total * 4, budget, T);
         *L_out = 0;
+        *Ly_out = Ly;
+        return RCPSP_OK;
+    }
+    if (G == kLayoutWave) {
+        // the profile is wave_profile_units(nw) units in the wave's registers
+        if (T != kWaveThreads) return fail(RCPSP_E_ARG, "one candidate per wave runs at %d threads", kWaveThreads);
+        if (I->n > kWaveMaxN)
+            return fail(RCPSP_E_TOO_LARGE, "one candidate per wave holds at most %d activities", kWaveMaxN);
+        if (L_req > 0 && L_req != wave_profile_units(D.nw))
+            return fail(RCPSP_E_TOO_LARGE, "wave profiles hold %d units", wave_profile_units(D.nw));
+        Layout Ly = make_layout(D, T, tcw, tl, pmax, std::max(I->H, 1), dec, G);
+        if (Ly.long_len < I->H || (size_t)Ly.total * 4 > (size_t)budget)
+            return fail(RCPSP_E_TOO_LARGE, "LDS %d bytes exceed %d (threads %d, wave profile)", Ly.total * 4, budget, T);
+        *L_out = wave_profile_units(D.nw);
         *Ly_out = Ly;
         return RCPSP_OK;
     }
@@ -726,20 +755,32 @@ static rcpsp_status shape_plan(rcpsp_search *s) {
     s->tcw = (p.swap_range + 31) / 32;
     s->P = potential_moves(N, p.swap_range);
     int T0 = p.threads ? p.threads : (B >= 256 ? 64 : (B >= 64 ? 128 : 256));
-    if (T0 != 64 && T0 != 128 && T0 != 192 && T0 != 256)
-        return fail(RCPSP_E_ARG, "threads must be 0, 64, 128, 192 or 256");
+    if (T0 != 64 && T0 != 128 && T0 != 192 && T0 != 256 && T0 != 512)
+        return fail(RCPSP_E_ARG, "threads must be 0, 64, 128, 192, 256 or 512");
     if (T0 == 192 && (s->dec != kEvalTime || p.lanes > 1))
         return fail(RCPSP_E_ARG, "192 threads per search needs the time-indexed decoder with one candidate per lane");
-    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 8 && p.lanes != 16)
-        return fail(RCPSP_E_ARG, "lanes must be 0, 1, 8 or 16");
+    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 8 && p.lanes != 16 && p.lanes != kLayoutWave)
+        return fail(RCPSP_E_ARG, "lanes must be 0, 1, 8, 16 or 64");
     if (p.lanes == 16 && s->dec != kEvalTime) return fail(RCPSP_E_ARG, "16 lanes per candidate needs the time-indexed decoder");
     if (p.lanes == 8 && s->dec != kEvalCapacity)
         return fail(RCPSP_E_ARG, "8 lanes per candidate needs the capacity-indexed decoder");
+    if (p.lanes == kLayoutWave && (s->dec != kEvalTime || (p.threads != 0 && p.threads != kWaveThreads)))
+        return fail(RCPSP_E_ARG, "one candidate per wave needs the time-indexed decoder and %d threads", kWaveThreads);
+    if (T0 == 512 && p.lanes != kLayoutWave && !(p.lanes == 8 && s->dec == kEvalCapacity))
+        return fail(RCPSP_E_ARG, "512 threads per search are for one candidate per wave (lanes 64) or "
+                                 "8 lanes per capacity-indexed candidate");
     int T = T0;
     rcpsp_status st = RCPSP_E_TOO_LARGE;
     auto try_shape = [&](int G, int Lreq) {
-        // 192 threads exist for the one-candidate-per-lane time-indexed layouts only
+        // 192 threads exist for the one-candidate-per-lane time-indexed layouts
+        // only, kWaveThreads for one candidate per wave (and nothing else)
         T = (T0 == 192 && (s->dec != kEvalTime || layout_is_group(G) || G == kLayoutRegs)) ? 128 : T0;
+        if (G == kLayoutWave) {
+            T = kWaveThreads;
+            st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, Lreq, s->reserve, &s->L, &s->Ly, G);
+            s->G = G;
+            return;
+        }
         st = plan_layout(I, s->dec, T, s->tcw, p.tabu_len, s->P, Lreq, s->reserve, &s->L, &s->Ly, G);
         while (st == RCPSP_E_TOO_LARGE && p.threads == 0 && T > 64) {
             T /= 2;
@@ -775,6 +816,10 @@ static rcpsp_status shape_plan(rcpsp_search *s) {
     } else {
         try_shape(1, p.profile_len);
     }
+    // no lane state fits: one time-indexed candidate per wave, else per 16
+    // lanes; one capacity-indexed candidate per 8 lanes
+    if (st == RCPSP_E_TOO_LARGE && p.lanes == 0 && s->dec == kEvalTime && p.threads == 0 && p.profile_len == 0)
+        try_shape(kLayoutWave, 0);
     if (st == RCPSP_E_TOO_LARGE && p.lanes == 0) try_shape(s->dec == kEvalTime ? 16 : 8, p.profile_len);
     if (st == RCPSP_E_TOO_LARGE && p.eval == RCPSP_EVAL_AUTO && s->dec == kEvalTime) {
         // automatic choice: no time-indexed profile fits, take the capacity-indexed decoder
@@ -1004,7 +1049,7 @@ extern "C" rcpsp_status rcpsp_search_get_config(const rcpsp_search *s, rcpsp_sea
     out->eval = s->dec;
     out->iteration_launches = s->iteration_launches;
     out->round_launches = s->round_launches;
-    out->lanes = layout_is_group(s->G) ? s->G : 1;
+    out->lanes = (layout_is_group(s->G) || s->G == kLayoutWave) ? s->G : 1;
     out->finish_bits = layout_finish_bits(s->G);
     out->register_profile = s->G == kLayoutRegs ? 1 : 0;
     return RCPSP_OK;
@@ -1405,10 +1450,12 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
     else lps = {1, 2};
     for (int ev : evals) {
       for (int G : lanes_c) {
-        if ((G == 16 && ev != kEvalTime) || (G == 8 && ev != kEvalCapacity)) continue;
-        // register profiles run at 256 threads whatever the search count
+        if ((G == 16 && ev != kEvalTime) || (G == 8 && ev != kEvalCapacity) || G == kLayoutWave) continue;
+        // register profiles run at 256 threads whatever the search count,
+        // capacity-indexed 8-lane groups also at 512
         std::vector<int> Ts = threads;
         if (!params->threads && std::find(Ts.begin(), Ts.end(), 256) == Ts.end()) Ts.push_back(256);
+        if (!params->threads && G == 8) Ts.push_back(512);
         for (int T : Ts)
         for (int lp : lps) {
             if (T == 256 && lp == 1 && std::find(threads.begin(), threads.end(), 256) == threads.end()) continue;
@@ -1460,6 +1507,46 @@ extern "C" rcpsp_status rcpsp_autotune(const rcpsp_instance *inst, const rcpsp_s
             }
         }
       }
+    }
+    // one time-indexed candidate per wave
+    const bool wave_ok = std::find(evals.begin(), evals.end(), kEvalTime) != evals.end() &&
+                         (params->lanes == 0 || params->lanes == kLayoutWave) &&
+                         (params->threads == 0 || params->threads == kWaveThreads) && !params->profile_len &&
+                         params->lane_profile != 2;
+    if (wave_ok) {
+        rcpsp_search_params q = *params;
+        q.eval = kEvalTime;
+        q.threads = kWaveThreads;
+        q.lanes = kLayoutWave;
+        q.lane_profile = 0;
+        q.profile_len = 0;
+        q.iterations = trial_iterations;
+        q.record_trajectory = 0;
+        q.count_work = 0;
+        rcpsp_search *s = nullptr;
+        rcpsp_status st = rcpsp_search_create(inst, &q, hip_stream, &s);
+        if (st != RCPSP_OK && st != RCPSP_E_TOO_LARGE) return st;
+        if (st == RCPSP_OK) {
+            double ms = 0.0;
+            rcpsp_search_result r{};
+            st = rcpsp_search_run(s, hip_stream);
+            if (st == RCPSP_OK) st = rcpsp_search_run_timed(s, hip_stream, nullptr, nullptr, &ms);
+            if (st == RCPSP_OK) st = rcpsp_search_results(s, &r, hip_stream);
+            rcpsp_search_destroy(s);
+            if (st != RCPSP_OK) return st;
+            ++trials;
+            const double ns = r.total_evaluations > 0 ? ms * 1e6 / (double)r.total_evaluations : ms * 1e6;
+            if (!found || ns < best_ns) {
+                found = true;
+                best_ns = ns;
+                best = *params;
+                best.eval = kEvalTime;
+                best.threads = kWaveThreads;
+                best.lanes = kLayoutWave;
+                best.lane_profile = 0;
+                best.profile_len = 0;
+            }
+        }
     }
     if (!found) return fail(RCPSP_E_TOO_LARGE, "no decoder/launch shape fits this instance");
     *out = best;
@@ -1534,7 +1621,7 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
         if (p.fbi) return fail(RCPSP_E_ARG, "batch member %d: forward-backward improvement is for search plans only", i);
         if (p.exchange_every > 1 || p.time_budget_us != 0)
             return fail(RCPSP_E_ARG, "batch member %d: batches exchange after every iteration and take no time budget", i);
-        if (p.threads == 0) p.threads = 64;
+        if (p.threads == 0) p.threads = p.lanes == kLayoutWave ? kWaveThreads : 64;
         p.count_work = 0;
         // the threads per search (chosen per group by the autotuner) are a
         // preference: a member whose workgroup does not fit takes fewer
@@ -1546,6 +1633,13 @@ static rcpsp_status build_batch(rcpsp_batch *bt, const rcpsp_instance *const *in
             s->p = p;
             s->reserve = kBatchStaticLds;
             st = alloc_plan(s);
+            if (st == RCPSP_E_TOO_LARGE && p.lanes == kLayoutWave) {
+                // no wave layout for this member: the automatic one
+                rcpsp_search_destroy(s);
+                p.lanes = 0;
+                p.threads = 256;
+                continue;
+            }
             if (st == RCPSP_E_TOO_LARGE && p.lane_profile == 2) {
                 // no register profile for this member: its profile in LDS
                 rcpsp_search_destroy(s);
@@ -1848,7 +1942,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         else threads = {64, 128, 192, 256};
         std::vector<int> lanes_c;
         if (p0.lanes) lanes_c.push_back(p0.lanes);
-        else lanes_c = {1, 8, 16};
+        else lanes_c = {1, 8, 16, kLayoutWave};
         std::vector<int> lps;
         if (p0.lane_profile) lps.push_back(p0.lane_profile);
         else lps = {1, 2};
@@ -1860,8 +1954,14 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         for (int ev : evals) {
           for (int G : lanes_c) {
             if ((G == 16 && ev != kEvalTime) || (G == 8 && ev != kEvalCapacity)) continue;
-            for (int T : threads)
-            for (int lp : lps) {
+            if (G == kLayoutWave && (ev != kEvalTime || (p0.threads && p0.threads != kWaveThreads))) continue;
+            // one candidate per wave: its own thread count, no lane profile choice
+            std::vector<int> Ts = G == kLayoutWave ? std::vector<int>{kWaveThreads} : threads;
+            if (G == 8 && !p0.threads) Ts.push_back(512);
+            const std::vector<int> lps_g = G == kLayoutWave ? std::vector<int>{0} : lps;
+            for (int T : Ts)
+            for (int lp : lps_g) {
+                if (T == 512 && G != kLayoutWave && G != 8) continue;
                 if (T == 192 && (ev != kEvalTime || G != 1)) continue;
                 if (lp == 2 && (ev != kEvalTime || G != 1 || T != 256 || !nw1)) continue;
                 for (auto &q : sp) {

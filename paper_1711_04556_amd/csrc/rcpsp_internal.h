@@ -23,8 +23,22 @@ constexpr int kEvalCapacity = 2;
 //      kRegUnits time units in registers (one dword per unit)
 //   8  one capacity-indexed candidate per 8 lanes (a lane per resource)
 //   16 one time-indexed candidate per 16 lanes
+//   64 one time-indexed candidate per wave, its profile spread over the
+//      wave's registers (kWaveDwords dwords per lane: 64 * kWaveDwords / NW
+//      time units), kWaveThreads threads
 constexpr int kLayoutRegs = 4;
 constexpr int kRegUnits = 160;
+constexpr int kLayoutWave = 64;
+constexpr int kWaveDwords = 32;
+constexpr int kWaveThreads = 512;
+constexpr int kWaveMaxN = 1024;  // finish times in registers: 16 per lane
+__host__ __device__ constexpr int wave_profile_units(int nw) { return 64 * (kWaveDwords / nw); }
+// A layout instantiated at T threads for decoder dec, for the set-up kernels
+// (which depend on T only): 512 threads exist for one candidate per wave
+// (time-indexed) and 8 lanes per candidate (capacity-indexed).
+__host__ __device__ constexpr int setup_layout(int T, int dec) {
+    return T == 512 ? (dec == kEvalTime ? kLayoutWave : 8) : 1;
+}
 __host__ __device__ constexpr bool layout_is_group(int G) { return G == 8 || G == 16; }
 __host__ __device__ constexpr int layout_finish_bits(int G) { return (G == 2 || G == kLayoutRegs) ? 8 : 16; }
 
@@ -52,7 +66,7 @@ struct InstDesc {
 
 // Dword offsets of the workgroup's LDS areas.
 struct Layout {
-    int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, prec, prq, predT, pin, bst, red, scal, region;
+    int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, prec, prq, predT, pin, pid, bst, red, scal, region;
     int per_lane;    // dwords of private decode state per candidate slot
     int base_stride; // dwords of each wave's base decode (one-candidate-per-lane layouts)
     int cands;       // candidate slots per round (threads, or threads / lanes per candidate)

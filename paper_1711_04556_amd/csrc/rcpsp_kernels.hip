@@ -38,14 +38,15 @@ hipError_t launch_search(const SearchArgs &A, int T, int nw, int dec, int G, siz
 hipError_t launch_fbi(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
     const int units = A.NF > 0 ? A.NF : A.B;
     if (units < 2) return hipSuccess;
-    RCPSP_DISPATCH(nw, T, dec, 1, {
+    // the set-up kernels run at the plan's threads (512 exist for two layouts only)
+    RCPSP_DISPATCH(nw, T, dec, setup_layout(T, dec), {
         hipLaunchKernelGGL((k_fbi<NW_, T_, DEC_>), dim3(units / 2), dim3(T_), lds, st, A);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_decode_records(const SearchArgs &A, int T, int nw, int dec, size_t lds, hipStream_t st) {
-    RCPSP_DISPATCH(nw, T, dec, 1, {
+    RCPSP_DISPATCH(nw, T, dec, setup_layout(T, dec), {
         hipLaunchKernelGGL((k_decode_records<NW_, T_, DEC_>), dim3(A.NF), dim3(T_), lds, st, A);
     });
     return hipGetLastError();

@@ -433,9 +433,9 @@ def test_group_decode_counts_same_work(rc):
 
 def test_large_instance_time_indexed_group(rc):
     """300 activities, 8 resources, durations 1..20: the per-lane profile does
-    not fit, so the automatic plan takes 16 lanes per candidate with the
-    time-indexed decoder; neighbourhood and a short cooperative search equal
-    the oracle."""
+    not fit; with 16 lanes per candidate and the time-indexed decoder the
+    neighbourhood (the evaluation entry point's automatic layout) and a
+    short cooperative search equal the oracle."""
     inst = synth.large_batch(1)[0]
     orc = oracle.Oracle(inst)
     gi = rc.Instance(inst, eval=TIME)
@@ -444,7 +444,8 @@ def test_large_instance_time_indexed_group(rc):
     mk_o, best_o = orc.evaluate_neighbourhood(W, 20, TIME)
     assert np.array_equal(mk_g, mk_o), np.nonzero(mk_g != mk_o)[0][:10]
     assert [best_g["u"], best_g["v"], best_g["makespan"], best_g["n_feasible"]] == best_o
-    plan = rc.SearchPlan(gi, rc.search_params(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, seed=3))
+    plan = rc.SearchPlan(gi, rc.search_params(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, seed=3,
+                                              lanes=16))
     assert plan.config["lanes"] == 16 and plan.config["eval"] == TIME
     plan.run()
     g = plan.results()
@@ -500,7 +501,7 @@ CAP_GROUP_CASES = GROUP_CASES[:4] + [
 
 
 @pytest.mark.parametrize("name,make,delta", CAP_GROUP_CASES, ids=[c[0] for c in CAP_GROUP_CASES])
-@pytest.mark.parametrize("threads", [64, 256])
+@pytest.mark.parametrize("threads", [64, 256, 512])
 def test_capacity_group_decode_search_parity(rc, name, make, delta, threads):
     inst = make()
     orc = oracle.Oracle(inst)
@@ -787,3 +788,118 @@ def test_register_profile_arguments(rc):
         with pytest.raises(rc.RcpspError) as e:
             rc.SearchPlan(gi, rc.search_params(6, 20, 5, searches=2, lane_profile=2, **bad))
         assert e.value.status == -1
+
+
+# ---------------------------------------------------------------------------
+# One candidate per wave (lanes = 64, 512 threads): the profile in the wave's
+# registers, 2048 / words-per-unit time units per bank.  Same results as the
+# oracle, including schedules past one bank (re-decoded over both) and past
+# both (group decode over the full horizon).
+
+def _scaled(make, k):
+    """Every duration multiplied by k (makespans scale by k)."""
+    def build():
+        b = make()
+        return synth.Instance(n=b.n, m=b.m, duration=[k * d for d in b.duration], capacity=b.capacity,
+                              request=b.request, succ=b.succ, name=f"{b.name}x{k}")
+    return build
+
+
+def _m8_16bit():
+    """8 resources with capacities above 127: four dwords per time unit
+    (512 units per bank)."""
+    b = synth.generate(50, 8, 20, 0.5, rs=None, cap_range=(10, 60), seed=4001)
+    return synth.Instance(n=b.n, m=b.m, duration=b.duration, capacity=[3 * c for c in b.capacity],
+                          request=[3 * r for r in b.request], succ=b.succ, name="m8x3")
+
+
+WAVE_CASES = [
+    ("table1", synth.table1_instance, 10, False),
+    ("g30", lambda: synth.single_instance_30(1), 8, False),
+    ("g60", lambda: synth.generate(60, 4, 10, 0.5, rs=0.3, seed=63), 14, False),
+    ("wide40", _wide_instance, 12, False),
+    ("m8", lambda: synth.generate(50, 8, 20, 0.5, rs=None, cap_range=(10, 60), seed=4001), 20, False),
+    ("m8x3", _m8_16bit, 20, False),
+    ("serial14", _serial_instance, 5, False),
+    ("g30x33", _scaled(lambda: synth.single_instance_30(1), 33), 8, True),    # around one bank
+    ("g30x66", _scaled(lambda: synth.single_instance_30(1), 66), 8, True),    # around both banks
+    ("g30x80", _scaled(lambda: synth.single_instance_30(1), 80), 8, True),    # past both banks
+]
+
+
+@pytest.mark.parametrize("name,make,delta,long", WAVE_CASES, ids=[c[0] for c in WAVE_CASES])
+@pytest.mark.parametrize("elite", [0, 4])
+def test_wave_layout_search_parity(rc, name, make, delta, long, elite):
+    inst = make()
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=delta, tabu_len=30, iterations=20, searches=6, elite=elite, phi_max=2, phi_steps=4,
+              seed=8)
+    plan = rc.SearchPlan(gi, rc.search_params(lanes=64, eval=TIME, **kw))
+    cfg = plan.config
+    assert cfg["lanes"] == 64 and cfg["threads"] == 512 and cfg["eval"] == TIME
+    print(f"wave {name} elite {elite}: {cfg}", flush=True)
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(delta, 30, 20, searches=6, elite=elite, phi_max=2, phi_steps=4, decoder=TIME, seed=8)
+    _compare_search(g, o, elite=elite)
+    assert (g["overflow_decodes"] > 0) == long
+
+
+def test_wave_layout_counts_same_work(rc):
+    """Decoded from position 0 (every candidate over both banks after the
+    loop), the wave decode counts the operations and cells of the lane
+    decode; with the shared prefix it gives the same search."""
+    inst = synth.generate(60, 4, 10, 0.5, rs=0.3, seed=24)
+    gi = rc.Instance(inst, eval=TIME)
+    kw = dict(swap_range=10, tabu_len=60, iterations=12, searches=6, elite=4, phi_steps=4, seed=6, count_work=True)
+    a = rc.tabu_search(gi, lanes=1, threads=256, full_decode=True, **kw)
+    b = rc.tabu_search(gi, lanes=64, full_decode=True, **kw)
+    c = rc.tabu_search(gi, lanes=64, **kw)
+    for k in ("trajectory", "best_makespan", "evaluations"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+    assert a["total_work"] == b["total_work"] > 0 and a["total_cells"] == b["total_cells"] > 0
+    assert 0 < c["total_work"] < b["total_work"]
+
+
+def test_wave_layout_large_instance(rc):
+    """300 activities, 8 resources, durations 1..20 (two dwords per unit,
+    1024 units per bank): the automatic plan takes one candidate per wave;
+    a cooperative search equals the oracle."""
+    inst = synth.large_batch(1)[0]
+    orc = oracle.Oracle(inst)
+    gi = rc.Instance(inst, eval=TIME)
+    plan = rc.SearchPlan(gi, rc.search_params(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, seed=3))
+    assert plan.config["lanes"] == 64 and plan.config["eval"] == TIME
+    plan.run()
+    g = plan.results()
+    plan.close()
+    o = orc.tabu_search(20, 60, 3, searches=4, elite=4, phi_max=2, phi_steps=4, decoder=TIME, seed=3)
+    _compare_search(g, o, elite=4)
+
+
+def test_batch_mixes_wave_lane_and_group_decode(rc):
+    insts = _batch_case()[:4] + [_scaled(lambda: synth.single_instance_30(1), 33)()]
+    gis = [rc.Instance(i, eval=TIME) for i in insts]
+    lanes = [64, 1, 16, 64, 64]
+    params = [rc.search_params(7, 30, 10, searches=5, elite=3, phi_max=2, phi_steps=4,
+                               threads=512 if lanes[k] == 64 else 64, lanes=lanes[k], seed=40 + k)
+              for k in range(len(insts))]
+    bt = rc.Batch(gis, params)
+    assert 512 in bt.info["class_threads"]
+    bt.run()
+    for k, inst in enumerate(insts):
+        o = oracle.Oracle(inst).tabu_search(7, 30, 10, searches=5, elite=3, phi_max=2, phi_steps=4, decoder=TIME,
+                                            seed=40 + k)
+        _compare_search(bt.results(k), o, elite=3)
+    bt.close()
+
+
+def test_wave_layout_arguments(rc):
+    gi = rc.Instance(synth.single_instance_30(1), eval=TIME)
+    for bad in (dict(lanes=64, threads=256), dict(threads=512), dict(lanes=64, eval=CAP)):
+        with pytest.raises(rc.RcpspError) as e:
+            rc.SearchPlan(gi, rc.search_params(6, 20, 5, searches=2, **bad))
+        assert e.value.status == -1, bad
