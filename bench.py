@@ -42,7 +42,7 @@ BATCH = dict(count=1024, base_seed=3000, searches=32, elite=16, phi_max=3, phi_s
 BATCH_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329)}
 # serving leg: open-loop Poisson arrivals, 50 ms budget from admission
 SERVE = dict(rate=2000.0, warmup_s=2.0, measure_s=10.0, budget_us=50000, searches=16, elite=16, iterations=1000,
-             phi_max=3, phi_steps=20, seed=5, pool=256, max_active=1024)
+             phi_max=3, phi_steps=20, seed=5, pool=256, max_active=1024, reduced_rate=400.0, reduced_measure_s=6.0)
 SERVE_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329), 302: (20, 869)}
 # large-instance leg: 256 instances of 300 activities, 8 resources; the
 # workload's 2000 iterations take tens of minutes at the measured rate, so
@@ -456,7 +456,7 @@ def pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
-def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
+def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s, big_threads=128):
     """Config: Poisson arrivals at `rate`/s, sizes uniform over 30/60/120/300
     activities, 16 searches and a working set of 16 per request, 50 ms
     budget from admission.  Latency = time the result is available to the
@@ -472,7 +472,7 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
         big = n >= 300
         base = rcpsp.search_params(d, tl, SERVE["iterations"], searches=SERVE["searches"], elite=SERVE["elite"],
                                    phi_max=SERVE["phi_max"], phi_steps=SERVE["phi_steps"],
-                                   threads=128 if big else 64, lanes=8 if big else 0,
+                                   threads=big_threads if big else 64, lanes=8 if big else 0,
                                    eval=rcpsp.EVAL_CAPACITY if big else rcpsp.EVAL_AUTO,
                                    record_trajectory=False, seed=SERVE["seed"])
         # decoder and lanes per size from the batch autotuner on a sample, at
@@ -481,7 +481,9 @@ def serving_leg(rcpsp, synth, stream, rate, warmup_s, measure_s):
         # is a class of its own with the longest tasks; the autotuner ranks
         # shapes by one iteration's throughput, which says nothing about task
         # length, so it takes the shape measured best for serving latency:
-        # capacity-indexed, 8 lanes per candidate, 128 threads
+        # capacity-indexed, 8 lanes per candidate, 512 threads (one search
+        # per CU: an iteration of a request's 16 searches in ~0.1 s, where
+        # 128 threads took longer than the budget)
         tuned, info = rcpsp.batch_autotune(lst[:8], base, trial_iterations=1, sample=8, stream=stream)
         params[n] = tuned[0]
         tuning[str(n)] = dict(eval=info["group_eval"][0], threads=info["group_threads"][0],
@@ -672,6 +674,10 @@ def main():
                     help="also run periodic decoder re-selection with this period (two periods)")
     ap.add_argument("--serve-rate", type=float, default=SERVE["rate"])
     ap.add_argument("--serve-seconds", type=float, default=SERVE["measure_s"])
+    ap.add_argument("--serve-big-threads", type=int, default=512,
+                    help="threads per search of the 300-activity serving class")
+    ap.add_argument("--serve-reduced-rate", type=float, default=SERVE["reduced_rate"],
+                    help="second serving run at this arrival rate (0 = off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the searches would shard across "
@@ -816,6 +822,7 @@ def main():
         "batched": None,
         "hosted": None,
         "serving": None,
+        "serving_reduced": None,
         "large": None,
         "cpu_baseline": None,
     }
@@ -837,7 +844,14 @@ def main():
     if not args.no_large:
         out["large"] = large_leg(rcpsp, synth, stream, 1)
     if not args.no_serve:
-        out["serving"] = serving_leg(rcpsp, synth, stream, args.serve_rate, SERVE["warmup_s"], args.serve_seconds)
+        out["serving"] = serving_leg(rcpsp, synth, stream, args.serve_rate, SERVE["warmup_s"], args.serve_seconds,
+                                     args.serve_big_threads)
+        if args.serve_reduced_rate > 0:
+            # the 300-activity requests cost ~1.5 GPUs at 2000 requests/s (16
+            # searches x ~4,750 evaluations per iteration each): a rate at
+            # which they still get their first iteration within the budget
+            out["serving_reduced"] = serving_leg(rcpsp, synth, stream, args.serve_reduced_rate, SERVE["warmup_s"],
+                                                 SERVE["reduced_measure_s"], args.serve_big_threads)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, dec)
         log("cpu baseline", out["cpu_baseline"])

@@ -792,13 +792,15 @@ __device__ inline int wave_max_uniform(int x) { return -wave_min_uniform(-x); }
 // Per activity (the positions are the same for the whole wave), Alg. 5 is a
 // sweep over the time units common to the wave: unit t is examined by every
 // lane whose scan is under way (t at or past its precedence earliest start,
-// no start found yet), each lane keeping the run of free units that ends at
-// t; the first t where the run reaches d gives that lane's start t + 1 - d.
-// The sweep starts at the block holding the wave's smallest earliest start
-// and ends when every lane has its start.  Alg. 6 is a second sweep over the
-// units covered by any lane's interval, each lane subtracting its request
-// inside its own [s, s + d).  Blocks of four units outside a sweep's range
-// are skipped by scalar branches.  A lane whose start is not found within
+// no start found yet), each lane keeping the last unit short of capacity it
+// has seen; the first t at least d units past it gives that lane's start
+// t + 1 - d.  The sweep starts at the block holding the wave's smallest
+// earliest start and ends after the first block (of kRegBlock units) by
+// which every lane has its start.  Alg. 6 is a second sweep over the units
+// covered by any lane's interval, each lane subtracting its request inside
+// its own [s, s + d).  Blocks outside a sweep's range are skipped by scalar
+// branches (eight-unit blocks measured best: fewer block tests than four,
+// fewer units past the last start than sixteen).  A lane whose start is not found within
 // the kRegUnits units (or whose finish passes 255) reports overflow and runs
 // along without touching its profile, like decode_ti.  Lanes without a
 // candidate (idle) take part in the sweeps' collective steps only.
@@ -806,7 +808,7 @@ __device__ inline int wave_max_uniform(int x) { return -wave_min_uniform(-x); }
 // The profile is initialised from the wave's base decode: units below its
 // frontier from the base profile (16-byte aligned, stride 1), the others at
 // the full capacity.  COUNT counts what decode_ti counts.
-constexpr int kRegBlock = 4;
+constexpr int kRegBlock = 8;
 
 template <int T, bool COUNT>
 __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, const uint32_t *bprof, int front,
@@ -863,8 +865,9 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
             // Alg. 5: lanes still scanning are `todo`
             const int tmin = wave_min_uniform(need ? es : 0x7fffffff);
             // per lane: lm = the last unit short of capacity seen (es - 1 to
-            // begin with: earlier units do not count), ft = the first unit t
-            // with t - lm >= d, i.e. closing d free units from lm + 1 on
+            // begin with: earlier units do not count); the lane is done at
+            // the first unit t with t - lm >= d (d free units from lm + 1
+            // on), after which lm stays: its start is lm + 1
             int lm = es - 1, ft = 0x7fffffff;
 #pragma unroll
             for (int b = 0; b < kRegUnits; b += kRegBlock) {
