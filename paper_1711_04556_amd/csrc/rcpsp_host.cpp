@@ -1946,8 +1946,10 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         std::vector<int> lps;
         if (p0.lane_profile) lps.push_back(p0.lane_profile);
         else lps = {1, 2};
-        bool nw1 = true;
-        for (int k = 0; k < ns; ++k) nw1 = nw1 && si[k]->desc.nw == 1;
+        // register profiles where a member's time unit packs into one dword
+        // (the batch keeps the others in LDS): a candidate when any does
+        bool nw1 = false;
+        for (int k = 0; k < ns; ++k) nw1 = nw1 || si[k]->desc.nw == 1;
         bool found = false;
         double best_rate = 0.0;
         int best_eval = 0, best_T = 0, best_G = 1, best_lp = 1;
