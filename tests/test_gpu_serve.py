@@ -133,3 +133,35 @@ def test_server_cancel_and_footprint(rc):
         assert np.array_equal(g[key], o[key]), key
     srv.release(t)
     srv.close()
+
+
+@pytest.mark.parametrize("dec,threads,lanes", [(CAP, 512, 8), (TIME, 512, 64), (TIME, 256, 0)])
+def test_server_wide_workgroup_classes(rc, dec, threads, lanes):
+    """Launch classes of 512-thread workgroups (capacity-indexed 8-lane
+    groups, one time-indexed candidate per wave) and 256-thread register
+    profiles, beside a one-wave class, each request against the oracle
+    replay of the iterations it ran."""
+    srv = rc.Server(max_active=6, slice_us=500)
+    items = []
+    for i in range(4):
+        inst = synth.generate(40 + 10 * i, 8 if dec == CAP else 4, 12, 0.5, rs=0.4, seed=950 + i)
+        gi = rc.Instance(inst, eval=dec)
+        wide = i % 2 == 0
+        p = rc.search_params(8, 30, 25, searches=4, elite=4, phi_max=2, phi_steps=4, seed=60 + i,
+                             threads=threads if wide else 64, lanes=lanes if wide else 0,
+                             lane_profile=2 if (wide and threads == 256) else 0, eval=dec)
+        items.append((srv.submit(gi, p, 0), inst, gi, p))
+    t_end = time.time() + 60
+    pending = list(items)
+    while pending and time.time() < t_end:
+        for item in list(pending):
+            t, inst, gi, p = item
+            if srv.poll(t)["state"] == rc.REQ_DONE:
+                st = _check_against_oracle(rc, srv, t, inst, dec, p)
+                # all iterations, or the working set reached the critical path
+                assert st["iterations"] == p.iterations or st["best_makespan"] == gi.info["critical_path"]
+                srv.release(t)
+                pending.remove(item)
+        time.sleep(0.002)
+    assert not pending
+    srv.close()
