@@ -429,6 +429,7 @@ def large_leg(rcpsp, synth, stream, steps):
         s_ev += cr["total_evaluations"]
     value = evals * steps / dt
     ops_ev = s_work / max(s_ev, 1)
+    cpm = [100.0 * (r["global_best"] - g.info["critical_path"]) / g.info["critical_path"] for r, g in zip(res, gis)]
     out = {
         "workload": f"{len(insts)} instances of 300 activities (8 resources, durations 1..20, capacities 10..60), "
                     f"{LARGE['searches']} searches and working set {LARGE['elite']} each, swap range 20, tabu list "
@@ -439,6 +440,7 @@ def large_leg(rcpsp, synth, stream, steps):
         "iterations_timed": LARGE["iterations"],
         "ms_per_iteration": dt / steps / LARGE["iterations"] * 1e3,
         "evaluations_per_step": evals,
+        "mean_cpm_dev_pct": sum(cpm) / len(cpm),
         "roofline": dict(bound="alu", achieved=value * ops_ev / 1e12, peak=PEAK_INT_OPS / 1e12, unit="Tops/s",
                          frac=value * ops_ev / PEAK_INT_OPS, ops_per_evaluation=ops_ev,
                          cells_per_evaluation=s_cells / max(s_ev, 1),

@@ -792,9 +792,9 @@ __device__ inline int wave_max_uniform(int x) { return -wave_min_uniform(-x); }
 // Per activity (the positions are the same for the whole wave), Alg. 5 is a
 // sweep over the time units common to the wave: unit t is examined by every
 // lane whose scan is under way (t at or past its precedence earliest start,
-// no start found yet), each lane keeping the last unit short of capacity it
-// has seen; the first t at least d units past it gives that lane's start
-// t + 1 - d.  The sweep starts at the block holding the wave's smallest
+// no start found yet), each lane keeping the unit at which d free units
+// after the last unit short of capacity it has seen would close; once the
+// sweep reaches that unit the lane's start is fixed.  The sweep starts at the block holding the wave's smallest
 // earliest start and ends after the first block (of kRegBlock units) by
 // which every lane has its start.  Alg. 6 is a second sweep over the units
 // covered by any lane's interval, each lane subtracting its request inside
@@ -864,11 +864,11 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
         if (__builtin_amdgcn_ballot_w64(need) != 0ull) {
             // Alg. 5: lanes still scanning are `todo`
             const int tmin = wave_min_uniform(need ? es : 0x7fffffff);
-            // per lane: lm = the last unit short of capacity seen (es - 1 to
-            // begin with: earlier units do not count); the lane is done at
-            // the first unit t with t - lm >= d (d free units from lm + 1
-            // on), after which lm stays: its start is lm + 1
-            int lm = es - 1, ft = 0x7fffffff;
+            // per lane: lmd = lm + d, lm the last unit short of capacity seen
+            // (es - 1 to begin with: earlier units do not count); d free
+            // units from lm + 1 on close at unit lmd, after which lmd stays
+            // (the start is lmd + 1 - d)
+            int lmd = es - 1 + d, tl = 0;
 #pragma unroll
             for (int b = 0; b < kRegUnits; b += kRegBlock) {
                 if (b + kRegBlock <= tmin) continue;
@@ -876,13 +876,14 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
                 for (int k = 0; k < kRegBlock; ++k) {
                     const int t = b + k;
                     const bool mis = ((P[t] - rq) & Gd) != Gd;
-                    lm = mis ? max(lm, t) : lm;
-                    ft = (t - lm >= d) ? min(ft, t) : ft;
+                    const int c = mis ? t + d : lmd;
+                    lmd = (t <= lmd) ? max(c, lmd) : lmd;
                 }
-                if (__builtin_amdgcn_ballot_w64(need && ft == 0x7fffffff) == 0ull) break;
+                tl = b + kRegBlock - 1;
+                if (__builtin_amdgcn_ballot_w64(need && lmd > tl) == 0ull) break;
             }
-            const bool todo = need && ft == 0x7fffffff;
-            if (need && !todo) s = ft + 1 - d;
+            const bool todo = need && lmd > tl;
+            if (need && !todo) s = lmd + 1 - d;
             // no start within the register profile: the long-profile path
             over = over || todo;
             // Alg. 6 over the units some lane covers
