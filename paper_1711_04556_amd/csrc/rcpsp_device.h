@@ -889,12 +889,11 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
             // Alg. 6 over the units some lane covers
             const bool upd = need && !todo;
             if (__builtin_amdgcn_ballot_w64(upd) != 0ull) {
-                const int smin = wave_min_uniform(upd ? s : 0x7fffffff);
-                const int emax = wave_max_uniform(upd ? s + d : 0);
+                // every interval lies in the swept units [tmin, tl]
 #pragma unroll
                 for (int b = 0; b < kRegUnits; b += kRegBlock) {
-                    if (b + kRegBlock <= smin) continue;
-                    if (b >= emax) break;
+                    if (b + kRegBlock <= tmin) continue;
+                    if (b > tl) break;
 #pragma unroll
                     for (int k = 0; k < kRegBlock; ++k) {
                         const int t = b + k;
