@@ -869,19 +869,27 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
             // units from lm + 1 on close at unit lmd, after which lmd stays
             // (the start is lmd + 1 - d)
             int lmd = es - 1 + d, tl = 0;
+            // blocks below tmin are skipped four at a time, then one at a time
+            constexpr int kSuper = 4 * kRegBlock;
+            static_assert(kRegUnits % kSuper == 0, "profile in whole groups of four blocks");
 #pragma unroll
-            for (int b = 0; b < kRegUnits; b += kRegBlock) {
-                if (b + kRegBlock <= tmin) continue;
+            for (int B = 0; B < kRegUnits; B += kSuper) {
+                if (B + kSuper <= tmin) continue;
 #pragma unroll
-                for (int k = 0; k < kRegBlock; ++k) {
-                    const int t = b + k;
-                    const bool mis = ((P[t] - rq) & Gd) != Gd;
-                    const int c = mis ? t + d : lmd;
-                    lmd = (t <= lmd) ? max(c, lmd) : lmd;
+                for (int b = B; b < B + kSuper; b += kRegBlock) {
+                    if (b + kRegBlock <= tmin) continue;
+#pragma unroll
+                    for (int k = 0; k < kRegBlock; ++k) {
+                        const int t = b + k;
+                        const bool mis = ((P[t] - rq) & Gd) != Gd;
+                        const int c = mis ? t + d : lmd;
+                        lmd = (t <= lmd) ? max(c, lmd) : lmd;
+                    }
+                    tl = b + kRegBlock - 1;
+                    if (__builtin_amdgcn_ballot_w64(need && lmd > tl) == 0ull) goto scan_done;
                 }
-                tl = b + kRegBlock - 1;
-                if (__builtin_amdgcn_ballot_w64(need && lmd > tl) == 0ull) break;
             }
+        scan_done:
             const bool todo = need && lmd > tl;
             if (need && !todo) s = lmd + 1 - d;
             // no start within the register profile: the long-profile path
@@ -891,14 +899,19 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
             if (__builtin_amdgcn_ballot_w64(upd) != 0ull) {
                 // every interval lies in the swept units [tmin, tl]
 #pragma unroll
-                for (int b = 0; b < kRegUnits; b += kRegBlock) {
-                    if (b + kRegBlock <= tmin) continue;
-                    if (b > tl) break;
+                for (int B = 0; B < kRegUnits; B += kSuper) {
+                    if (B + kSuper <= tmin) continue;
+                    if (B > tl) break;
 #pragma unroll
-                    for (int k = 0; k < kRegBlock; ++k) {
-                        const int t = b + k;
-                        const bool in = upd && (unsigned)(t - s) < (unsigned)d;
-                        P[t] -= in ? rq : 0u;
+                    for (int b = B; b < B + kSuper; b += kRegBlock) {
+                        if (b + kRegBlock <= tmin) continue;
+                        if (b > tl) break;
+#pragma unroll
+                        for (int k = 0; k < kRegBlock; ++k) {
+                            const int t = b + k;
+                            const bool in = upd && (unsigned)(t - s) < (unsigned)d;
+                            P[t] -= in ? rq : 0u;
+                        }
                     }
                 }
             }
