@@ -771,12 +771,16 @@ __device__ int decode_tg(const Sh &S, const InstDesc &D, uint32_t *cb, int L, in
 
 // Minimum and maximum over the 64 lanes of a wave as wave-uniform values
 // (every lane must be active): DPP moves inside each row of 16 lanes, then
-// the four row results in scalar registers.
+// the four row results in scalar registers.  Every lane of a row has a
+// source under these four patterns, so the "old" operand is never taken;
+// giving it the identity of min lets the compiler fold each move into the
+// min as a DPP operand.
 __device__ inline int wave_min_uniform(int x) {
-    x = min(x, __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
-    x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
-    x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false));   // row_half_mirror
-    x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x140, 0xF, 0xF, false));   // row_mirror
+    constexpr int kId = 0x7fffffff;
+    x = min(x, __builtin_amdgcn_update_dpp(kId, x, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+    x = min(x, __builtin_amdgcn_update_dpp(kId, x, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+    x = min(x, __builtin_amdgcn_update_dpp(kId, x, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    x = min(x, __builtin_amdgcn_update_dpp(kId, x, 0x140, 0xF, 0xF, false));   // row_mirror
     const int a = __builtin_amdgcn_readlane(x, 0), b = __builtin_amdgcn_readlane(x, 16);
     const int c = __builtin_amdgcn_readlane(x, 32), e = __builtin_amdgcn_readlane(x, 48);
     return min(min(a, b), min(c, e));
@@ -864,11 +868,17 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
         if (__builtin_amdgcn_ballot_w64(need) != 0ull) {
             // Alg. 5: lanes still scanning are `todo`
             const int tmin = wave_min_uniform(need ? es : 0x7fffffff);
-            // per lane: lmd = lm + d, lm the last unit short of capacity seen
-            // (es - 1 to begin with: earlier units do not count); d free
-            // units from lm + 1 on close at unit lmd, after which lmd stays
-            // (the start is lmd + 1 - d)
-            int lmd = es - 1 + d, tl = 0;
+            // per lane: lm is the last unit short of capacity that lies in
+            // the free run being grown (es - 1 to begin with: earlier units
+            // do not count); a shortfall at t restarts the run only while
+            // the run is still open (lm < t <= lm + d), so units past a
+            // closed run, and units before es, leave lm alone; the start is
+            // lm + 1
+            int lm = es - 1, tl = 0;
+            // lanes that place nothing scan with a run length no unit can
+            // reach, which keeps them out of the block-end test
+            int dd = need ? d : -(1 << 20);
+            asm volatile("" : "+v"(dd));
             // blocks below tmin are skipped four at a time, then one at a time
             constexpr int kSuper = 4 * kRegBlock;
             static_assert(kRegUnits % kSuper == 0, "profile in whole groups of four blocks");
@@ -882,20 +892,22 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
                     for (int k = 0; k < kRegBlock; ++k) {
                         const int t = b + k;
                         const bool mis = ((P[t] - rq) & Gd) != Gd;
-                        const int c = mis ? t + d : lmd;
-                        lmd = (t <= lmd) ? max(c, lmd) : lmd;
+                        const bool open = (unsigned)(t - 1 - lm) < (unsigned)dd;
+                        lm = (mis && open) ? t : lm;
                     }
                     tl = b + kRegBlock - 1;
-                    if (__builtin_amdgcn_ballot_w64(need && lmd > tl) == 0ull) goto scan_done;
+                    if (__builtin_amdgcn_ballot_w64(lm + dd > tl) == 0ull) goto scan_done;
                 }
             }
         scan_done:
-            const bool todo = need && lmd > tl;
-            if (need && !todo) s = lmd + 1 - d;
+            const bool todo = need && lm + d > tl;
+            if (need && !todo) s = lm + 1;
             // no start within the register profile: the long-profile path
             over = over || todo;
             // Alg. 6 over the units some lane covers
             const bool upd = need && !todo;
+            // lanes without an interval subtract over an empty one
+            const int se = upd ? s + d : s;
             if (__builtin_amdgcn_ballot_w64(upd) != 0ull) {
                 // every interval lies in the swept units [tmin, tl]
 #pragma unroll
@@ -906,12 +918,14 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
                     for (int b = B; b < B + kSuper; b += kRegBlock) {
                         if (b + kRegBlock <= tmin) continue;
                         if (b > tl) break;
+                        // the lane's interval as a mask over the block's
+                        // units; unit k takes bit k, sign-extended
+                        const int a0 = min(max(s - b, 0), kRegBlock);
+                        const int a1 = min(max(se - b, 0), kRegBlock);
+                        const uint32_t m = ((1u << a1) - 1u) ^ ((1u << a0) - 1u);
 #pragma unroll
-                        for (int k = 0; k < kRegBlock; ++k) {
-                            const int t = b + k;
-                            const bool in = upd && (unsigned)(t - s) < (unsigned)d;
-                            P[t] -= in ? rq : 0u;
-                        }
+                        for (int k = 0; k < kRegBlock; ++k)
+                            P[b + k] -= (uint32_t)__builtin_amdgcn_sbfe((int)m, k, 1) & rq;
                     }
                 }
             }
