@@ -2420,12 +2420,23 @@ __device__ inline int iterations_assigned(int iblock, int ck, int cstar, int ic,
 // bookkeeping is sequential; the data moves are done by the readers
 // themselves in their next step, from the record buffer or from the writer's
 // export buffer they were pointed at.  rs: 6B + 5NF ints of LDS scratch.
+//
+// The fired searches are first listed in ascending id (wave ballots); one
+// thread then walks the list touching LDS only, and leaves per search what
+// its read saw (source, record makespan, C* and the record's iteration count
+// at that moment); eq. 8's table lookups and the searches' scalars in global
+// memory are done afterwards by all threads.
 template <int T>
 __device__ void exchange_round(const SearchArgs &A, int parity, int init, int *rs) {
     const int B = A.B, NF = A.NF, tid = threadIdx.x, N2 = n2(A.D.n), tcn = A.D.n * A.tcw;
+    // per search b (in order of use): fired flag, then the read's source;
+    // slot; iterations since the read, then the record's count at the read;
+    // C_imp, then the record's makespan; C_read, then C* at the read
     int *fired = rs, *slot = rs + B, *itr = rs + 2 * B, *cimp = rs + 3 * B, *cread = rs + 4 * B;
-    int *cstar_s = rs + 5 * B;
+    int *list = rs + 5 * B;
     int *fC = rs + 6 * B, *fIC = fC + NF, *fR = fIC + NF, *fB = fR + NF, *content = fB + NF;
+    __shared__ int wcnt[T / 64];
+    __shared__ int nfired, cstar_s;
     for (int b = tid; b < B; b += T) {
         const SearchScalars &s = A.sc[b];
         if (init) {
@@ -2450,41 +2461,74 @@ __device__ void exchange_round(const SearchArgs &A, int parity, int init, int *r
         content[k] = -1;
     }
     __syncthreads();
+    // list of the fired searches in ascending id
+    {
+        const int w = tid >> 6, lane = tid & 63;
+        int base = 0;
+        for (int b0 = 0; b0 < B; b0 += T) {
+            const int b = b0 + tid;
+            const bool f = b < B && fired[b] != 0;
+            const unsigned long long m = __ballot(f);
+            if (lane == 0) wcnt[w] = __popcll(m);
+            __syncthreads();
+            int off = base, tot = 0;
+#pragma unroll
+            for (int j = 0; j < T / 64; ++j) {
+                off += j < w ? wcnt[j] : 0;
+                tot += wcnt[j];
+            }
+            if (f) list[off + __popcll(m & ((1ull << lane) - 1ull))] = b;
+            base += tot;
+            __syncthreads();
+        }
+        if (tid == 0) nfired = base;
+    }
     if (tid == 0) {
         int cstar = 0x7fffffff;
         for (int k = 0; k < NF; ++k) cstar = min(cstar, fC[k]);
-        for (int b = 0; b < B; ++b) {
-            if (!fired[b]) continue;
+        const int nf = nfired;
+        for (int i = 0; i < nf; ++i) {
+            const int b = list[i];
             const int k = slot[b];
+            const int ci = cimp[b], cr = cread[b];
             fIC[k] += itr[b];
-            if (cimp[b] < cread[b] && cimp[b] < fC[k]) {
-                fC[k] = cimp[b];
+            if (ci < cr && ci < fC[k]) {
+                fC[k] = ci;
                 fIC[k] = 0;
                 fR[k] = 0;
                 content[k] = b;
-                cstar = min(cstar, fC[k]);
+                cstar = min(cstar, ci);
             }
             const int k2 = (k + 1) % NF;
-            fR[k2] += 1;
-            SearchScalars &s = A.sc[b];
-            if (content[k2] < 0) {
-                s.src_kind = kSrcRecord;
-                s.src_idx = k2;
-                s.src_buf = fB[k2];
-            } else {
-                s.src_kind = kSrcExport;
-                s.src_idx = content[k2];
-                s.src_buf = parity;
-            }
-            s.src_C = fC[k2];
-            s.C_read = fC[k2];
-            s.I_assigned = iterations_assigned(A.iters, fC[k2], cstar, fIC[k2], A.decay, A.decay_len);
-            s.flags |= kFlagReadPending | (fR[k2] > A.phi_max ? kFlagDiversify : 0);
-            s.slot = k2;
-            s.it_read = 0;
-            s.fired = 0;
+            const int reads = fR[k2] + 1;
+            fR[k2] = reads;
+            // the source: bits 0-23 index (searches and records number far
+            // fewer: 6B ints of scratch fit in LDS), bit 24 export, bit 25
+            // buffer, bit 26 diversify
+            const int w = content[k2];
+            const int src = w < 0 ? (k2 | (fB[k2] << 25)) : (w | (1 << 24) | (parity << 25));
+            fired[b] = src | (reads > A.phi_max ? 1 << 26 : 0);
+            cimp[b] = fC[k2];
+            cread[b] = cstar;
+            itr[b] = fIC[k2];
         }
-        *cstar_s = cstar;
+        cstar_s = cstar;
+    }
+    __syncthreads();
+    for (int i = tid; i < nfired; i += T) {
+        const int b = list[i];
+        const int src = fired[b];
+        SearchScalars &s = A.sc[b];
+        s.src_kind = (src >> 24) & 1 ? kSrcExport : kSrcRecord;
+        s.src_idx = src & 0xffffff;
+        s.src_buf = (src >> 25) & 1;
+        s.src_C = cimp[b];
+        s.C_read = cimp[b];
+        s.I_assigned = iterations_assigned(A.iters, cimp[b], cread[b], itr[b], A.decay, A.decay_len);
+        s.flags |= kFlagReadPending | ((src >> 26) & 1 ? kFlagDiversify : 0);
+        s.slot = (slot[b] + 1) % NF;
+        s.it_read = 0;
+        s.fired = 0;
     }
     __syncthreads();
     // final content of each written record -> its other buffer
@@ -2507,8 +2551,8 @@ __device__ void exchange_round(const SearchArgs &A, int parity, int init, int *r
         A.Fmeta[k].buf = content[k] >= 0 ? (fB[k] ^ 1) : fB[k];
     }
     if (tid == 0) {
-        A.g->Cstar = *cstar_s;
-        A.g->gstop = *cstar_s == A.D.cp;
+        A.g->Cstar = cstar_s;
+        A.g->gstop = cstar_s == A.D.cp;
     }
     __threadfence();
     __syncthreads();
