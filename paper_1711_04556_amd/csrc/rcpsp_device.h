@@ -980,11 +980,15 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
     Work lw{0, 0};
     int *ovf_n = S.scal;                  // overflowed candidates
     int *bstate = S.scal + 1 + 3 * wv;    // this wave's base decode: positions done, front, overflowed
+    int *next_chunk = S.scal + 1 + 3 * (T / 64);
     // this wave's base decode, 16-byte aligned (register layout: its profile,
     // after the finish times, is the aligned part)
     uint32_t *bst = S.bst + wv * Ly.base_stride + (REG ? ((-f_dwords<FB>(D.n)) & 3) : 0);
     const bool use_base = share;
-    if (tid == 0) *ovf_n = 0;
+    if (tid == 0) {
+        *ovf_n = 0;
+        *next_chunk = T / 64;
+    }
     if (lane == 0) {
         bstate[0] = 0;
         bstate[1] = 0;
@@ -993,7 +997,13 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
     }
     __syncthreads();
     uint32_t *lane_base = S.region + tid;
-    for (int j0 = wv * 64; j0 < nfeas; j0 += T) {
+    // Chunks of 64 moves in canonical order: wave w starts with chunk w and
+    // then takes the next chunk not yet taken, so chunks with early u (the
+    // longest decodes) go first and the waves finish close together; each
+    // wave still meets its chunks in ascending order, as its base decode
+    // needs.  Counting runs keep the fixed order (chunks w, w + T/64, ...)
+    // so that the base decodes' work does not depend on timing.
+    for (int j0 = wv * 64; j0 < nfeas;) {
         if (use_base) {
             const int ulo = S.moves[j0] & 0xffff;
             if constexpr (DEC == kEvalTime) {
@@ -1079,6 +1089,13 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
             }
         }
         __builtin_amdgcn_wave_barrier();
+        if constexpr (COUNT) {
+            j0 += T;
+        } else {
+            int c = 0;
+            if (lane == 0) c = atomicAdd(next_chunk, 1);
+            j0 = __builtin_amdgcn_readlane(c, 0) * 64;
+        }
     }
     __syncthreads();
     if constexpr (DEC == kEvalTime) {
