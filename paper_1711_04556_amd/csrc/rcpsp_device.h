@@ -1399,22 +1399,28 @@ __device__ inline int decode_grp(const Sh &S, const InstDesc &D, uint32_t *cb, i
     else return decode_tg<NW, G, COUNT>(S, D, cb, L, u, v, p0, p1, front, ovf, wk);
 }
 
-// Group version of evaluate_moves: T/G candidates per round, one per group
-// of G lanes.  The shared prefix is decoded by group 0 into the base area;
-// candidates that overflow their profile are decoded afterwards by group 0
+// Group version of evaluate_moves: one candidate per group of G lanes,
+// chunks of 64/G moves per wave.  Waves take chunks in canonical order from
+// a counter and run independently, sharing one base decode (the prefix
+// before the chunk's smallest u): chunk k's wave waits until chunk k - 1's
+// wave has copied the base, extends it with its first group and copies it
+// into its groups' states, then lets chunk k + 1 go on while it decodes.
+// Candidates that overflow their profile are decoded afterwards by group 0
 // over the whole candidate region (>= horizon units).
 template <int NW, int T, int DEC, int G, bool COUNT = false>
 __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, const Layout &Ly, int nfeas,
                                                int L, int delta, TabuSrc tabu, int asp, int *out_mk,
                                                long long *ovf_total, Work *work_total = nullptr,
                                                bool share = true) {
-    constexpr int C = T / G;
     constexpr bool CAP = DEC == kEvalCapacity;
     const int tid = threadIdx.x, grp = tid / G, g = tid & (G - 1);
     unsigned long long best = ~0ull;
     Work lw{0, 0};
+    constexpr int CW = 64 / G;   // candidates per wave chunk
+    const int wv = tid >> 6, lane = tid & 63, gw = lane / G;
     int *ovf_n = S.scal;
     int *bstate = S.scal + 1;
+    int *next_chunk = S.scal + 4, *copied = S.scal + 5;
     const bool use_base = share;
     const int F0 = (D.n + 1) >> 1, Cd = (D.sum_r + 1) >> 1;
     if (tid == 0) {
@@ -1422,16 +1428,28 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
         bstate[0] = 0;
         bstate[1] = 0;
         bstate[2] = 0;
+        *next_chunk = T / 64;
+        *copied = -1;
     }
     // capacity-indexed states start with every c_k entry at zero
     if (CAP && use_base)
         for (int i = tid; i < Cd; i += T) S.bst[F0 + i] = 0u;
     __syncthreads();
     uint32_t *cb = S.region + grp * Ly.per_lane;
-    for (int j0 = 0; j0 < nfeas; j0 += C) {
+    for (int k = wv; k * CW < nfeas;) {
+        const int j0 = k * CW;
+        const int j = j0 + gw;
+        const bool has = j < nfeas;
+        const uint32_t mv = has ? S.moves[j] : 0u;
+        int p0 = 0, front = 0;
+        bool from_base = false;
         if (use_base) {
+            // the base decode is chunk k's once chunk k - 1's copies are
+            // done (every lane reads the flag: one load, one value)
+            while (__hip_atomic_load(copied, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < k - 1)
+                __builtin_amdgcn_s_sleep(1);
             const int ulo = S.moves[j0] & 0xffff;
-            if (grp == 0 && !bstate[2] && bstate[0] < ulo) {
+            if (gw == 0 && !bstate[2] && bstate[0] < ulo) {
                 bool bovf = false;
                 int bf = bstate[1];
                 Work bw{0, 0};
@@ -1443,14 +1461,9 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
                     bstate[2] = bovf ? 1 : 0;
                 }
             }
-            __syncthreads();
-        }
-        const int j = j0 + grp;
-        if (j < nfeas) {
-            const uint32_t mv = S.moves[j];
-            const int u = mv & 0xffff, v = mv >> 16;
-            int p0 = 0, front = 0;
-            if (use_base && !bstate[2]) {
+            __builtin_amdgcn_wave_barrier();
+            from_base = !bstate[2];
+            if (has && from_base) {
                 p0 = bstate[0];
                 front = bstate[1];
                 const int nd = F0 + (CAP ? Cd : front * NW);
@@ -1458,11 +1471,17 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
                 uint4 *dst = reinterpret_cast<uint4 *>(cb);
                 for (int i = g; i < (nd >> 2); i += G) dst[i] = src[i];
                 for (int i = (nd & ~3) + g; i < nd; i += G) cb[i] = S.bst[i];
-                __builtin_amdgcn_wave_barrier();
-            } else if (CAP) {
-                for (int i = g; i < Cd; i += G) cb[F0 + i] = 0u;
-                __builtin_amdgcn_wave_barrier();
             }
+            // this wave's reads of the base are done: chunk k + 1 may go on
+            __builtin_amdgcn_wave_barrier();
+            __hip_atomic_store(copied, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (has) {
+            const int u = mv & 0xffff, v = mv >> 16;
+            if (!from_base && CAP) {
+                for (int i = g; i < Cd; i += G) cb[F0 + i] = 0u;
+            }
+            __builtin_amdgcn_wave_barrier();
             bool ovf = false;
             Work cw{0, 0};
             const int c = decode_grp<NW, DEC, G, COUNT>(S, D, cb, L, u, v, p0, D.n, front, ovf, &cw);
@@ -1473,13 +1492,16 @@ __device__ unsigned long long evaluate_moves_g(const Sh &S, const InstDesc &D, c
                     S.moves[j] = mv | 0x80000000u;
                     atomicAdd(ovf_n, 1);
                 } else {
-                    const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
-                    best = k < best ? k : best;
+                    const unsigned long long key = move_key(c, u, v, tabu.get(u, v), asp);
+                    best = key < best ? key : best;
                     if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
                 }
             }
         }
-        if (use_base) __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        int nk = 0;
+        if (lane == 0) nk = atomicAdd(next_chunk, 1);
+        k = __builtin_amdgcn_readlane(nk, 0);
     }
     __syncthreads();
     // capacity-indexed states have no horizon and never overflow

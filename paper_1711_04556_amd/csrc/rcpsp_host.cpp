@@ -369,7 +369,7 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     }
     o = (o + 1) & ~1;
     Ly.red = o; o += 2 * (T / 64);
-    Ly.scal = o; o += std::max(4, 2 + 3 * (T / 64));
+    Ly.scal = o; o += std::max(6, 2 + 3 * (T / 64));
     // per candidate: finish times, then the time-indexed profile (L units
     // plus 4 of slack for the 4-wide scan) or the capacity arrays and the
     // copy ring
