@@ -888,13 +888,18 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
 #pragma unroll
                 for (int b = B; b < B + kSuper; b += kRegBlock) {
                     if (b + kRegBlock <= tmin) continue;
+                    // units past 64 are counted from the block's start,
+                    // so that every constant of the step is an inline one
+                    const int o = b >= 64 ? b : 0;
+                    if (o) lm -= o;
 #pragma unroll
                     for (int k = 0; k < kRegBlock; ++k) {
-                        const int t = b + k;
-                        const bool mis = ((P[t] - rq) & Gd) != Gd;
+                        const int t = b + k - o;
+                        const bool mis = ((P[b + k] - rq) & Gd) != Gd;
                         const bool open = (unsigned)(t - 1 - lm) < (unsigned)dd;
                         lm = (mis && open) ? t : lm;
                     }
+                    if (o) lm += o;
                     tl = b + kRegBlock - 1;
                     if (__builtin_amdgcn_ballot_w64(lm + dd > tl) == 0ull) goto scan_done;
                 }
