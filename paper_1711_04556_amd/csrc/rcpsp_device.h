@@ -1328,69 +1328,99 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
     const int pmask = D.copy_p - 1;
     const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
     long long w_ops = 0, w_cells = 0;
-    // the positions are the same for every lane of the wave: a scalar loop
+    // the update of decode_ci on one resource; leading units at or past the
+    // finish are passed over by a binary search
+    auto update = [&](int rk, uint16_t *ck, int Rk, int s, int d) {
+        int left = rk * d, raised = 0, bound = s + d;
+        int lo = 0, hi = Rk;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((int)ck[mid] < bound) hi = mid;
+            else lo = mid + 1;
+        }
+        if (COUNT) {
+            w_ops += lo;
+            w_cells += lo;
+        }
+        for (int j = lo; j < Rk && left > 0; ++j) {
+            if (COUNT) {
+                ++w_ops;
+                ++w_cells;
+            }
+            const int cv = ck[j];
+            if (cv >= bound) continue;
+            if (raised >= rk) bound = ring[(raised - rk) & pmask];
+            const int from = max(cv, s);
+            if (bound - from >= left) {
+                ck[j] = (uint16_t)(from + left);
+                left = 0;
+            } else {
+                left -= bound - from;
+                ring[raised & pmask] = (uint16_t)cv;
+                ++raised;
+                ck[j] = (uint16_t)bound;
+            }
+        }
+    };
+    // with at most G resources a lane owns at most one (k = g): its capacity
+    // and c_k offset are read once
+    const bool one = Mr <= G;
+    const bool own = one && g < Mr;
+    const int Rk1 = own ? (int)S.res[2 * g] : 0;
+    uint16_t *const ck1 = Cc + (own ? (int)S.res[2 * g + 1] : 0);
+    auto qof = [&](int p) {
+        p = min(p, D.n - 1);
+        return (p == u) ? v : ((p == v) ? u : p);
+    };
+    // the positions are the same for every lane of the wave: a scalar loop;
+    // each position's record is read while the previous one is placed
     p0 = __builtin_amdgcn_readfirstlane(p0);
     p1 = __builtin_amdgcn_readfirstlane(p1);
+    uint4 r = rec[qof(p0)];
     for (int p = p0; p < p1; ++p) {
-        const int q = (p == u) ? v : ((p == v) ? u : p);
-        const uint4 r = rec[q];
         const int d = r.y & 0xffff, np = r.y >> 16, a = (int)r.w;
+        const uint4 rn = rec[qof(p + 1)];
         int s = 0;
         for (int e = g; e < np; e += G) s = max(s, (int)F[S.pred[r.z + e]]);
-        for (int k = g; k < Mr; k += G) {
-            const int rk = S.reqk[a * Mr + k];
-            if (rk > 0) {
-                s = max(s, (int)Cc[(int)S.res[2 * k + 1] + (int)S.res[2 * k] - rk]);
-                if (COUNT) {
-                    ++w_ops;
-                    ++w_cells;
+        int rk1 = 0;
+        if (one) {
+            if (own) {
+                rk1 = S.reqk[a * Mr + g];
+                if (rk1 > 0) {
+                    s = max(s, (int)ck1[Rk1 - rk1]);
+                    if (COUNT) {
+                        ++w_ops;
+                        ++w_cells;
+                    }
+                }
+            }
+        } else {
+            for (int k = g; k < Mr; k += G) {
+                const int rk = S.reqk[a * Mr + k];
+                if (rk > 0) {
+                    s = max(s, (int)Cc[(int)S.res[2 * k + 1] + (int)S.res[2 * k] - rk]);
+                    if (COUNT) {
+                        ++w_ops;
+                        ++w_cells;
+                    }
                 }
             }
         }
         s = group_max<G>(s);
         if (d > 0) {
-            for (int k = g; k < Mr; k += G) {
-                const int rk = S.reqk[a * Mr + k];
-                if (rk == 0) continue;
-                uint16_t *ck = Cc + (int)S.res[2 * k + 1];
-                const int Rk = (int)S.res[2 * k];
-                // the update of decode_ci; leading units at or past the
-                // finish are passed over by a binary search
-                int left = rk * d, raised = 0, bound = s + d;
-                int lo = 0, hi = Rk;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if ((int)ck[mid] < bound) hi = mid;
-                    else lo = mid + 1;
-                }
-                if (COUNT) {
-                    w_ops += lo;
-                    w_cells += lo;
-                }
-                for (int j = lo; j < Rk && left > 0; ++j) {
-                    if (COUNT) {
-                        ++w_ops;
-                        ++w_cells;
-                    }
-                    const int cv = ck[j];
-                    if (cv >= bound) continue;
-                    if (raised >= rk) bound = ring[(raised - rk) & pmask];
-                    const int from = max(cv, s);
-                    if (bound - from >= left) {
-                        ck[j] = (uint16_t)(from + left);
-                        left = 0;
-                    } else {
-                        left -= bound - from;
-                        ring[raised & pmask] = (uint16_t)cv;
-                        ++raised;
-                        ck[j] = (uint16_t)bound;
-                    }
+            if (one) {
+                if (rk1 > 0) update(rk1, ck1, Rk1, s, d);
+            } else {
+                for (int k = g; k < Mr; k += G) {
+                    const int rk = S.reqk[a * Mr + k];
+                    if (rk > 0) update(rk, Cc + (int)S.res[2 * k + 1], (int)S.res[2 * k], s, d);
                 }
             }
         }
         if (COUNT && g == 0) w_ops += 1 + np;
         if (g == 0) F[a] = (uint16_t)(s + d);
         __builtin_amdgcn_wave_barrier();
+        r = rn;
     }
     if (COUNT) wk->add(Work{w_ops, w_cells});
     return p1 == D.n ? (int)F[D.n - 1] : 0;
