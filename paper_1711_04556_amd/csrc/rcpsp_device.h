@@ -1347,9 +1347,12 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
                 ++w_ops;
                 ++w_cells;
             }
+            // the copy ring's entry is read together with the unit (it is
+            // used once rk units were raised; the index is always in range)
             const int cv = ck[j];
+            const int rb = ring[(raised - rk) & pmask];
             if (cv >= bound) continue;
-            if (raised >= rk) bound = ring[(raised - rk) & pmask];
+            if (raised >= rk) bound = rb;
             const int from = max(cv, s);
             if (bound - from >= left) {
                 ck[j] = (uint16_t)(from + left);
