@@ -795,16 +795,18 @@ __device__ inline int wave_max_uniform(int x) { return -wave_min_uniform(-x); }
 //
 // Per activity (the positions are the same for the whole wave), Alg. 5 is a
 // sweep over the time units common to the wave: unit t is examined by every
-// lane whose scan is under way (t at or past its precedence earliest start,
-// no start found yet), each lane keeping the unit at which d free units
-// after the last unit short of capacity it has seen would close; once the
-// sweep reaches that unit the lane's start is fixed.  The sweep starts at the block holding the wave's smallest
+// lane, each keeping the last unit short of capacity inside the free run it
+// is growing (a shortfall counts only while the run is open: after the
+// lane's earliest start, before d free units followed the last shortfall);
+// once the sweep has passed d free units after it, the lane's start is
+// fixed.  The sweep starts at the block holding the wave's smallest
 // earliest start and ends after the first block (of kRegBlock units) by
-// which every lane has its start.  Alg. 6 is a second sweep over the units
-// covered by any lane's interval, each lane subtracting its request inside
-// its own [s, s + d).  Blocks outside a sweep's range are skipped by scalar
-// branches (eight-unit blocks measured best: fewer block tests than four,
-// fewer units past the last start than sixteen).  A lane whose start is not found within
+// which every lane has its start.  Alg. 6 is a second sweep over the same
+// blocks, each lane subtracting its request inside its own [s, s + d) (a
+// bit mask of the interval per block).  Blocks outside a sweep's range are
+// skipped by scalar branches (eight-unit blocks measured best: fewer block
+// tests than four, fewer units past the last start than sixteen).  A lane
+// whose start is not found within
 // the kRegUnits units (or whose finish passes 255) reports overflow and runs
 // along without touching its profile, like decode_ti.  Lanes without a
 // candidate (idle) take part in the sweeps' collective steps only.
