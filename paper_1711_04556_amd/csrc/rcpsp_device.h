@@ -818,7 +818,8 @@ constexpr int kRegBlock = 8;
 
 template <int T, bool COUNT>
 __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, const uint32_t *bprof, int front,
-                         int u, int v, int p0, int p1, bool idle, bool &ovf, Work *wk) {
+                         int u, int v, int p0, int p1, bool idle, bool &ovf, Work *wk, int *rel = nullptr,
+                         int relk = 0) {
     LaneMem<T> M{lane_base};
     const uint32_t Gd = D.guard[0], FULL = D.full[0];
     const uint4 *rec = reinterpret_cast<const uint4 *>(S.prec);
@@ -842,6 +843,12 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
 #pragma unroll
             for (int k = 0; k < 4; ++k) P[b + k] = (b + k < front) ? bprof[b + k] : FULL;
         }
+    }
+    // the shared base decode has been read: hand it on (rel: the ticket of
+    // the workgroup's base decode, relk this chunk's index)
+    if (rel) {
+        __builtin_amdgcn_wave_barrier();
+        __hip_atomic_store(rel, relk, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     bool over = idle;
     // the source finishes at 0; absent predecessors read its slot
@@ -963,14 +970,17 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
 // Decode every feasible move; return the workgroup's minimum key.
 // out_mk (global, canonical index) receives every makespan when non-null.
 //
-// Each wave takes chunks of 64 moves in canonical order (wave w: chunks w,
-// w + T/64, ...), one candidate per lane, and keeps its own base decode:
-// before a chunk, the wave extends the decode of W itself (no swap) in its
-// base area up to the chunk's smallest u (time-indexed: lanes 0-15 with the
-// group decode; capacity-indexed: lane 0); every lane copies that state and
-// decodes its candidate from there.  Waves never wait for
-// each other inside the loop.  If W's own schedule passes the lane profile
-// length, lanes decode from scratch instead.  Candidates that overflow the
+// Each wave takes chunks of 64 moves in canonical order, one candidate per
+// lane: wave w starts with chunk w, then takes the next chunk not yet taken
+// from a counter, so the chunks of early u (the longest decodes) go first
+// and the waves finish close together.  The workgroup keeps one base decode
+// of W itself (no swap), handed from chunk to chunk in canonical order: the
+// wave of chunk k waits until chunk k - 1's wave has read it, extends it up
+// to the chunk's smallest u (time-indexed: lanes 0-15 with the group decode;
+// capacity-indexed: lane 0), every lane copies that state, and chunk k + 1
+// may go on while the lanes decode their candidates from there.  If W's own
+// schedule passes the lane profile length, lanes decode from scratch
+// instead.  Candidates that overflow the
 // lane profile are decoded afterwards with a profile of the full horizon.
 // With COUNT the algorithmic work of every decode the launch runs is added
 // to *work_total: the base extensions and each candidate's suffix (or whole
@@ -986,17 +996,16 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
     unsigned long long best = ~0ull;
     Work lw{0, 0};
     int *ovf_n = S.scal;                  // overflowed candidates
-    int *bstate = S.scal + 1 + 3 * wv;    // this wave's base decode: positions done, front, overflowed
-    int *next_chunk = S.scal + 1 + 3 * (T / 64);
-    // this wave's base decode, 16-byte aligned (register layout: its profile,
-    // after the finish times, is the aligned part)
-    uint32_t *bst = S.bst + wv * Ly.base_stride + (REG ? ((-f_dwords<FB>(D.n)) & 3) : 0);
+    int *bstate = S.scal + 1;             // the base decode: positions done, front, overflowed
+    int *next_chunk = S.scal + 4, *copied = S.scal + 5;
+    // the base decode, 16-byte aligned (register layout: its profile, after
+    // the finish times, is the aligned part)
+    uint32_t *bst = S.bst + (REG ? ((-f_dwords<FB>(D.n)) & 3) : 0);
     const bool use_base = share;
     if (tid == 0) {
         *ovf_n = 0;
         *next_chunk = T / 64;
-    }
-    if (lane == 0) {
+        *copied = -1;
         bstate[0] = 0;
         bstate[1] = 0;
         bstate[2] = 0;
@@ -1004,14 +1013,15 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
     }
     __syncthreads();
     uint32_t *lane_base = S.region + tid;
-    // Chunks of 64 moves in canonical order: wave w starts with chunk w and
-    // then takes the next chunk not yet taken, so chunks with early u (the
-    // longest decodes) go first and the waves finish close together; each
-    // wave still meets its chunks in ascending order, as its base decode
-    // needs.  Counting runs keep the fixed order (chunks w, w + T/64, ...)
-    // so that the base decodes' work does not depend on timing.
-    for (int j0 = wv * 64; j0 < nfeas;) {
+    for (int k = wv; k * 64 < nfeas;) {
+        const int j0 = k * 64;
+        int p0 = 0, front = 0;
+        bool from_base = false;
         if (use_base) {
+            // chunk k's turn with the base decode once chunk k - 1's lanes
+            // have read it (every lane reads the flag: one load, one value)
+            while (__hip_atomic_load(copied, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < k - 1)
+                __builtin_amdgcn_s_sleep(1);
             const int ulo = S.moves[j0] & 0xffff;
             if constexpr (DEC == kEvalTime) {
                 // lanes 0-15 of the wave extend it together (group decode)
@@ -1035,74 +1045,73 @@ __device__ unsigned long long evaluate_moves(const Sh &S, const InstDesc &D, con
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            from_base = !bstate[2];
+            p0 = from_base ? bstate[0] : 0;
+            front = from_base ? bstate[1] : 0;
         }
         const int j = j0 + lane;
+        const bool has = j < nfeas;
         if constexpr (REG) {
             // register profiles: every lane takes part in the decode's
             // collective steps, lanes past the last move as idle
-            const bool has = j < nfeas;
             const uint32_t mv = has ? S.moves[j] : 0u;
             const int u = mv & 0xffff, v = (mv >> 16) & 0x7fff;
-            const bool from_base = use_base && !bstate[2];
-            int p0 = 0, front = 0;
             if (from_base) {
-                p0 = bstate[0];
-                front = bstate[1];
                 // the finish times (dword copies: the base's start need not be aligned)
                 LaneMem<T> M{lane_base};
                 for (int i = 0; i < f_dwords<FB>(D.n); ++i) M.st(i, bst[i]);
             }
             bool ovf = false;
             Work cw{0, 0};
+            // the decode hands the base on once its profile is in registers
             const int c = decode_tv<T, COUNT>(S, D, lane_base, bst + f_dwords<FB>(D.n), front, u, v, p0, D.n, !has,
-                                              ovf, &cw);
+                                              ovf, &cw, use_base ? copied : nullptr, k);
             if (has) {
                 if (COUNT && !ovf) lw.add(cw);
                 if (ovf) {
                     S.moves[j] = mv | 0x80000000u;
                     atomicAdd(ovf_n, 1);
                 } else {
-                    const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
-                    best = k < best ? k : best;
+                    const unsigned long long key = move_key(c, u, v, tabu.get(u, v), asp);
+                    best = key < best ? key : best;
                     if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
                 }
             }
-        } else if (j < nfeas) {
-            const uint32_t mv = S.moves[j];
+        } else {
+            const uint32_t mv = has ? S.moves[j] : 0u;
             const int u = mv & 0xffff, v = (mv >> 16) & 0x7fff;
-            int p0 = 0, front = 0;
-            if (use_base && !bstate[2]) {
-                p0 = bstate[0];
-                front = bstate[1];
-                copy_state<NW, DEC, T, FB>(D, bst, lane_base, front);
-            } else {
-                init_state<DEC, T>(D, lane_base);
+            if (has) {
+                if (from_base) copy_state<NW, DEC, T, FB>(D, bst, lane_base, front);
+                else init_state<DEC, T>(D, lane_base);
             }
-            bool ovf = false;
-            int c;
-            Work cw{0, 0};
-            if (DEC == kEvalTime)
-                c = decode_ti<NW, T, COUNT, FB>(S, D, lane_base, L, u, v, p0, D.n, front, ovf, &cw);
-            else
-                c = decode_ci<T, COUNT>(S, D, lane_base, u, v, p0, D.n, &cw);
-            if (COUNT && !ovf) lw.add(cw);
-            if (ovf) {
-                S.moves[j] = mv | 0x80000000u;
-                atomicAdd(ovf_n, 1);
-            } else {
-                const unsigned long long k = move_key(c, u, v, tabu.get(u, v), asp);
-                best = k < best ? k : best;
-                if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+            if (use_base) {
+                // the lanes' copies are done: chunk k + 1 may take the base on
+                __builtin_amdgcn_wave_barrier();
+                __hip_atomic_store(copied, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            if (has) {
+                bool ovf = false;
+                int c;
+                Work cw{0, 0};
+                if (DEC == kEvalTime)
+                    c = decode_ti<NW, T, COUNT, FB>(S, D, lane_base, L, u, v, p0, D.n, front, ovf, &cw);
+                else
+                    c = decode_ci<T, COUNT>(S, D, lane_base, u, v, p0, D.n, &cw);
+                if (COUNT && !ovf) lw.add(cw);
+                if (ovf) {
+                    S.moves[j] = mv | 0x80000000u;
+                    atomicAdd(ovf_n, 1);
+                } else {
+                    const unsigned long long key = move_key(c, u, v, tabu.get(u, v), asp);
+                    best = key < best ? key : best;
+                    if (out_mk) out_mk[canon_index(D.n, delta, u, v)] = c;
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
-        if constexpr (COUNT) {
-            j0 += T;
-        } else {
-            int c = 0;
-            if (lane == 0) c = atomicAdd(next_chunk, 1);
-            j0 = __builtin_amdgcn_readlane(c, 0) * 64;
-        }
+        int nk = 0;
+        if (lane == 0) nk = atomicAdd(next_chunk, 1);
+        k = __builtin_amdgcn_readlane(nk, 0);
     }
     __syncthreads();
     if constexpr (DEC == kEvalTime) {
