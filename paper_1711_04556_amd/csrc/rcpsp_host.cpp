@@ -390,11 +390,11 @@ static Layout make_layout(const InstDesc &D, int T, int tcw, int tl, int pmax, i
     Ly.cands = group ? T / G : (wave ? T / 64 : T);
     o = (o + 3) & ~3;
     Ly.bst = o;
-    // one base state per wave (the register layout's base keeps its profile
-    // in LDS: finish times placed so that the L + 4 units after them start
-    // 16-byte aligned)
+    // one base state per workgroup (the register layout's base keeps its
+    // profile in LDS: finish times placed so that the L + 4 units after them
+    // start 16-byte aligned)
     Ly.base_stride = reg ? ((Fl + 3) & ~3) + (L + 4) * D.nw : ((Ly.per_lane + 3) & ~3);
-    o += wave ? 0 : (group ? Ly.per_lane : (T / 64) * Ly.base_stride);
+    o += wave ? 0 : (group ? Ly.per_lane : Ly.base_stride);
     o = (o + 3) & ~3;
     Ly.region = o;
     o += Ly.cands * Ly.per_lane;

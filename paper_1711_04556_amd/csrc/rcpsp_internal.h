@@ -68,7 +68,7 @@ struct InstDesc {
 struct Layout {
     int blob, W, Wimp, pos, fs, lp, cnt, tc, ring, moves, prec, prq, predT, pin, pid, bst, red, scal, region;
     int per_lane;    // dwords of private decode state per candidate slot
-    int base_stride; // dwords of each wave's base decode (one-candidate-per-lane layouts)
+    int base_stride; // dwords of the workgroup's base decode (one-candidate-per-lane layouts)
     int cands;       // candidate slots per round (threads, or threads / lanes per candidate)
     int long_len;    // time slots available to the single-thread long-profile decode
     int total;       // dwords
