@@ -783,7 +783,12 @@ __device__ inline int wave_min_uniform(int x) {
     x = min(x, __builtin_amdgcn_update_dpp(kId, x, 0x140, 0xF, 0xF, false));   // row_mirror
     const int a = __builtin_amdgcn_readlane(x, 0), b = __builtin_amdgcn_readlane(x, 16);
     const int c = __builtin_amdgcn_readlane(x, 32), e = __builtin_amdgcn_readlane(x, 48);
-    return min(min(a, b), min(c, e));
+    // the four row minima are scalars: combine them on the scalar unit
+    int ab, ce, m;
+    asm("s_min_i32 %0, %1, %2" : "=s"(ab) : "s"(a), "s"(b));
+    asm("s_min_i32 %0, %1, %2" : "=s"(ce) : "s"(c), "s"(e));
+    asm("s_min_i32 %0, %1, %2" : "=s"(m) : "s"(ab), "s"(ce));
+    return m;
 }
 __device__ inline int wave_max_uniform(int x) { return -wave_min_uniform(-x); }
 
