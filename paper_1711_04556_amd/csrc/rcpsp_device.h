@@ -882,14 +882,16 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
         if (__builtin_amdgcn_ballot_w64(need) != 0ull) {
             // Alg. 5: lanes still scanning are `todo`
             const int tmin = wave_min_uniform(need ? es : 0x7fffffff);
-            // per lane: lm is the last unit short of capacity that lies in
-            // the free run being grown (es - 1 to begin with: earlier units
-            // do not count); a shortfall at t restarts the run only while
-            // the run is still open (lm < t <= lm + d), so units past a
-            // closed run, and units before es, leave lm alone; the start is
-            // lm + 1
-            int lm = es - 1, tl = 0;
-            // lanes that place nothing scan with a run length no unit can
+            // per lane: g counts the units since the last one short of
+            // capacity inside the free run being grown, up to the unit just
+            // examined (es - 1 stands for that unit at first, so units before
+            // es give negative counts); a shortfall restarts the run only
+            // while it is open (0 <= g < d), so once g reaches d the run is
+            // closed and g only grows; the start is the last unit examined
+            // minus g, plus one.  (Counting from the run's start keeps the
+            // step's dependent chain short and its constants out of it.)
+            int g = (tmin & ~(kRegBlock - 1)) - es, tl = 0;
+            // lanes that place nothing scan with a run length no count can
             // reach, which keeps them out of the block-end test
             int dd = need ? d : -(1 << 20);
             asm volatile("" : "+v"(dd));
@@ -902,25 +904,19 @@ __device__ int decode_tv(const Sh &S, const InstDesc &D, uint32_t *lane_base, co
 #pragma unroll
                 for (int b = B; b < B + kSuper; b += kRegBlock) {
                     if (b + kRegBlock <= tmin) continue;
-                    // units past 64 are counted from the block's start,
-                    // so that every constant of the step is an inline one
-                    const int o = b >= 64 ? b : 0;
-                    if (o) lm -= o;
 #pragma unroll
                     for (int k = 0; k < kRegBlock; ++k) {
-                        const int t = b + k - o;
                         const bool mis = ((P[b + k] - rq) & Gd) != Gd;
-                        const bool open = (unsigned)(t - 1 - lm) < (unsigned)dd;
-                        lm = (mis && open) ? t : lm;
+                        const bool open = (unsigned)g < (unsigned)dd;
+                        g = (mis && open) ? 0 : g + 1;
                     }
-                    if (o) lm += o;
                     tl = b + kRegBlock - 1;
-                    if (__builtin_amdgcn_ballot_w64(lm + dd > tl) == 0ull) goto scan_done;
+                    if (__builtin_amdgcn_ballot_w64(g < dd) == 0ull) goto scan_done;
                 }
             }
         scan_done:
-            const bool todo = need && lm + d > tl;
-            if (need && !todo) s = lm + 1;
+            const bool todo = need && g < d;
+            if (need && !todo) s = tl - g + 1;
             // no start within the register profile: the long-profile path
             over = over || todo;
             // Alg. 6 over the units some lane covers
