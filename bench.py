@@ -42,7 +42,7 @@ BATCH = dict(count=1024, base_seed=3000, searches=32, elite=16, phi_max=3, phi_s
 BATCH_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329)}
 # serving leg: open-loop Poisson arrivals, 50 ms budget from admission
 SERVE = dict(rate=2000.0, warmup_s=2.0, measure_s=10.0, budget_us=50000, searches=16, elite=16, iterations=1000,
-             phi_max=3, phi_steps=20, seed=5, pool=256, max_active=1024, reduced_rate=700.0, reduced_measure_s=6.0)
+             phi_max=3, phi_steps=20, seed=5, pool=256, max_active=1024, reduced_rate=500.0, reduced_measure_s=6.0)
 SERVE_DELTA_TL = {32: (8, 60), 62: (14, 110), 122: (20, 329), 302: (20, 869)}
 # large-instance leg: 256 instances of 300 activities, 8 resources; the
 # workload's 2000 iterations take tens of minutes at the measured rate, so
