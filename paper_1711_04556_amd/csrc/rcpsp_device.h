@@ -684,7 +684,12 @@ __device__ int decode_ci(const Sh &S, const InstDesc &D, uint32_t *lane_base, in
                 // to the finish, later ones to the time of the unit raised r
                 // raises before (the ring), the last one by what is left
                 int left = rk * d, raised = 0, bound = s + d;
-                int lo = 0, hi = Rk;
+                // the passed-over prefix ends by unit Rk - rk (free from the
+                // eq. 7 start); the first unit is tested on its own (about
+                // half of the updates pass over nothing)
+                int lo = 0, hi = Rk - rk;
+                if (M.ld16(cb) < bound) hi = 0;
+                else lo = 1;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
                     if (M.ld16(cb + mid) < bound) hi = mid;
@@ -1344,7 +1349,12 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
     // finish are passed over by a binary search
     auto update = [&](int rk, uint16_t *ck, int Rk, int s, int d) {
         int left = rk * d, raised = 0, bound = s + d;
-        int lo = 0, hi = Rk;
+        // the search ends by unit Rk - rk (free from the eq. 7 start, which
+        // s does not precede); about half of the updates pass over nothing,
+        // so the first unit is tested on its own
+        int lo = 0, hi = Rk - rk;
+        if ((int)ck[0] < bound) hi = 0;
+        else lo = 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if ((int)ck[mid] < bound) hi = mid;
