@@ -1369,12 +1369,13 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
                 ++w_ops;
                 ++w_cells;
             }
-            // the copy ring's entry is read together with the unit (it is
-            // used once rk units were raised; the index is always in range)
+            // the copy ring's entry is read together with the unit, by the
+            // lanes that use it (once rk units were raised)
             const int cv = ck[j];
-            const int rb = ring[(raised - rk) & pmask];
+            int rb = bound;
+            if (raised >= rk) rb = ring[(raised - rk) & pmask];
             if (cv >= bound) continue;
-            if (raised >= rk) bound = rb;
+            bound = rb;
             const int from = max(cv, s);
             if (bound - from >= left) {
                 ck[j] = (uint16_t)(from + left);
