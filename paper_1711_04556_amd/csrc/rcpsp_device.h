@@ -1347,13 +1347,13 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
     long long w_ops = 0, w_cells = 0;
     // the update of decode_ci on one resource; leading units at or past the
     // finish are passed over by a binary search
-    auto update = [&](int rk, uint16_t *ck, int Rk, int s, int d) {
+    auto update = [&](int rk, uint16_t *ck, int Rk, int s, int d, int c0) {
         int left = rk * d, raised = 0, bound = s + d;
         // the search ends by unit Rk - rk (free from the eq. 7 start, which
         // s does not precede); about half of the updates pass over nothing,
         // so the first unit is tested on its own
         int lo = 0, hi = Rk - rk;
-        if ((int)ck[0] < bound) hi = 0;
+        if (c0 < bound) hi = 0;
         else lo = 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -1408,12 +1408,14 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
         const uint4 rn = rec[qof(p + 1)];
         int s = 0;
         for (int e = g; e < np; e += G) s = max(s, (int)F[S.pred[r.z + e]]);
-        int rk1 = 0;
+        int rk1 = 0, c01 = 0;
         if (one) {
             if (own) {
                 rk1 = S.reqk[a * Mr + g];
                 if (rk1 > 0) {
+                    // Alg. 4's first unit is read with the eq. 7 lookup
                     s = max(s, (int)ck1[Rk1 - rk1]);
+                    c01 = ck1[0];
                     if (COUNT) {
                         ++w_ops;
                         ++w_cells;
@@ -1435,11 +1437,14 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
         s = group_max<G>(s);
         if (d > 0) {
             if (one) {
-                if (rk1 > 0) update(rk1, ck1, Rk1, s, d);
+                if (rk1 > 0) update(rk1, ck1, Rk1, s, d, c01);
             } else {
                 for (int k = g; k < Mr; k += G) {
                     const int rk = S.reqk[a * Mr + k];
-                    if (rk > 0) update(rk, Cc + (int)S.res[2 * k + 1], (int)S.res[2 * k], s, d);
+                    if (rk > 0) {
+                        uint16_t *const ck = Cc + (int)S.res[2 * k + 1];
+                        update(rk, ck, (int)S.res[2 * k], s, d, (int)ck[0]);
+                    }
                 }
             }
         }
