@@ -1364,6 +1364,19 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
             w_ops += lo;
             w_cells += lo;
         }
+        // lo < Rk (unit Rk - rk is below the bound); if unit lo is free at s,
+        // so is every later one (non-increasing): the loop's rk steps each
+        // take d of the effort, raising rk units to s + d and reading no
+        // copy (most updates)
+        const int cl = lo == 0 ? c0 : (int)ck[lo];
+        if (cl <= s) {
+            for (int i = 0; i < rk; ++i) ck[lo + i] = (uint16_t)bound;
+            if (COUNT) {
+                w_ops += rk;
+                w_cells += rk;
+            }
+            return;
+        }
         for (int j = lo; j < Rk && left > 0; ++j) {
             if (COUNT) {
                 ++w_ops;
@@ -1371,7 +1384,7 @@ __device__ int decode_cg(const Sh &S, const InstDesc &D, uint32_t *cb, int u, in
             }
             // the copy ring's entry is read together with the unit, by the
             // lanes that use it (once rk units were raised)
-            const int cv = ck[j];
+            const int cv = j == lo ? cl : (int)ck[j];
             int rb = bound;
             if (raised >= rk) rb = ring[(raised - rk) & pmask];
             if (cv >= bound) continue;
