@@ -193,7 +193,10 @@ def batched_leg(rcpsp, synth, stream, steps, warmup, plain_sample=12):
                                           phi_steps=BATCH["phi_steps"], record_trajectory=False,
                                           seed=BATCH["base_seed"] + k))
     t1 = time.perf_counter()
-    params, tuning = rcpsp.batch_autotune(gis, params, trial_iterations=5, sample=64, stream=stream)
+    # trials on whole groups (up to 512 members): a 64-member sample has a
+    # fifth of the tasks per iteration of its group, and there shapes that
+    # hold a CU's whole LDS rank above shapes that run faster on the group
+    params, tuning = rcpsp.batch_autotune(gis, params, trial_iterations=5, sample=512, stream=stream)
     tuning["seconds"] = time.perf_counter() - t1
     log("batch autotune", tuning)
     bt = rcpsp.Batch(gis, params, stream)
