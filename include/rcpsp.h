@@ -507,7 +507,9 @@ int64_t rcpsp_server_now_ns(void);
 void rcpsp_server_destroy(rcpsp_server *s);
 
 /* Decoder and threads per search for every instance of a batch (the batch
- * counterpart of rcpsp_autotune).  Instances are grouped by (N, M); for each
+ * counterpart of rcpsp_autotune).  Instances are grouped by (N, M and the
+ * dwords a time-indexed unit takes, which decides whether register profiles
+ * are possible); for each
  * group, up to `sample` evenly spaced members run as a batch of
  * trial_iterations iterations under every candidate (decoder time- or
  * capacity-indexed where the instance allows it, threads 64/128/192/256,

@@ -1900,11 +1900,13 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
     if (trial_iterations < 1 || sample < 1) return fail(RCPSP_E_ARG, "trial_iterations and sample must be >= 1");
     for (int i = 0; i < count; ++i)
         if (!inst[i]) return fail(RCPSP_E_ARG, "null instance %d", i);
-    // groups by (N, M), in order of first appearance
+    // groups by (N, M, dwords per time-indexed unit), in order of first
+    // appearance: members whose units take more words cannot share the
+    // register profiles of the others and are timed on their own
     std::vector<std::pair<int, int>> keys;
     std::vector<std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
-        const std::pair<int, int> k(inst[i]->n, inst[i]->m);
+        const std::pair<int, int> k(inst[i]->n, inst[i]->m * 8 + inst[i]->desc.nw);
         size_t g = 0;
         while (g < keys.size() && keys[g] != k) ++g;
         if (g == keys.size()) {
@@ -2001,7 +2003,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
           }
         }
         if (!found) return fail(RCPSP_E_TOO_LARGE, "no decoder/threads candidate fits instances of N=%d, M=%d",
-                                keys[g].first, keys[g].second);
+                                keys[g].first, keys[g].second / 8);
         for (int i : mem) {
             out[i].eval = best_eval;
             out[i].threads = best_T;
@@ -2010,7 +2012,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
         }
         if (info && g < 8) {
             info->group_n[g] = keys[g].first;
-            info->group_m[g] = keys[g].second;
+            info->group_m[g] = keys[g].second / 8;
             info->group_members[g] = (int32_t)mem.size();
             info->group_eval[g] = best_eval;
             info->group_threads[g] = best_T;
