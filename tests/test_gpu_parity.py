@@ -497,6 +497,11 @@ def test_lane_decode_after_requestless_activities(rc, threads, elite):
 CAP_GROUP_CASES = GROUP_CASES[:4] + [
     ("m12", lambda: synth.generate(40, 12, 10, 0.5, rs=0.5, seed=4012), 10),   # lanes own two resources
     ("m3", lambda: synth.generate(45, 3, 10, 0.7, rs=0.3, seed=4013), 12),     # lanes without a resource
+    # capacity = the largest request (resource strength 0): updates whose
+    # request takes every unit (Alg. 4 passes over nothing and raises all)
+    ("rs0", lambda: synth.generate(40, 4, 10, 0.5, rs=0.0, seed=4014), 10),
+    # every activity requests every resource, lanes own up to two
+    ("rs0m9rf1", lambda: synth.generate(36, 9, 10, 1.0, rs=0.0, seed=4015), 10),
 ]
 
 
