@@ -49,6 +49,9 @@ EVAL_CASES = [
     ("m8", lambda: synth.generate(50, 8, 20, 0.5, rs=None, cap_range=(10, 60), seed=4001), 20),
     ("serial14", _serial_instance, 5),
     ("g120", synth.instance_120_rs30, 20),
+    # capacity = the largest request: requests that take every unit
+    ("rs0", lambda: synth.generate(40, 4, 10, 0.5, rs=0.0, seed=4014), 10),
+    ("rs0m9rf1", lambda: synth.generate(36, 9, 10, 1.0, rs=0.0, seed=4015), 10),
 ]
 
 
