@@ -1903,6 +1903,7 @@ extern "C" rcpsp_status rcpsp_batch_autotune(const rcpsp_instance *const *inst, 
     // groups by (N, M, dwords per time-indexed unit), in order of first
     // appearance: members whose units take more words cannot share the
     // register profiles of the others and are timed on their own
+    static_assert(kMaxNW < 8, "M and the words per unit share one key");
     std::vector<std::pair<int, int>> keys;
     std::vector<std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
