@@ -569,6 +569,32 @@ def test_batch_mixes_capacity_lane_and_group_decode(rc):
     bt.close()
 
 
+def test_batch_autotune_groups_by_words_per_unit(rc):
+    """Instances of one (N, M) whose capacities need 16-bit profile fields
+    are tuned as a group of their own (they cannot take the 8-bit members'
+    register profiles); the tuned batch equals the oracle for every member."""
+    narrow = [synth.generate(30, 4, 10, 0.5, rs=0.4, seed=900 + k) for k in range(3)]
+    wide = []
+    for k in range(2):
+        b = synth.generate(30, 4, 10, 0.75, rs=0.7, seed=910 + k)
+        wide.append(synth.Instance(n=b.n, m=b.m, duration=b.duration, capacity=[3 * c for c in b.capacity],
+                                   request=[3 * r for r in b.request], succ=b.succ, name=f"wide{k}"))
+    insts = [narrow[0], wide[0], narrow[1], wide[1], narrow[2]]
+    gis = [rc.Instance(i, eval=TIME) for i in insts]
+    assert {g.info["field_bits"] for g in gis} == {8, 16}
+    kw = dict(searches=4, elite=3, phi_max=2, phi_steps=4)
+    params = [rc.search_params(7, 30, 8, eval=TIME, seed=70 + k, **kw) for k in range(len(insts))]
+    tuned, info = rc.batch_autotune(gis, params, trial_iterations=2, sample=8)
+    assert info["groups"] == 2
+    assert sorted(info["group_members"][:2]) == [2, 3]
+    bt = rc.Batch(gis, tuned)
+    bt.run()
+    for k, inst in enumerate(insts):
+        o = oracle.Oracle(inst).tabu_search(7, 30, 8, decoder=TIME, seed=70 + k, **kw)
+        _compare_search(bt.results(k), o, elite=3)
+    bt.close()
+
+
 @pytest.mark.parametrize("threads,profile_len,bits", [(192, 0, 8), (64, 300, 16), (128, 0, 8)])
 def test_finish_time_width_and_three_waves(rc, threads, profile_len, bits):
     """Lane states hold 8-bit finish times while the lane profile is at most
